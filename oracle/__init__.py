@@ -1,0 +1,162 @@
+"""CPU oracle for top-k subgraph discovery -- test infrastructure only.
+
+A plain, slow rendering of the paper's Algorithm 1 (Section 3.2) for top-k
+maximal cliques and top-k labelled subgraph matching, in oracle.c, plus this
+ctypes loader.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import it; the GPU engine never does, and the two share
+no code.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build() -> str:
+    src = os.path.join(_HERE, "oracle.c")
+    tmp = _SO + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", tmp, src])
+    os.replace(tmp, _SO)
+    return _SO
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_SO):
+        build()
+    lib = ctypes.CDLL(_SO)
+    vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    lib.oracle_topk_cliques.restype = ctypes.c_int64
+    lib.oracle_topk_cliques.argtypes = [u32, vp, vp, vp, u32, i32, i32, i32, i32, vp, vp, vp, u64, vp]
+    lib.oracle_clique_trace.restype = ctypes.c_int64
+    lib.oracle_clique_trace.argtypes = [u32, vp, vp, u32, vp, u64, vp, u64, vp]
+    lib.oracle_topk_match.restype = ctypes.c_int64
+    lib.oracle_topk_match.argtypes = [u32, vp, vp, vp, vp, u32, u32, vp, u32, vp, u32, i32, vp, vp, vp]
+    lib.oracle_vertex_order.argtypes = [u32, vp, vp, i32, vp]
+    _lib = lib
+    return lib
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+CLIQUE_STATS = ("popped", "expanded", "children", "pruned_at_creation", "pruned_at_pop", "offered",
+                "ids")
+MATCH_STATS = ("popped", "expanded", "children", "pruned_at_creation", "pruned_at_pop", "offered",
+               "automorphisms")
+
+
+def topk_cliques(g, k: int, weighted: bool = False, bound: int = 0, priority: int = 0,
+                 order: int = 1) -> Tuple[List[Tuple[int, Tuple[int, ...]]], dict]:
+    """Top-k maximal cliques of g.
+
+    Returns ([(score, ids_ascending), ...] best first, stats).
+    bound: 0 Carraghan-Pardalos, 1 greedy colouring.
+    priority: 0 paper (|V|, |P|), 1 bound, 2 FIFO.  order: 0 id, 1 degeneracy.
+    """
+    lib = _load()
+    rp, col = _arr(g.row_ptr, np.uint64), _arr(g.col, np.uint32)
+    vw = _arr(g.vertex_weight, np.int32) if weighted else None
+    if weighted and vw is None:
+        raise ValueError("weighted cliques need vertex weights")
+    cap = max(1024, 64 * k)
+    while True:
+        scores = np.zeros(k, np.int64)
+        off = np.zeros(k + 1, np.uint64)
+        ids = np.zeros(cap, np.uint32)
+        stats = np.zeros(8, np.uint64)
+        c = lib.oracle_topk_cliques(g.n, rp.ctypes.data, col.ctypes.data,
+                                    vw.ctypes.data if vw is not None else None, k, int(weighted),
+                                    bound, priority, order, scores.ctypes.data, off.ctypes.data,
+                                    ids.ctypes.data, cap, stats.ctypes.data)
+        if c == -2:
+            raise ValueError("invalid arguments")
+        if c == -1:
+            cap = int(stats[6]) + 16
+            continue
+        res = [(int(scores[i]), tuple(int(x) for x in ids[int(off[i]):int(off[i + 1])]))
+               for i in range(c)]
+        return res, dict(zip(CLIQUE_STATS, (int(x) for x in stats[:7])))
+
+
+def clique_trace(g, k: int):
+    """Paper-trace mode of the clique computation (Section 3.2 worked example).
+
+    Returns (pops, R, stats) where pops is a list of
+    (sorted vertex tuple, inserted_into_R, pruned_at_pop, n_children_inserted).
+    """
+    lib = _load()
+    rp, col = _arr(g.row_ptr, np.uint64), _arr(g.col, np.uint32)
+    pop_log = np.zeros(1 << 16, np.int32)
+    r_log = np.zeros(1 << 12, np.int32)
+    stats = np.zeros(8, np.uint64)
+    npop = lib.oracle_clique_trace(g.n, rp.ctypes.data, col.ctypes.data, k, pop_log.ctypes.data,
+                                   pop_log.size, r_log.ctypes.data, r_log.size, stats.ctypes.data)
+    if npop < 0:
+        raise ValueError("invalid arguments")
+    pops = []
+    i = 0
+    for _ in range(npop):
+        vs = []
+        while pop_log[i] != -1:
+            vs.append(int(pop_log[i]))
+            i += 1
+        pops.append((tuple(vs), int(pop_log[i + 1]), int(pop_log[i + 2]), int(pop_log[i + 3])))
+        i += 4
+    R = []
+    cur = []
+    for x in r_log:
+        if x == -1:
+            R.append(tuple(cur))
+            cur = []
+            if len(R) == int(stats[4]):
+                break
+        else:
+            cur.append(int(x))
+    st = dict(zip(("popped", "children", "pruned_at_creation", "pruned_at_pop", "r_size"),
+                  (int(x) for x in stats[:5])))
+    return pops, R[:st["r_size"]], st
+
+
+def topk_match(g, labels, edges, k: int, n_labels: int = 16, priority: int = 0):
+    """Top-k labelled matches of the pattern (labels[q], edges [(a,b)]) in g.
+
+    Returns ([(score, (mu(0), ..., mu(q-1))), ...] best first, stats).
+    """
+    lib = _load()
+    q = len(labels)
+    rp, col = _arr(g.row_ptr, np.uint64), _arr(g.col, np.uint32)
+    lab = _arr(g.vertex_label, np.uint8)
+    ew = _arr(g.edge_weight, np.int32) if g.edge_weight is not None else None
+    pl = _arr(labels, np.uint8)
+    pe = _arr(np.array(edges, dtype=np.uint32).reshape(-1), np.uint32)
+    scores = np.zeros(k, np.int64)
+    ids = np.zeros(k * q, np.uint32)
+    stats = np.zeros(8, np.uint64)
+    c = lib.oracle_topk_match(g.n, rp.ctypes.data, col.ctypes.data, lab.ctypes.data,
+                              ew.ctypes.data if ew is not None else None, n_labels, q,
+                              pl.ctypes.data, len(edges), pe.ctypes.data, k, priority,
+                              scores.ctypes.data, ids.ctypes.data, stats.ctypes.data)
+    if c < 0:
+        raise ValueError("invalid pattern or k")
+    res = [(int(scores[i]), tuple(int(x) for x in ids[i * q:(i + 1) * q])) for i in range(c)]
+    return res, dict(zip(MATCH_STATS, (int(x) for x in stats[:7])))
+
+
+def vertex_order(g, order: int = 1) -> np.ndarray:
+    lib = _load()
+    rp, col = _arr(g.row_ptr, np.uint64), _arr(g.col, np.uint32)
+    pi = np.zeros(g.n, np.uint32)
+    lib.oracle_vertex_order(g.n, rp.ctypes.data, col.ctypes.data, order, pi.ctypes.data)
+    return pi

@@ -1,0 +1,915 @@
+/*
+ * CPU oracle for top-k subgraph discovery (test infrastructure only).
+ *
+ * This is a plain, slow, deliberately unoptimised rendering of the paper's
+ * basic computational model (Algorithm 1, Section 3.2) for two
+ * computations:
+ *
+ *   - top-k maximal cliques (Section 3.2 "Example: Maximum Clique
+ *     Discovery", Section 4.1, Listing 1), and
+ *   - top-k labelled subgraph matching (Section 2.1 "Subgraph Isomorphism",
+ *     Section 4.3), scored by the sum of matched edge weights.
+ *
+ * It exists to check the GPU engine.  It shares no code with it: no
+ * headers, helpers or tables.  Only the tests, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.
+ *
+ * Readings of the paper this file takes (each is also listed with the
+ * design notes):
+ *   - A clique result is a *maximal* clique (relevant(s) is true only when
+ *     nothing can extend s).  Its score is |V| or the int64 sum of vertex
+ *     weights.
+ *   - The result set holds exactly min(k, #results) entries ranked by
+ *     score descending, then by the ascending-sorted original ids
+ *     compared lexicographically (ascending).  The queue priority only
+ *     orders exploration.
+ *   - Candidate sets are ordered: P_s holds only vertices later than every
+ *     member of s in a fixed total order pi (the duplicate-free generation
+ *     of Section 3.2).  X_s holds the earlier common neighbours, so that
+ *     maximality can be decided when P_s is empty.
+ *   - dominated(s, kth) is strict: bound(s) < score(kth) (Section 3.2
+ *     footnote on Carraghan-Pardalos; Section 4.1).
+ *   - Matching is non-induced (a monomorphism); two embeddings with the
+ *     same image are one result, represented by the lexicographically
+ *     smallest tuple (mu(0), ..., mu(q-1)) in its automorphism orbit.
+ *
+ * All arithmetic is integer.  parity pins: see tests/test_oracle_*.py.
+ */
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+  uint32_t n;
+  const uint64_t *row_ptr;
+  const uint32_t *col;
+  const int32_t *vw;   /* vertex weights or NULL */
+  const uint8_t *lab;  /* vertex labels or NULL */
+  const int32_t *ew;   /* edge weights aligned with col, or NULL */
+} graph_t;
+
+/* ------------------------------------------------------------------ */
+/* small helpers                                                       */
+/* ------------------------------------------------------------------ */
+
+static void *xmalloc(size_t n) {
+  void *p = malloc(n ? n : 1);
+  if (!p) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+  return p;
+}
+
+static int is_adjacent(const graph_t *g, uint32_t u, uint32_t v) {
+  uint64_t lo = g->row_ptr[u], hi = g->row_ptr[u + 1];
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (g->col[mid] == v) return 1;
+    if (g->col[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return 0;
+}
+
+/* weight of edge {u,v}; 0 if absent */
+static int64_t edge_weight(const graph_t *g, uint32_t u, uint32_t v) {
+  uint64_t lo = g->row_ptr[u], hi = g->row_ptr[u + 1];
+  while (lo < hi) {
+    uint64_t mid = lo + (hi - lo) / 2;
+    if (g->col[mid] == v) return g->ew ? g->ew[mid] : 1;
+    if (g->col[mid] < v) lo = mid + 1; else hi = mid;
+  }
+  return 0;
+}
+
+static int cmp_u32(const void *a, const void *b) {
+  uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+  return x < y ? -1 : x > y;
+}
+
+/* lexicographic comparison of two id sequences */
+static int lex_cmp(const uint32_t *a, uint32_t na, const uint32_t *b, uint32_t nb) {
+  uint32_t n = na < nb ? na : nb;
+  for (uint32_t i = 0; i < n; ++i)
+    if (a[i] != b[i]) return a[i] < b[i] ? -1 : 1;
+  return na < nb ? -1 : (na > nb);
+}
+
+/* ------------------------------------------------------------------ */
+/* the priority queue Q: a binary max-heap (Algorithm 1, lines 3, 5, 16) */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Priorities are compared as lexicographic tuples of up to 3 int64 values.
+ * Ties are broken by insertion sequence, earlier first, which fixes the
+ * exploration order but never the result.
+ */
+typedef struct {
+  int64_t key[3];
+  uint64_t seq;
+  void *item;
+} pq_entry;
+
+typedef struct {
+  pq_entry *a;
+  uint64_t n, cap, next_seq;
+} pq_t;
+
+static int pq_higher(const pq_entry *x, const pq_entry *y) {
+  for (int i = 0; i < 3; ++i)
+    if (x->key[i] != y->key[i]) return x->key[i] > y->key[i];
+  return x->seq < y->seq;
+}
+
+static void pq_insert(pq_t *q, const int64_t key[3], void *item) {
+  if (q->n == q->cap) {
+    q->cap = q->cap ? 2 * q->cap : 1024;
+    q->a = (pq_entry *)realloc(q->a, q->cap * sizeof(pq_entry));
+    if (!q->a) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+  }
+  pq_entry e;
+  memcpy(e.key, key, sizeof(e.key));
+  e.seq = q->next_seq++;
+  e.item = item;
+  uint64_t i = q->n++;
+  while (i > 0) {
+    uint64_t p = (i - 1) / 2;
+    if (!pq_higher(&e, &q->a[p])) break;
+    q->a[i] = q->a[p];
+    i = p;
+  }
+  q->a[i] = e;
+}
+
+static void *pq_remove_max(pq_t *q) {
+  void *top = q->a[0].item;
+  pq_entry last = q->a[--q->n];
+  uint64_t i = 0;
+  for (;;) {
+    uint64_t l = 2 * i + 1, r = l + 1, b = i;
+    const pq_entry *best = &last;
+    if (l < q->n && pq_higher(&q->a[l], best)) { b = l; best = &q->a[l]; }
+    if (r < q->n && pq_higher(&q->a[r], best)) { b = r; best = &q->a[r]; }
+    if (b == i) break;
+    q->a[i] = q->a[b];
+    i = b;
+  }
+  if (q->n) q->a[i] = last;
+  return top;
+}
+
+/* ------------------------------------------------------------------ */
+/* the result set R: exactly min(k, #results) entries                   */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  int64_t score;
+  uint32_t len;
+  uint32_t *ids; /* cliques: ascending original ids; matches: mu(0..q-1) */
+} result_t;
+
+typedef struct {
+  result_t *e; /* sorted best first */
+  uint32_t n, k;
+} rset_t;
+
+/* -1 if (s1, ids1) ranks before (s2, ids2) */
+static int rank_cmp(int64_t s1, const uint32_t *a, uint32_t na, int64_t s2, const uint32_t *b,
+                    uint32_t nb) {
+  if (s1 != s2) return s1 > s2 ? -1 : 1;
+  return lex_cmp(a, na, b, nb);
+}
+
+/* offer a result; returns 1 if it entered R */
+static int rset_offer(rset_t *R, int64_t score, const uint32_t *ids, uint32_t len) {
+  if (R->n == R->k) {
+    const result_t *kth = &R->e[R->k - 1];
+    if (rank_cmp(score, ids, len, kth->score, kth->ids, kth->len) >= 0) return 0;
+    free(R->e[R->k - 1].ids);
+    R->n--;
+  }
+  uint32_t i = R->n;
+  while (i > 0 && rank_cmp(score, ids, len, R->e[i - 1].score, R->e[i - 1].ids, R->e[i - 1].len) < 0) {
+    R->e[i] = R->e[i - 1];
+    --i;
+  }
+  R->e[i].score = score;
+  R->e[i].len = len;
+  R->e[i].ids = (uint32_t *)xmalloc(len * sizeof(uint32_t));
+  memcpy(R->e[i].ids, ids, len * sizeof(uint32_t));
+  R->n++;
+  return 1;
+}
+
+/* dominated(s, kth(R)) with the strict rule: bound < score of the k-th */
+static int rset_dominates(const rset_t *R, int64_t bound) {
+  return R->n == R->k && bound < R->e[R->k - 1].score;
+}
+
+typedef struct {
+  uint64_t popped, expanded, children, pruned_at_creation, pruned_at_pop, offered;
+} ostats_t;
+
+/* flatten R into caller buffers; returns count */
+static uint32_t rset_export(rset_t *R, int64_t *score_out, uint64_t *off_out, uint32_t *ids_out,
+                            uint64_t ids_cap) {
+  uint64_t t = 0;
+  off_out[0] = 0;
+  for (uint32_t i = 0; i < R->n; ++i) {
+    score_out[i] = R->e[i].score;
+    for (uint32_t j = 0; j < R->e[i].len; ++j) {
+      if (t < ids_cap) ids_out[t] = R->e[i].ids[j];
+      ++t;
+    }
+    off_out[i + 1] = t;
+    free(R->e[i].ids);
+  }
+  uint32_t c = R->n;
+  free(R->e);
+  return c;
+}
+
+/* ------------------------------------------------------------------ */
+/* vertex order pi                                                     */
+/* ------------------------------------------------------------------ */
+
+/*
+ * order_kind 0: pi = vertex id.
+ * order_kind 1: degeneracy order (repeatedly remove a vertex of minimum
+ * remaining degree); pi(v) = removal position.  Among vertices of equal
+ * remaining degree the one at the head of that degree's list goes first,
+ * which makes the order deterministic.  Any order yields the same result
+ * set; this one keeps candidate sets small (at most the degeneracy).
+ */
+static uint32_t *vertex_order(const graph_t *g, int order_kind) {
+  uint32_t n = g->n;
+  uint32_t *pi = (uint32_t *)xmalloc((uint64_t)n * sizeof(uint32_t));
+  if (order_kind == 0) {
+    for (uint32_t v = 0; v < n; ++v) pi[v] = v;
+    return pi;
+  }
+  uint32_t *deg = (uint32_t *)xmalloc((uint64_t)n * sizeof(uint32_t));
+  uint32_t maxd = 0;
+  for (uint32_t v = 0; v < n; ++v) {
+    deg[v] = (uint32_t)(g->row_ptr[v + 1] - g->row_ptr[v]);
+    if (deg[v] > maxd) maxd = deg[v];
+  }
+  /* one doubly linked list of vertices per remaining degree */
+  uint32_t NIL = 0xFFFFFFFFu;
+  uint32_t *head = (uint32_t *)xmalloc(((uint64_t)maxd + 1) * sizeof(uint32_t));
+  uint32_t *nxt = (uint32_t *)xmalloc((uint64_t)n * sizeof(uint32_t));
+  uint32_t *prv = (uint32_t *)xmalloc((uint64_t)n * sizeof(uint32_t));
+  uint8_t *gone = (uint8_t *)calloc(n ? n : 1, 1);
+  for (uint32_t d = 0; d <= maxd; ++d) head[d] = NIL;
+  for (uint32_t v = n; v-- > 0;) {
+    uint32_t d = deg[v];
+    nxt[v] = head[d];
+    prv[v] = NIL;
+    if (head[d] != NIL) prv[head[d]] = v;
+    head[d] = v;
+  }
+  uint32_t cur = 0;
+  for (uint32_t pos = 0; pos < n; ++pos) {
+    if (cur > 0) cur--; /* a removal lowers neighbour degrees by at most one */
+    while (head[cur] == NIL) cur++;
+    uint32_t v = head[cur];
+    /* unlink v */
+    if (prv[v] != NIL) nxt[prv[v]] = nxt[v]; else head[cur] = nxt[v];
+    if (nxt[v] != NIL) prv[nxt[v]] = prv[v];
+    gone[v] = 1;
+    pi[v] = pos;
+    for (uint64_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; ++e) {
+      uint32_t u = g->col[e];
+      if (gone[u]) continue;
+      uint32_t d = deg[u];
+      if (prv[u] != NIL) nxt[prv[u]] = nxt[u]; else head[d] = nxt[u];
+      if (nxt[u] != NIL) prv[nxt[u]] = prv[u];
+      deg[u] = d - 1;
+      nxt[u] = head[d - 1];
+      prv[u] = NIL;
+      if (head[d - 1] != NIL) prv[head[d - 1]] = u;
+      head[d - 1] = u;
+    }
+  }
+  free(deg); free(head); free(nxt); free(prv); free(gone);
+  return pi;
+}
+
+/* ------------------------------------------------------------------ */
+/* top-k cliques                                                       */
+/* ------------------------------------------------------------------ */
+
+/* A clique subgraph s: V_s, the ordered candidate set P_s, and X_s. */
+typedef struct {
+  uint32_t nv, np, nx;
+  uint32_t *V; /* original ids, in insertion order */
+  uint32_t *P; /* sorted by pi */
+  uint32_t *X; /* sorted by pi */
+  int64_t score, bound;
+} clique_rec;
+
+static void clique_free(clique_rec *s) {
+  free(s->V); free(s->P); free(s->X); free(s);
+}
+
+static int64_t vweight(const graph_t *g, int weighted, uint32_t v) {
+  return weighted ? (int64_t)g->vw[v] : 1;
+}
+
+/*
+ * Upper bound on the score of any clique s can expand into.
+ * bound_kind 0 (Carraghan-Pardalos, Section 3.2): score(V) + score(P),
+ *   i.e. |V| + |P| for size scores.
+ * bound_kind 1 (greedy colouring, the tighter bound the paper leaves to
+ *   future work): colour P greedily in pi order with the smallest colour
+ *   not used by an adjacent earlier vertex; a clique takes at most one
+ *   vertex per colour, so score(V) + sum over colours of the largest
+ *   weight in that colour is a bound.
+ */
+static int64_t clique_bound(const graph_t *g, int weighted, int bound_kind, const clique_rec *s) {
+  int64_t b = s->score;
+  if (bound_kind == 0) {
+    for (uint32_t i = 0; i < s->np; ++i) b += vweight(g, weighted, s->P[i]);
+    return b;
+  }
+  uint32_t np = s->np;
+  uint32_t *color = (uint32_t *)xmalloc(np * sizeof(uint32_t));
+  uint32_t ncol = 0;
+  uint8_t *used = (uint8_t *)xmalloc(np + 1);
+  for (uint32_t i = 0; i < np; ++i) {
+    memset(used, 0, np + 1);
+    for (uint32_t j = 0; j < i; ++j)
+      if (is_adjacent(g, s->P[i], s->P[j])) used[color[j]] = 1;
+    uint32_t c = 0;
+    while (used[c]) ++c;
+    color[i] = c;
+    if (c + 1 > ncol) ncol = c + 1;
+  }
+  int64_t *cmax = (int64_t *)calloc(ncol ? ncol : 1, sizeof(int64_t));
+  for (uint32_t i = 0; i < np; ++i) {
+    int64_t w = vweight(g, weighted, s->P[i]);
+    if (w > cmax[color[i]]) cmax[color[i]] = w;
+  }
+  for (uint32_t c = 0; c < ncol; ++c) b += cmax[c];
+  free(color); free(used); free(cmax);
+  return b;
+}
+
+/*
+ * Queue priority of a clique subgraph.
+ * priority_kind 0: the paper's (|V_s|, |P_s|) compared lexicographically
+ *   (Section 3.2, prioritized expansion).
+ * priority_kind 1: (bound) - best bound first.
+ * priority_kind 2: FIFO - no prioritisation, as in the paper's Nuri-NP
+ *   variant (Section 6.1), keyed by insertion order alone.
+ */
+static void clique_priority(int priority_kind, const clique_rec *s, int64_t key[3]) {
+  key[0] = key[1] = key[2] = 0;
+  if (priority_kind == 0) { key[0] = s->nv; key[1] = s->np; }
+  else if (priority_kind == 1) { key[0] = s->bound; }
+}
+
+/*
+ * Top-k maximal cliques by Algorithm 1.
+ *   weighted: 0 score = |C|; 1 score = sum of vertex weights (int64).
+ * Outputs up to k results: score_out[i], ids_out[off_out[i]..off_out[i+1])
+ * holding the ascending original ids.  Returns the count, or -1 if the id
+ * buffer was too small (ids_needed then holds the size required).
+ */
+int64_t oracle_topk_cliques(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                            const int32_t *vw, uint32_t k, int weighted, int bound_kind,
+                            int priority_kind, int order_kind, int64_t *score_out,
+                            uint64_t *off_out, uint32_t *ids_out, uint64_t ids_cap,
+                            uint64_t *stats_out) {
+  graph_t G = {n, row_ptr, col, vw, NULL, NULL};
+  const graph_t *g = &G;
+  if (k == 0) return -2;
+  uint32_t *pi = vertex_order(g, order_kind);
+  pq_t Q = {0};
+  rset_t R = {(result_t *)xmalloc((uint64_t)k * sizeof(result_t)), 0, k};
+  ostats_t st = {0};
+
+  /* lines 1-3: one unit subgraph per vertex */
+  for (uint32_t v = 0; v < n; ++v) {
+    clique_rec *s = (clique_rec *)xmalloc(sizeof(clique_rec));
+    uint64_t deg = row_ptr[v + 1] - row_ptr[v];
+    s->V = (uint32_t *)xmalloc(sizeof(uint32_t));
+    s->P = (uint32_t *)xmalloc(deg * sizeof(uint32_t));
+    s->X = (uint32_t *)xmalloc(deg * sizeof(uint32_t));
+    s->nv = 1; s->V[0] = v; s->np = 0; s->nx = 0;
+    for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+      uint32_t u = col[e];
+      if (pi[u] > pi[v]) s->P[s->np++] = u; else s->X[s->nx++] = u;
+    }
+    /* sort P and X by pi (insertion sort on pi keys) */
+    for (int which = 0; which < 2; ++which) {
+      uint32_t *a = which ? s->X : s->P, m = which ? s->nx : s->np;
+      for (uint32_t i = 1; i < m; ++i) {
+        uint32_t x = a[i], j = i;
+        while (j > 0 && pi[a[j - 1]] > pi[x]) { a[j] = a[j - 1]; --j; }
+        a[j] = x;
+      }
+    }
+    s->score = vweight(g, weighted, v);
+    s->bound = clique_bound(g, weighted, bound_kind, s);
+    int64_t key[3];
+    clique_priority(priority_kind, s, key);
+    pq_insert(&Q, key, s);
+  }
+
+  uint32_t *tmp_ids = (uint32_t *)xmalloc(((uint64_t)n + 1) * sizeof(uint32_t));
+  while (Q.n > 0) {                                   /* line 4 */
+    clique_rec *s = (clique_rec *)pq_remove_max(&Q);   /* line 5 */
+    st.popped++;
+    /* lines 6-10: relevant(s) iff s is a maximal clique (P and X empty) */
+    if (s->np == 0 && s->nx == 0) {
+      memcpy(tmp_ids, s->V, s->nv * sizeof(uint32_t));
+      qsort(tmp_ids, s->nv, sizeof(uint32_t), cmp_u32);
+      st.offered++;
+      rset_offer(&R, s->score, tmp_ids, s->nv);
+    }
+    /* line 11: skip s when dominated by the k-th result */
+    if (rset_dominates(&R, s->bound)) { st.pruned_at_pop++; clique_free(s); continue; }
+    if (s->np > 0) st.expanded++;
+    /* lines 12-16: expand by every p in P_s, in pi order */
+    for (uint32_t i = 0; i < s->np; ++i) {
+      uint32_t p = s->P[i];
+      clique_rec *c = (clique_rec *)xmalloc(sizeof(clique_rec));
+      c->nv = s->nv + 1;
+      c->V = (uint32_t *)xmalloc(c->nv * sizeof(uint32_t));
+      memcpy(c->V, s->V, s->nv * sizeof(uint32_t));
+      c->V[s->nv] = p;
+      /* P' = {u in P_s after p} intersect N(p) */
+      c->P = (uint32_t *)xmalloc((s->np - i) * sizeof(uint32_t));
+      c->np = 0;
+      for (uint32_t j = i + 1; j < s->np; ++j)
+        if (is_adjacent(g, p, s->P[j])) c->P[c->np++] = s->P[j];
+      /* X' = (X_s union {u in P_s before p}) intersect N(p), kept pi-sorted */
+      c->X = (uint32_t *)xmalloc((s->nx + i + 1) * sizeof(uint32_t));
+      c->nx = 0;
+      uint32_t a = 0, b = 0;
+      while (a < s->nx || b < i) {
+        uint32_t u;
+        if (b >= i || (a < s->nx && pi[s->X[a]] < pi[s->P[b]])) u = s->X[a++];
+        else u = s->P[b++];
+        if (is_adjacent(g, p, u)) c->X[c->nx++] = u;
+      }
+      c->score = s->score + vweight(g, weighted, p);
+      c->bound = clique_bound(g, weighted, bound_kind, c);
+      st.children++;
+      /* line 15: insert unless dominated */
+      if (rset_dominates(&R, c->bound)) { st.pruned_at_creation++; clique_free(c); continue; }
+      int64_t key[3];
+      clique_priority(priority_kind, c, key);
+      pq_insert(&Q, key, c);                          /* line 16 */
+    }
+    clique_free(s);
+  }
+  free(tmp_ids);
+  free(Q.a);
+  free(pi);
+
+  uint64_t need = 0;
+  for (uint32_t i = 0; i < R.n; ++i) need += R.e[i].len;
+  if (stats_out) {
+    stats_out[0] = st.popped; stats_out[1] = st.expanded; stats_out[2] = st.children;
+    stats_out[3] = st.pruned_at_creation; stats_out[4] = st.pruned_at_pop; stats_out[5] = st.offered;
+    stats_out[6] = need;
+  }
+  if (need > ids_cap) {
+    for (uint32_t i = 0; i < R.n; ++i) free(R.e[i].ids);
+    free(R.e);
+    return -1;
+  }
+  return (int64_t)rset_export(&R, score_out, off_out, ids_out, ids_cap);
+}
+
+/*
+ * Paper-trace mode (Section 3.2 worked example): every clique is relevant,
+ * priority is (|V_s|, |P_s|), R ranks entries by that priority and keeps
+ * every entry tied with the k-th (lines 7-10), dominated(s, s') is
+ * |V_s| + |P_s| < |V_s'|, pi = vertex id.
+ *
+ * Logs, for each pop in order: the popped vertex set (sorted ids, -1
+ * terminated), whether it entered R, whether it was pruned at pop, and the
+ * number of children inserted.  Writes R's final vertex sets the same way.
+ * Returns the number of pops.
+ */
+int64_t oracle_clique_trace(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, uint32_t k,
+                            int32_t *pop_log, uint64_t pop_log_cap, int32_t *r_log,
+                            uint64_t r_log_cap, uint64_t *stats_out) {
+  graph_t G = {n, row_ptr, col, NULL, NULL, NULL};
+  const graph_t *g = &G;
+  if (n > 64 || k == 0) return -2; /* trace mode is for tiny worked examples */
+  pq_t Q = {0};
+  /* R holds pointers to vertex sets with their priority */
+  typedef struct { int64_t p0, p1; uint32_t nv; uint32_t *V; } tentry;
+  tentry *R = (tentry *)xmalloc(((uint64_t)n * n + 8) * sizeof(tentry));
+  uint64_t rn = 0, lt = 0, npop = 0;
+  ostats_t st = {0};
+  for (uint32_t v = 0; v < n; ++v) {
+    clique_rec *s = (clique_rec *)xmalloc(sizeof(clique_rec));
+    uint64_t deg = row_ptr[v + 1] - row_ptr[v];
+    s->V = (uint32_t *)xmalloc(sizeof(uint32_t));
+    s->P = (uint32_t *)xmalloc(deg * sizeof(uint32_t));
+    s->X = NULL;
+    s->nv = 1; s->V[0] = v; s->np = 0; s->nx = 0;
+    for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+      if (col[e] > v) s->P[s->np++] = col[e];
+    s->score = 1;
+    s->bound = 1 + s->np;
+    int64_t key[3] = {s->nv, s->np, 0};
+    pq_insert(&Q, key, s);
+  }
+  while (Q.n > 0) {
+    clique_rec *s = (clique_rec *)pq_remove_max(&Q);
+    st.popped++;
+    npop++;
+    int inserted = 0, pruned = 0, nchild = 0;
+    /* k-th(R): the k-th entry when R is ordered by priority, best first */
+    /* R is kept sorted by priority descending (stable for equal keys) */
+    int admit = (rn < k);
+    if (!admit) {
+      tentry *kth = &R[k - 1];
+      admit = (s->nv > kth->p0) || (s->nv == kth->p0 && (int64_t)s->np >= kth->p1);
+    }
+    if (admit) {
+      uint64_t i = rn;
+      while (i > 0 && (R[i - 1].p0 < s->nv || (R[i - 1].p0 == s->nv && R[i - 1].p1 < (int64_t)s->np))) {
+        R[i] = R[i - 1];
+        --i;
+      }
+      R[i].p0 = s->nv; R[i].p1 = s->np; R[i].nv = s->nv;
+      R[i].V = (uint32_t *)xmalloc(s->nv * sizeof(uint32_t));
+      memcpy(R[i].V, s->V, s->nv * sizeof(uint32_t));
+      qsort(R[i].V, s->nv, sizeof(uint32_t), cmp_u32);
+      rn++;
+      inserted = 1;
+      if (rn > k) {
+        int64_t k0 = R[k - 1].p0, k1 = R[k - 1].p1;
+        uint64_t w = 0;
+        for (uint64_t j = 0; j < rn; ++j) {
+          int lower = (R[j].p0 < k0) || (R[j].p0 == k0 && R[j].p1 < k1);
+          if (lower) free(R[j].V); else R[w++] = R[j];
+        }
+        rn = w;
+      }
+    }
+    if (rn >= k && (int64_t)(s->nv + s->np) < R[k - 1].p0) {
+      pruned = 1;
+      st.pruned_at_pop++;
+    } else {
+      for (uint32_t i = 0; i < s->np; ++i) {
+        uint32_t p = s->P[i];
+        clique_rec *c = (clique_rec *)xmalloc(sizeof(clique_rec));
+        c->nv = s->nv + 1;
+        c->V = (uint32_t *)xmalloc(c->nv * sizeof(uint32_t));
+        memcpy(c->V, s->V, s->nv * sizeof(uint32_t));
+        c->V[s->nv] = p;
+        c->P = (uint32_t *)xmalloc((s->np - i) * sizeof(uint32_t));
+        c->np = 0;
+        c->X = NULL; c->nx = 0;
+        for (uint32_t j = i + 1; j < s->np; ++j)
+          if (is_adjacent(g, p, s->P[j])) c->P[c->np++] = s->P[j];
+        c->score = c->nv;
+        c->bound = c->nv + c->np;
+        st.children++;
+        if (rn >= k && (int64_t)(c->nv + c->np) < R[k - 1].p0) {
+          st.pruned_at_creation++;
+          clique_free(c);
+          continue;
+        }
+        int64_t key[3] = {c->nv, c->np, 0};
+        pq_insert(&Q, key, c);
+        nchild++;
+      }
+    }
+    /* log: sorted V, -1, inserted, pruned, nchild */
+    uint32_t tmp[64];
+    uint32_t nv = s->nv < 64 ? s->nv : 64;
+    memcpy(tmp, s->V, nv * sizeof(uint32_t));
+    qsort(tmp, nv, sizeof(uint32_t), cmp_u32);
+    for (uint32_t i = 0; i < nv; ++i) if (lt < pop_log_cap) pop_log[lt++] = (int32_t)tmp[i];
+    int32_t tail[4] = {-1, inserted, pruned, nchild};
+    for (int i = 0; i < 4; ++i) if (lt < pop_log_cap) pop_log[lt++] = tail[i];
+    clique_free(s);
+  }
+  uint64_t rt = 0;
+  for (uint64_t j = 0; j < rn; ++j) {
+    for (uint32_t i = 0; i < R[j].nv; ++i) if (rt < r_log_cap) r_log[rt++] = (int32_t)R[j].V[i];
+    if (rt < r_log_cap) r_log[rt++] = -1;
+    free(R[j].V);
+  }
+  free(R);
+  free(Q.a);
+  if (stats_out) {
+    stats_out[0] = st.popped; stats_out[1] = st.children; stats_out[2] = st.pruned_at_creation;
+    stats_out[3] = st.pruned_at_pop; stats_out[4] = rn;
+  }
+  return (int64_t)npop;
+}
+
+/* ------------------------------------------------------------------ */
+/* top-k labelled subgraph matching                                    */
+/* ------------------------------------------------------------------ */
+
+#define QMAX 8
+
+/* a partial embedding: mu(order[0..depth-1]) assigned */
+typedef struct {
+  uint32_t depth;
+  uint32_t mu[QMAX]; /* indexed by pattern vertex; valid for matched ones */
+  int64_t score, bound;
+} match_rec;
+
+typedef struct {
+  uint32_t q, ne;
+  uint8_t label[QMAX];
+  uint32_t ea[QMAX * QMAX], eb[QMAX * QMAX];
+  uint8_t adj[QMAX][QMAX];
+  uint32_t order[QMAX], pos[QMAX];
+  uint32_t naut;
+  uint8_t *aut; /* naut x q permutations */
+} pattern_t;
+
+/*
+ * The automorphisms of the labelled pattern: every permutation s of
+ * {0..q-1} with label(s(a)) = label(a) and {s(a), s(b)} an edge for every
+ * edge {a, b}.  Brute force over all q! permutations (q <= 8).
+ */
+static void pattern_automorphisms(pattern_t *P) {
+  uint32_t q = P->q;
+  uint32_t perm[QMAX], c[QMAX];
+  uint64_t cap = 1;
+  for (uint32_t i = 2; i <= q; ++i) cap *= i;
+  P->aut = (uint8_t *)xmalloc(cap * q);
+  P->naut = 0;
+  for (uint32_t i = 0; i < q; ++i) { perm[i] = i; c[i] = 0; }
+  /* Heap's algorithm enumerates every permutation once */
+  for (;;) {
+    int ok = 1;
+    for (uint32_t a = 0; a < q && ok; ++a)
+      if (P->label[perm[a]] != P->label[a]) ok = 0;
+    for (uint32_t e = 0; e < P->ne && ok; ++e)
+      if (!P->adj[perm[P->ea[e]]][perm[P->eb[e]]]) ok = 0;
+    if (ok) { for (uint32_t a = 0; a < q; ++a) P->aut[P->naut * q + a] = (uint8_t)perm[a]; P->naut++; }
+    uint32_t i = 1;
+    while (i < q && c[i] >= i) { c[i] = 0; ++i; }
+    if (i >= q) break;
+    uint32_t j = (i % 2) ? c[i] : 0;
+    uint32_t t = perm[i]; perm[i] = perm[j]; perm[j] = t;
+    c[i]++;
+  }
+}
+
+/* bound tables: best[v*nl + l] = max weight of an edge from v to a label-l vertex */
+typedef struct {
+  uint32_t nl;
+  int64_t *best;     /* n x nl */
+  int64_t *pairmax;  /* nl x nl */
+} tables_t;
+
+static void build_tables(const graph_t *g, uint32_t nl, tables_t *T) {
+  T->nl = nl;
+  T->best = (int64_t *)calloc((uint64_t)g->n * nl, sizeof(int64_t));
+  T->pairmax = (int64_t *)calloc((uint64_t)nl * nl, sizeof(int64_t));
+  for (uint32_t v = 0; v < g->n; ++v)
+    for (uint64_t e = g->row_ptr[v]; e < g->row_ptr[v + 1]; ++e) {
+      uint32_t u = g->col[e];
+      int64_t w = g->ew ? g->ew[e] : 1;
+      uint32_t lu = g->lab[u], lv = g->lab[v];
+      if (w > T->best[(uint64_t)v * nl + lu]) T->best[(uint64_t)v * nl + lu] = w;
+      if (w > T->pairmax[lv * nl + lu]) T->pairmax[lv * nl + lu] = w;
+    }
+}
+
+/*
+ * Upper bound on the final score of any completion of r (Section 4.3:
+ * current score plus an index-based bound for what is still unmatched).
+ * Per pattern edge {a,b}: its weight if both ends are matched; the
+ * largest weight from mu(a) to a vertex labelled label(b) if only a is
+ * matched; the largest weight over all edges with that label pair if
+ * neither is.  Returns -1 when an unmatched edge has no possible data
+ * edge (no completion exists).
+ */
+static int64_t match_bound(const graph_t *g, const pattern_t *P, const tables_t *T,
+                           const match_rec *r) {
+  int64_t b = 0;
+  uint8_t matched[QMAX] = {0};
+  for (uint32_t i = 0; i < r->depth; ++i) matched[P->order[i]] = 1;
+  for (uint32_t e = 0; e < P->ne; ++e) {
+    uint32_t a = P->ea[e], c = P->eb[e];
+    int64_t ub;
+    if (matched[a] && matched[c]) ub = edge_weight(g, r->mu[a], r->mu[c]);
+    else if (matched[a]) ub = T->best[(uint64_t)r->mu[a] * T->nl + P->label[c]];
+    else if (matched[c]) ub = T->best[(uint64_t)r->mu[c] * T->nl + P->label[a]];
+    else ub = T->pairmax[P->label[a] * T->nl + P->label[c]];
+    if (ub <= 0) return -1;
+    b += ub;
+  }
+  return b;
+}
+
+/*
+ * True when the complete embedding mu is the lexicographically smallest
+ * tuple (mu(0), ..., mu(q-1)) among mu o s for all automorphisms s.
+ */
+static int match_is_canonical(const pattern_t *P, const uint32_t *mu) {
+  for (uint32_t t = 0; t < P->naut; ++t) {
+    const uint8_t *s = &P->aut[t * P->q];
+    for (uint32_t i = 0; i < P->q; ++i) {
+      uint32_t x = mu[s[i]];
+      if (x < mu[i]) return 0;
+      if (x > mu[i]) break;
+    }
+  }
+  return 1;
+}
+
+/*
+ * Partial check of the same condition: mu can still be completed into the
+ * smallest tuple of its orbit only if, for each automorphism s, the
+ * comparison of mu o s against mu over the leading positions whose values
+ * are all known does not already come out smaller.  (A full embedding
+ * passes this test exactly when match_is_canonical holds.)
+ */
+static int match_may_be_canonical(const pattern_t *P, const match_rec *r) {
+  uint8_t matched[QMAX] = {0};
+  for (uint32_t i = 0; i < r->depth; ++i) matched[P->order[i]] = 1;
+  for (uint32_t t = 0; t < P->naut; ++t) {
+    const uint8_t *s = &P->aut[t * P->q];
+    for (uint32_t i = 0; i < P->q; ++i) {
+      if (!matched[i] || !matched[s[i]]) break;
+      uint32_t x = r->mu[s[i]];
+      if (x < r->mu[i]) return 0;
+      if (x > r->mu[i]) break;
+    }
+  }
+  return 1;
+}
+
+/*
+ * Top-k matches of the labelled pattern (q vertices, edges as pairs) by
+ * Algorithm 1 with vertex-at-a-time expansion in a fixed matching order.
+ * Score = sum of the data-edge weights under the pattern's edges (int64).
+ * Results: score_out[i] and mu(0..q-1) at ids_out[i*q ..].  Returns count.
+ */
+int64_t oracle_topk_match(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                          const uint8_t *lab, const int32_t *ew, uint32_t n_labels, uint32_t q,
+                          const uint8_t *plabel, uint32_t ne, const uint32_t *pedges, uint32_t k,
+                          int priority_kind, int64_t *score_out, uint32_t *ids_out,
+                          uint64_t *stats_out) {
+  graph_t G = {n, row_ptr, col, NULL, lab, ew};
+  const graph_t *g = &G;
+  if (k == 0 || q < 2 || q > QMAX) return -2;
+  pattern_t P;
+  memset(&P, 0, sizeof(P));
+  P.q = q;
+  P.ne = ne;
+  for (uint32_t a = 0; a < q; ++a) P.label[a] = plabel[a];
+  for (uint32_t e = 0; e < ne; ++e) {
+    uint32_t a = pedges[2 * e], b = pedges[2 * e + 1];
+    if (a >= q || b >= q || a == b || P.adj[a][b]) return -2;
+    P.ea[e] = a; P.eb[e] = b;
+    P.adj[a][b] = P.adj[b][a] = 1;
+  }
+  /* connectivity */
+  {
+    uint8_t seen[QMAX] = {1};
+    for (uint32_t round = 0; round < q; ++round)
+      for (uint32_t a = 0; a < q; ++a)
+        if (seen[a]) for (uint32_t b = 0; b < q; ++b) if (P.adj[a][b]) seen[b] = 1;
+    for (uint32_t a = 0; a < q; ++a) if (!seen[a]) return -2;
+  }
+  pattern_automorphisms(&P);
+
+  /* matching order: first the vertex whose label is rarest in the graph
+     (ties: larger pattern degree, then smaller id); then repeatedly the
+     vertex with the most edges to the ones already ordered (ties: smaller
+     id). */
+  uint64_t *lcount = (uint64_t *)calloc(n_labels ? n_labels : 1, sizeof(uint64_t));
+  for (uint32_t v = 0; v < n; ++v) if (lab[v] < n_labels) lcount[lab[v]]++;
+  {
+    uint8_t used[QMAX] = {0};
+    uint32_t best = 0;
+    for (uint32_t a = 1; a < q; ++a) {
+      uint32_t da = 0, db = 0;
+      for (uint32_t x = 0; x < q; ++x) { da += P.adj[a][x]; db += P.adj[best][x]; }
+      uint64_t ca = P.label[a] < n_labels ? lcount[P.label[a]] : 0;
+      uint64_t cb = P.label[best] < n_labels ? lcount[P.label[best]] : 0;
+      if (ca < cb || (ca == cb && da > db)) best = a;
+    }
+    P.order[0] = best; used[best] = 1;
+    for (uint32_t i = 1; i < q; ++i) {
+      uint32_t pick = q, pc = 0;
+      for (uint32_t a = 0; a < q; ++a) {
+        if (used[a]) continue;
+        uint32_t c = 0;
+        for (uint32_t j = 0; j < i; ++j) c += P.adj[a][P.order[j]];
+        if (pick == q || c > pc) { pick = a; pc = c; }
+      }
+      P.order[i] = pick; used[pick] = 1;
+    }
+    for (uint32_t i = 0; i < q; ++i) P.pos[P.order[i]] = i;
+  }
+  free(lcount);
+
+  tables_t T;
+  build_tables(g, n_labels, &T);
+  pq_t Q = {0};
+  rset_t R = {(result_t *)xmalloc((uint64_t)k * sizeof(result_t)), 0, k};
+  ostats_t st = {0};
+
+  /* lines 1-3: unit subgraphs = data vertices that can host order[0] */
+  uint32_t first = P.order[0];
+  for (uint32_t v = 0; v < n; ++v) {
+    if (lab[v] != P.label[first]) continue;
+    match_rec *r = (match_rec *)xmalloc(sizeof(match_rec));
+    memset(r, 0, sizeof(*r));
+    r->depth = 1;
+    r->mu[first] = v;
+    r->score = 0;
+    r->bound = match_bound(g, &P, &T, r);
+    if (r->bound < 0) { free(r); continue; }
+    int64_t key[3] = {priority_kind == 2 ? 0 : 1, priority_kind == 2 ? 0 : r->bound, 0};
+    if (priority_kind == 1) { key[0] = r->bound; key[1] = 0; }
+    pq_insert(&Q, key, r);
+  }
+
+  while (Q.n > 0) {
+    match_rec *r = (match_rec *)pq_remove_max(&Q);
+    st.popped++;
+    if (r->depth == q && match_is_canonical(&P, r->mu)) {
+      st.offered++;
+      rset_offer(&R, r->score, r->mu, q);
+    }
+    if (rset_dominates(&R, r->bound)) { st.pruned_at_pop++; free(r); continue; }
+    if (r->depth == q) { free(r); continue; }
+    st.expanded++;
+    uint32_t a = P.order[r->depth];
+    /* candidates: neighbours of the matched pattern-neighbour that comes
+       first in the order, filtered by label, injectivity and adjacency to
+       every other matched pattern-neighbour (Ullmann-style refinement) */
+    uint32_t anchor = q;
+    for (uint32_t i = 0; i < r->depth; ++i)
+      if (P.adj[a][P.order[i]]) { anchor = P.order[i]; break; }
+    uint32_t av = r->mu[anchor];
+    for (uint64_t e = row_ptr[av]; e < row_ptr[av + 1]; ++e) {
+      uint32_t c = col[e];
+      if (lab[c] != P.label[a]) continue;
+      int ok = 1;
+      int64_t add = 0;
+      for (uint32_t i = 0; i < r->depth && ok; ++i) {
+        uint32_t b = P.order[i];
+        if (r->mu[b] == c) ok = 0;
+        else if (P.adj[a][b]) {
+          int64_t w = edge_weight(g, c, r->mu[b]);
+          if (w == 0) ok = 0; else add += w;
+        }
+      }
+      if (!ok) continue;
+      match_rec *ch = (match_rec *)xmalloc(sizeof(match_rec));
+      *ch = *r;
+      ch->mu[a] = c;
+      ch->depth = r->depth + 1;
+      ch->score = r->score + add;
+      st.children++;
+      if (!match_may_be_canonical(&P, ch)) { free(ch); continue; }
+      ch->bound = match_bound(g, &P, &T, ch);
+      if (ch->bound < 0 || rset_dominates(&R, ch->bound)) {
+        st.pruned_at_creation++;
+        free(ch);
+        continue;
+      }
+      int64_t key[3] = {ch->depth, ch->bound, 0};
+      if (priority_kind == 1) { key[0] = ch->bound; key[1] = 0; }
+      if (priority_kind == 2) { key[0] = 0; key[1] = 0; }
+      pq_insert(&Q, key, ch);
+    }
+    free(r);
+  }
+  free(Q.a);
+  free(T.best);
+  free(T.pairmax);
+  free(P.aut);
+  if (stats_out) {
+    stats_out[0] = st.popped; stats_out[1] = st.expanded; stats_out[2] = st.children;
+    stats_out[3] = st.pruned_at_creation; stats_out[4] = st.pruned_at_pop; stats_out[5] = st.offered;
+    stats_out[6] = P.naut;
+  }
+  uint32_t cnt = R.n;
+  for (uint32_t i = 0; i < cnt; ++i) {
+    score_out[i] = R.e[i].score;
+    memcpy(&ids_out[(uint64_t)i * q], R.e[i].ids, q * sizeof(uint32_t));
+    free(R.e[i].ids);
+  }
+  free(R.e);
+  return cnt;
+}
+
+/* order used by the clique oracle, exposed for tests */
+void oracle_vertex_order(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int order_kind,
+                         uint32_t *pi_out) {
+  graph_t G = {n, row_ptr, col, NULL, NULL, NULL};
+  uint32_t *pi = vertex_order(&G, order_kind);
+  memcpy(pi_out, pi, (uint64_t)n * sizeof(uint32_t));
+  free(pi);
+}
