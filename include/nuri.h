@@ -1,0 +1,242 @@
+/*
+ * nuri.h -- C ABI of the MI355X top-k subgraph discovery engine.
+ *
+ * The engine runs the paper's basic computational model (Algorithm 1,
+ * Section 3.2: prioritized expansion of partial subgraphs with pruning
+ * against the k-th result) on one AMD Instinct MI355X (gfx950), for
+ *   - top-k maximal cliques (Section 3.2 "Example: Maximum Clique
+ *     Discovery", Section 4.1, Listing 1), scored by size or by the sum
+ *     of vertex weights, and
+ *   - top-k labelled subgraph matching (Section 2.1 "Subgraph
+ *     Isomorphism", Section 4.3), scored by the sum of matched edge
+ *     weights.
+ * The user functions of Table 1 are fixed specialisations selected by the
+ * arguments below; no user code runs on the device.
+ *
+ * Conventions for every entry point:
+ *   - Return value: NURI_OK (0) on success, a negative nuri_status on
+ *     error.  On error, out-parameters are left untouched and
+ *     nuri_last_error() returns a message (thread-local, valid until the
+ *     next call on the same thread).
+ *   - Host pointers passed in are owned by the caller, read during the
+ *     call only, and never retained.
+ *   - Handles (nuri_graph, nuri_result, nuri_server) are owned by the
+ *     library and released by the matching free/destroy call.
+ *   - A graph is immutable after load; several queries may run on one
+ *     graph from different threads.  A single query call is synchronous:
+ *     it returns when its results are on the host.
+ *   - The library fails loudly: it never returns a truncated or inexact
+ *     top-k as success.
+ */
+#ifndef NURI_H
+#define NURI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NURI_OK = 0,
+  NURI_EINVAL = -1,   /* malformed argument (graph, pattern, k = 0, ...) */
+  NURI_ENOMEM = -2,   /* device or host allocation failed */
+  NURI_EBUDGET = -3,  /* the frontier does not fit the frontier budget */
+  NURI_EDEVICE = -4,  /* a HIP call failed; the message names it */
+  NURI_ETIMEOUT = -5  /* the query passed its deadline */
+} nuri_status;
+
+typedef struct nuri_graph nuri_graph;
+typedef struct nuri_result nuri_result;
+typedef struct nuri_server nuri_server;
+
+/*
+ * An undirected simple data graph in CSR form (Section 2.1; the engine
+ * loads it once and keeps it resident, Section 5).  All arrays are host
+ * memory.
+ *   n        vertices 0..n-1 (n >= 1)
+ *   nnz      directed entries = 2 * |E|
+ *   row_ptr  [n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
+ *   col_idx  [nnz]; each row strictly increasing, no self loops, ids < n,
+ *            and symmetric (v in row u iff u in row v)
+ *   vertex_weight [n] or NULL; every weight >= 1 (needed by
+ *            NURI_SCORE_VERTEX_WEIGHT)
+ *   vertex_label  [n] or NULL; labels < NURI_MAX_LABELS (needed by
+ *            matching)
+ *   edge_weight   [nnz] or NULL, aligned with col_idx, equal for both
+ *            directions of an edge, each in [1, 2^31); NULL means weight 1
+ * Anything else is rejected with NURI_EINVAL; the input is never repaired.
+ */
+#define NURI_MAX_LABELS 16
+typedef struct {
+  uint32_t n;
+  uint64_t nnz;
+  const uint64_t *row_ptr;
+  const uint32_t *col_idx;
+  const int32_t *vertex_weight;
+  const uint8_t *vertex_label;
+  const int32_t *edge_weight;
+} nuri_csr;
+
+/*
+ * Validates the CSR, copies it to the device and builds the resident
+ * structures every query uses: a degeneracy order and the graph relabelled
+ * by it, the oriented adjacency N+(v) (later neighbours), one dense local
+ * adjacency bitmap per vertex over N+(v), root orders by bound, and the
+ * per-(vertex, label) maximum edge weight table (the 1-hop form of the
+ * Section 4.3 index, Listing 3).  `hip_stream` is a hipStream_t or NULL
+ * (the library's own stream); all later work on this graph runs on it.
+ * Limit: the degeneracy must be at most 4096 (NURI_EINVAL otherwise).
+ */
+int nuri_load_graph(const nuri_csr *csr, void *hip_stream, nuri_graph **out);
+void nuri_free_graph(nuri_graph *g);
+
+typedef struct {
+  uint32_t n;
+  uint64_t nnz;
+  uint32_t degeneracy;        /* max |N+(v)| under the degeneracy order */
+  uint64_t bitmap_bytes;      /* bytes of all local adjacency bitmaps */
+  uint64_t device_bytes;      /* device memory held by the graph */
+  uint64_t preprocess_ns;     /* wall time of nuri_load_graph */
+} nuri_graph_info;
+int nuri_graph_get_info(const nuri_graph *g, nuri_graph_info *info);
+
+/* Clique score (relevant results are maximal cliques, ranked by score). */
+typedef enum {
+  NURI_SCORE_SIZE = 0,          /* |C| */
+  NURI_SCORE_VERTEX_WEIGHT = 1  /* sum of vertex weights, int64 */
+} nuri_weight_fn;
+
+/*
+ * A connected labelled query pattern (Section 2.1): q vertices 0..q-1 with
+ * label[q] and n_edges undirected edges edges[2*i], edges[2*i+1]
+ * (distinct, a != b, a, b < q).  2 <= q <= NURI_MAX_PATTERN.
+ */
+#define NURI_MAX_PATTERN 8
+typedef struct {
+  uint32_t q, n_edges;
+  const uint8_t *label;
+  const uint32_t *edges;
+} nuri_pattern;
+
+/*
+ * Tuning and limits; pass NULL for defaults.  None of these changes a
+ * result, only speed, memory and whether the call may fail.
+ *   frontier_budget_bytes  device bytes for the frontier of partial
+ *                          subgraphs (0 = 8 GiB); NURI_EBUDGET if the
+ *                          search cannot proceed within it
+ *   batch_B                records expanded per step (0 = automatic)
+ *   root_batch             unit subgraphs expanded per step (0 = automatic)
+ *   deadline_ns            wall-clock limit per call (0 = none)
+ *   profile                1: time every expansion launch with HIP events
+ *                          (reported in nuri_stats)
+ *   hip_stream             hipStream_t to run on (NULL = the graph's stream)
+ */
+typedef struct {
+  uint64_t frontier_budget_bytes;
+  uint32_t batch_B;
+  uint32_t root_batch;
+  uint64_t deadline_ns;
+  uint32_t profile;
+  void *hip_stream;
+} nuri_opts;
+
+/*
+ * Top-k maximal cliques (Algorithm 1 with the clique user functions of
+ * Section 4.1: targeted expansion by the ordered candidate set, priority
+ * (|V|, bound), dominated when bound < score of the k-th result).
+ * Results are the first min(k, #maximal cliques) maximal cliques ordered
+ * by score descending, then by the ascending list of their vertex ids
+ * compared lexicographically.  k >= 1.
+ */
+int nuri_topk_cliques(nuri_graph *g, uint32_t k, nuri_weight_fn wf, const nuri_opts *o,
+                      nuri_result **out);
+
+/*
+ * Top-k matches of a labelled pattern (Section 4.3): injective,
+ * label-preserving maps mu with every pattern edge mapped onto a data edge
+ * (non-induced).  Embeddings with the same image are one result,
+ * represented by the lexicographically smallest (mu(0), ..., mu(q-1)).
+ * Score = sum over pattern edges of the data edge weight (int64).  Order:
+ * score descending, then the representative tuple ascending.  Needs
+ * vertex labels.  k >= 1.
+ */
+int nuri_topk_match(nuri_graph *g, const nuri_pattern *p, uint32_t k, const nuri_opts *o,
+                    nuri_result **out);
+
+/* One query of a batch. kind 0 = clique (uses k, wf), 1 = match (uses k, p). */
+typedef struct {
+  uint32_t kind;
+  uint32_t k;
+  nuri_weight_fn wf;
+  const nuri_pattern *p;
+} nuri_query;
+
+/*
+ * Runs nq queries together: every expansion launch serves all live
+ * queries, each with its own frontier, threshold and result set.  outs
+ * [nq] receives one result per query; each equals what the single-query
+ * call returns.  On error no result is returned.
+ */
+int nuri_topk_batch(nuri_graph *g, const nuri_query *qs, uint32_t nq, const nuri_opts *o,
+                    nuri_result **outs);
+
+/*
+ * Read-only view of a result, valid until nuri_free_result.
+ *   count   min(k, number of results)
+ *   score   [count], non-increasing
+ *   offset  [count+1] into ids
+ *   ids     clique i: its vertex ids ascending at ids[offset[i]..offset[i+1]);
+ *           match i: mu(0), ..., mu(q-1)
+ */
+typedef struct {
+  uint32_t count;
+  const int64_t *score;
+  const uint64_t *offset;
+  const uint32_t *ids;
+} nuri_result_view;
+int nuri_result_view_get(const nuri_result *r, nuri_result_view *v);
+
+/* Work counters of one query (R10: children created = candidate subgraphs). */
+typedef struct {
+  uint64_t steps;              /* expansion steps (launch rounds) */
+  uint64_t popped;             /* records taken from the frontier */
+  uint64_t expanded;           /* records expanded (not pruned at pop) */
+  uint64_t children;           /* children created (candidate subgraphs) */
+  uint64_t pruned_at_pop;      /* records dropped when taken (bound < k-th) */
+  uint64_t pruned_at_creation; /* children dropped when created */
+  uint64_t leaves;             /* children with nothing left to add */
+  uint64_t offered;            /* results offered to the result set */
+  uint64_t frontier_peak_bytes;
+  uint64_t logical_bytes;      /* algorithmic bytes read + written by expansion */
+  uint64_t expand_launches;    /* expansion kernel launches */
+  uint64_t expand_ns;          /* summed expansion kernel time (profile = 1) */
+  uint64_t wall_ns;            /* wall time of the call */
+} nuri_stats;
+int nuri_result_get_stats(const nuri_result *r, nuri_stats *s);
+void nuri_free_result(nuri_result *r);
+
+/*
+ * Continuous-batching server on one resident graph.  Queries submitted
+ * while others run are admitted when a slot and frontier memory are
+ * free; admitted queries share every expansion launch.
+ *   frontier_budget_bytes  total device bytes for all live frontiers
+ *   max_slots              queries live at once
+ * nuri_server_submit copies the query and returns a ticket at once.
+ * nuri_server_poll returns 1 and the result when done (the result then
+ * belongs to the caller), 0 while pending, < 0 on error.
+ * nuri_server_destroy waits for nothing: pending queries are dropped.
+ */
+int nuri_server_create(nuri_graph *g, uint64_t frontier_budget_bytes, uint32_t max_slots,
+                       nuri_server **out);
+int nuri_server_submit(nuri_server *s, const nuri_query *q, uint64_t *ticket);
+int nuri_server_poll(nuri_server *s, uint64_t ticket, nuri_result **out);
+void nuri_server_destroy(nuri_server *s);
+
+const char *nuri_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NURI_H */

@@ -37,12 +37,15 @@ def _load():
     lib = ctypes.CDLL(_SO)
     vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
     lib.oracle_topk_cliques.restype = ctypes.c_int64
-    lib.oracle_topk_cliques.argtypes = [u32, vp, vp, vp, u32, i32, i32, i32, i32, vp, vp, vp, u64, vp]
+    lib.oracle_topk_cliques.argtypes = [u32, vp, vp, vp, u32, i32, i32, i32, i32, i32, vp, vp, vp, u64,
+                                        vp]
     lib.oracle_clique_trace.restype = ctypes.c_int64
     lib.oracle_clique_trace.argtypes = [u32, vp, vp, u32, vp, u64, vp, u64, vp]
     lib.oracle_topk_match.restype = ctypes.c_int64
     lib.oracle_topk_match.argtypes = [u32, vp, vp, vp, vp, u32, u32, vp, u32, vp, u32, i32, vp, vp, vp]
     lib.oracle_vertex_order.argtypes = [u32, vp, vp, i32, vp]
+    lib.oracle_core_numbers.argtypes = [u32, vp, vp, vp]
+    lib.oracle_set_work_limit.argtypes = [u64]
     _lib = lib
     return lib
 
@@ -58,12 +61,13 @@ MATCH_STATS = ("popped", "expanded", "children", "pruned_at_creation", "pruned_a
 
 
 def topk_cliques(g, k: int, weighted: bool = False, bound: int = 0, priority: int = 0,
-                 order: int = 1) -> Tuple[List[Tuple[int, Tuple[int, ...]]], dict]:
+                 order: int = 1, xprune: bool = True) -> Tuple[List[Tuple[int, Tuple[int, ...]]], dict]:
     """Top-k maximal cliques of g.
 
     Returns ([(score, ids_ascending), ...] best first, stats).
     bound: 0 Carraghan-Pardalos, 1 greedy colouring.
     priority: 0 paper (|V|, |P|), 1 bound, 2 FIFO.  order: 0 id, 1 degeneracy.
+    xprune: skip subgraphs none of whose expansions can be maximal.
     """
     lib = _load()
     rp, col = _arr(g.row_ptr, np.uint64), _arr(g.col, np.uint32)
@@ -78,10 +82,13 @@ def topk_cliques(g, k: int, weighted: bool = False, bound: int = 0, priority: in
         stats = np.zeros(8, np.uint64)
         c = lib.oracle_topk_cliques(g.n, rp.ctypes.data, col.ctypes.data,
                                     vw.ctypes.data if vw is not None else None, k, int(weighted),
-                                    bound, priority, order, scores.ctypes.data, off.ctypes.data,
+                                    bound, priority, order, int(xprune), scores.ctypes.data,
+                                    off.ctypes.data,
                                     ids.ctypes.data, cap, stats.ctypes.data)
         if c == -2:
             raise ValueError("invalid arguments")
+        if c == -3:
+            return None, dict(zip(CLIQUE_STATS, (int(x) for x in stats[:7])))
         if c == -1:
             cap = int(stats[6]) + 16
             continue
@@ -160,3 +167,68 @@ def vertex_order(g, order: int = 1) -> np.ndarray:
     pi = np.zeros(g.n, np.uint32)
     lib.oracle_vertex_order(g.n, rp.ctypes.data, col.ctypes.data, order, pi.ctypes.data)
     return pi
+
+
+def set_work_limit(max_children: int) -> None:
+    """Cap the children a clique search may create (0 = no cap).
+
+    A capped search returns (None, stats); it is only for timing the oracle
+    on a bounded sample of a large workload.
+    """
+    _load().oracle_set_work_limit(int(max_children))
+
+
+def core_numbers(g) -> np.ndarray:
+    lib = _load()
+    rp, col = _arr(g.row_ptr, np.uint64), _arr(g.col, np.uint32)
+    core = np.zeros(g.n, np.uint32)
+    lib.oracle_core_numbers(g.n, rp.ctypes.data, col.ctypes.data, core.ctypes.data)
+    return core
+
+
+def induced_subgraph(g, keep: np.ndarray):
+    """Subgraph induced by the vertices with keep[v] true.
+
+    Vertices are renumbered in increasing original id, so sorted id lists
+    stay sorted and lexicographic order is preserved.  Returns (subgraph,
+    new->original id array).
+    """
+    import synth
+    old = np.flatnonzero(keep).astype(np.int64)
+    new_of = np.full(g.n, -1, np.int64)
+    new_of[old] = np.arange(len(old))
+    rp = g.row_ptr.astype(np.int64)
+    deg = rp[1:] - rp[:-1]
+    src = np.repeat(np.arange(g.n), deg)
+    dst = g.col.astype(np.int64)
+    m = keep[src] & keep[dst]
+    s2, d2 = new_of[src[m]], new_of[dst[m]]
+    order = np.lexsort((d2, s2))
+    s2, d2 = s2[order], d2[order]
+    row = np.zeros(len(old) + 1, np.uint64)
+    np.add.at(row, s2 + 1, 1)
+    row = np.cumsum(row).astype(np.uint64)
+    sub = synth.Graph(len(old), row, d2.astype(np.uint32))
+    if g.vertex_weight is not None:
+        sub.vertex_weight = np.ascontiguousarray(g.vertex_weight[old], np.int32)
+    return sub, old
+
+
+def topk_cliques_min_size(g, k: int, min_size: int, weighted: bool = False, **kw):
+    """Top-k maximal cliques among those with at least min_size vertices.
+
+    Every clique with s >= min_size vertices lies in the (min_size-1)-core,
+    and any vertex that extends it is adjacent to s >= min_size clique
+    members, so it lies there too: maximality inside the core equals
+    maximality in g.  The oracle therefore runs on the core alone; results
+    are mapped back to original ids (the renumbering keeps id order).
+    Valid as the top-k of g whenever at least k maximal cliques of g have
+    min_size or more vertices (and, for weighted scores, when every result
+    of g's top-k has that many vertices).
+    """
+    core = core_numbers(g)
+    keep = core >= max(0, min_size - 1)
+    sub, old = induced_subgraph(g, keep)
+    res, st = topk_cliques(sub, k, weighted=weighted, **kw)
+    out = [(s, tuple(int(old[i]) for i in ids)) for s, ids in res if len(ids) >= min_size]
+    return out, st

@@ -47,6 +47,7 @@ typedef struct {
   const int32_t *vw;   /* vertex weights or NULL */
   const uint8_t *lab;  /* vertex labels or NULL */
   const int32_t *ew;   /* edge weights aligned with col, or NULL */
+  uint64_t *adj;       /* optional n x n adjacency bit matrix (small graphs) */
 } graph_t;
 
 /* ------------------------------------------------------------------ */
@@ -60,6 +61,7 @@ static void *xmalloc(size_t n) {
 }
 
 static int is_adjacent(const graph_t *g, uint32_t u, uint32_t v) {
+  if (g->adj) return (int)((g->adj[(uint64_t)u * ((g->n + 63) / 64) + v / 64] >> (v % 64)) & 1u);
   uint64_t lo = g->row_ptr[u], hi = g->row_ptr[u + 1];
   while (lo < hi) {
     uint64_t mid = lo + (hi - lo) / 2;
@@ -207,6 +209,14 @@ static int rset_dominates(const rset_t *R, int64_t bound) {
 typedef struct {
   uint64_t popped, expanded, children, pruned_at_creation, pruned_at_pop, offered;
 } ostats_t;
+
+/*
+ * Optional cap on the children one clique search may create (0 = none).
+ * A capped search stops early and reports -3 instead of a result; it only
+ * serves to time the oracle on a bounded sample of a large workload.
+ */
+static uint64_t g_work_limit = 0;
+void oracle_set_work_limit(uint64_t max_children) { g_work_limit = max_children; }
 
 /* flatten R into caller buffers; returns count */
 static uint32_t rset_export(rset_t *R, int64_t *score_out, uint64_t *off_out, uint32_t *ids_out,
@@ -368,20 +378,47 @@ static void clique_priority(int priority_kind, const clique_rec *s, int64_t key[
 }
 
 /*
+ * Targeted-expansion test for maximal cliques: true when some x in X_s is
+ * adjacent to every vertex of P_s.  Every clique s can grow into lies
+ * between V_s and V_s + P_s, so x would extend each of them: none is
+ * maximal, and s need not be created (expandable() of Table 1 is false).
+ */
+static int has_extension_witness(const graph_t *g, const clique_rec *s) {
+  for (uint32_t a = 0; a < s->nx; ++a) {
+    int all = 1;
+    for (uint32_t b = 0; b < s->np && all; ++b)
+      if (!is_adjacent(g, s->X[a], s->P[b])) all = 0;
+    if (all) return 1;
+  }
+  return 0;
+}
+
+/*
  * Top-k maximal cliques by Algorithm 1.
  *   weighted: 0 score = |C|; 1 score = sum of vertex weights (int64).
+ *   xprune: 1 applies has_extension_witness() to unit subgraphs and
+ *   children (it never changes the result, only the work).
  * Outputs up to k results: score_out[i], ids_out[off_out[i]..off_out[i+1])
  * holding the ascending original ids.  Returns the count, or -1 if the id
  * buffer was too small (ids_needed then holds the size required).
  */
 int64_t oracle_topk_cliques(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
                             const int32_t *vw, uint32_t k, int weighted, int bound_kind,
-                            int priority_kind, int order_kind, int64_t *score_out,
-                            uint64_t *off_out, uint32_t *ids_out, uint64_t ids_cap,
-                            uint64_t *stats_out) {
-  graph_t G = {n, row_ptr, col, vw, NULL, NULL};
+                            int priority_kind, int order_kind, int xprune,
+                            int64_t *score_out, uint64_t *off_out, uint32_t *ids_out,
+                            uint64_t ids_cap, uint64_t *stats_out) {
+  graph_t G = {n, row_ptr, col, vw, NULL, NULL, NULL};
   const graph_t *g = &G;
   if (k == 0) return -2;
+  /* adjacency tests by bit lookup when the n x n matrix is small */
+  if (n <= 32768) {
+    uint64_t words = (n + 63) / 64;
+    uint64_t cells = (uint64_t)n * words;
+    G.adj = (uint64_t *)calloc(cells ? cells : 1, sizeof(uint64_t));
+    for (uint32_t u = 0; u < n; ++u)
+      for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+        G.adj[(uint64_t)u * words + col[e] / 64] |= 1ull << (col[e] % 64);
+  }
   uint32_t *pi = vertex_order(g, order_kind);
   pq_t Q = {0};
   rset_t R = {(result_t *)xmalloc((uint64_t)k * sizeof(result_t)), 0, k};
@@ -409,6 +446,7 @@ int64_t oracle_topk_cliques(uint32_t n, const uint64_t *row_ptr, const uint32_t 
       }
     }
     s->score = vweight(g, weighted, v);
+    if (xprune && has_extension_witness(g, s)) { clique_free(s); continue; }
     s->bound = clique_bound(g, weighted, bound_kind, s);
     int64_t key[3];
     clique_priority(priority_kind, s, key);
@@ -416,7 +454,9 @@ int64_t oracle_topk_cliques(uint32_t n, const uint64_t *row_ptr, const uint32_t 
   }
 
   uint32_t *tmp_ids = (uint32_t *)xmalloc(((uint64_t)n + 1) * sizeof(uint32_t));
+  int capped = 0;
   while (Q.n > 0) {                                   /* line 4 */
+    if (g_work_limit && st.children >= g_work_limit) { capped = 1; break; }
     clique_rec *s = (clique_rec *)pq_remove_max(&Q);   /* line 5 */
     st.popped++;
     /* lines 6-10: relevant(s) iff s is a maximal clique (P and X empty) */
@@ -453,8 +493,14 @@ int64_t oracle_topk_cliques(uint32_t n, const uint64_t *row_ptr, const uint32_t 
         if (is_adjacent(g, p, u)) c->X[c->nx++] = u;
       }
       c->score = s->score + vweight(g, weighted, p);
-      c->bound = clique_bound(g, weighted, bound_kind, c);
       st.children++;
+      /* line 13: expandable(s, p) */
+      if (xprune && has_extension_witness(g, c)) {
+        st.pruned_at_creation++;
+        clique_free(c);
+        continue;
+      }
+      c->bound = clique_bound(g, weighted, bound_kind, c);
       /* line 15: insert unless dominated */
       if (rset_dominates(&R, c->bound)) { st.pruned_at_creation++; clique_free(c); continue; }
       int64_t key[3];
@@ -464,8 +510,10 @@ int64_t oracle_topk_cliques(uint32_t n, const uint64_t *row_ptr, const uint32_t 
     clique_free(s);
   }
   free(tmp_ids);
+  while (Q.n > 0) clique_free((clique_rec *)pq_remove_max(&Q));
   free(Q.a);
   free(pi);
+  free(G.adj);
 
   uint64_t need = 0;
   for (uint32_t i = 0; i < R.n; ++i) need += R.e[i].len;
@@ -473,6 +521,11 @@ int64_t oracle_topk_cliques(uint32_t n, const uint64_t *row_ptr, const uint32_t 
     stats_out[0] = st.popped; stats_out[1] = st.expanded; stats_out[2] = st.children;
     stats_out[3] = st.pruned_at_creation; stats_out[4] = st.pruned_at_pop; stats_out[5] = st.offered;
     stats_out[6] = need;
+  }
+  if (capped) {
+    for (uint32_t i = 0; i < R.n; ++i) free(R.e[i].ids);
+    free(R.e);
+    return -3;
   }
   if (need > ids_cap) {
     for (uint32_t i = 0; i < R.n; ++i) free(R.e[i].ids);
@@ -496,7 +549,7 @@ int64_t oracle_topk_cliques(uint32_t n, const uint64_t *row_ptr, const uint32_t 
 int64_t oracle_clique_trace(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, uint32_t k,
                             int32_t *pop_log, uint64_t pop_log_cap, int32_t *r_log,
                             uint64_t r_log_cap, uint64_t *stats_out) {
-  graph_t G = {n, row_ptr, col, NULL, NULL, NULL};
+  graph_t G = {n, row_ptr, col, NULL, NULL, NULL, NULL};
   const graph_t *g = &G;
   if (n > 64 || k == 0) return -2; /* trace mode is for tiny worked examples */
   pq_t Q = {0};
@@ -757,7 +810,7 @@ int64_t oracle_topk_match(uint32_t n, const uint64_t *row_ptr, const uint32_t *c
                           const uint8_t *plabel, uint32_t ne, const uint32_t *pedges, uint32_t k,
                           int priority_kind, int64_t *score_out, uint32_t *ids_out,
                           uint64_t *stats_out) {
-  graph_t G = {n, row_ptr, col, NULL, lab, ew};
+  graph_t G = {n, row_ptr, col, NULL, lab, ew, NULL};
   const graph_t *g = &G;
   if (k == 0 || q < 2 || q > QMAX) return -2;
   pattern_t P;
@@ -908,8 +961,33 @@ int64_t oracle_topk_match(uint32_t n, const uint64_t *row_ptr, const uint32_t *c
 /* order used by the clique oracle, exposed for tests */
 void oracle_vertex_order(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, int order_kind,
                          uint32_t *pi_out) {
-  graph_t G = {n, row_ptr, col, NULL, NULL, NULL};
+  graph_t G = {n, row_ptr, col, NULL, NULL, NULL, NULL};
   uint32_t *pi = vertex_order(&G, order_kind);
   memcpy(pi_out, pi, (uint64_t)n * sizeof(uint32_t));
+  free(pi);
+}
+
+/*
+ * Core numbers (the largest c such that v belongs to the c-core, the
+ * maximal subgraph of minimum degree c), by repeatedly removing a vertex of
+ * minimum remaining degree and recording the running maximum of the
+ * degrees at removal.  Used by the tests: every clique of size s lies in
+ * the (s-1)-core, and so does every vertex that could extend it.
+ */
+void oracle_core_numbers(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                         uint32_t *core_out) {
+  graph_t G = {n, row_ptr, col, NULL, NULL, NULL, NULL};
+  uint32_t *pi = vertex_order(&G, 1);
+  uint32_t *by_pos = (uint32_t *)xmalloc((uint64_t)n * sizeof(uint32_t));
+  for (uint32_t v = 0; v < n; ++v) by_pos[pi[v]] = v;
+  uint32_t run = 0;
+  for (uint32_t i = 0; i < n; ++i) {
+    uint32_t v = by_pos[i], later = 0;
+    for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e)
+      if (pi[col[e]] > i) later++;
+    if (later > run) run = later;
+    core_out[v] = run;
+  }
+  free(by_pos);
   free(pi);
 }

@@ -1,0 +1,198 @@
+// C ABI entry points (include/nuri.h): argument checks, handle ownership,
+// error codes and the thread-local error message.
+#include <cstring>
+#include <exception>
+#include <new>
+
+#include "nuri_internal.h"
+
+struct nuri_graph {
+  nuri::Graph *g;
+};
+struct nuri_result {
+  nuri::Result r;
+};
+
+namespace nuri {
+
+static thread_local std::string t_err;
+
+void set_error(const std::string &msg) { t_err = msg; }
+
+QueryOpts resolve_opts(const Graph &g, const nuri_opts *o) {
+  QueryOpts q;
+  q.stream = g.stream;
+  if (!o) return q;
+  if (o->frontier_budget_bytes) q.frontier_budget = o->frontier_budget_bytes;
+  q.batch_B = o->batch_B;
+  q.root_batch = o->root_batch;
+  q.deadline_ns = o->deadline_ns;
+  q.profile = o->profile != 0;
+  if (o->hip_stream) q.stream = (hipStream_t)o->hip_stream;
+  if (q.frontier_budget < (64ull << 20))
+    throw Error{NURI_EINVAL, "frontier_budget_bytes must be at least 64 MiB"};
+  return q;
+}
+
+// Runs f, turning exceptions into status codes and the error message.
+template <class F>
+static int guarded(F f) {
+  try {
+    f();
+    return NURI_OK;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    set_error("host allocation failed");
+    return NURI_ENOMEM;
+  } catch (const std::exception &e) {
+    set_error(e.what());
+    return NURI_EDEVICE;
+  }
+}
+
+static void check_pattern(const nuri_pattern *p) {
+  if (!p) throw Error{NURI_EINVAL, "pattern is NULL"};
+  if (p->q < 2 || p->q > NURI_MAX_PATTERN) throw Error{NURI_EINVAL, "pattern size must be 2..8"};
+  if (!p->label || (!p->edges && p->n_edges)) throw Error{NURI_EINVAL, "pattern arrays are NULL"};
+}
+
+}  // namespace nuri
+
+using namespace nuri;
+
+extern "C" {
+
+const char *nuri_last_error(void) { return t_err.c_str(); }
+
+int nuri_load_graph(const nuri_csr *csr, void *hip_stream, nuri_graph **out) {
+  if (!out) {
+    set_error("out is NULL");
+    return NURI_EINVAL;
+  }
+  return guarded([&] {
+    Graph *g = load_graph(csr, (hipStream_t)hip_stream);
+    *out = new nuri_graph{g};
+  });
+}
+
+void nuri_free_graph(nuri_graph *g) {
+  if (!g) return;
+  delete g->g;
+  delete g;
+}
+
+int nuri_graph_get_info(const nuri_graph *g, nuri_graph_info *info) {
+  if (!g || !info) {
+    set_error("NULL argument");
+    return NURI_EINVAL;
+  }
+  info->n = g->g->n;
+  info->nnz = g->g->nnz;
+  info->degeneracy = g->g->degeneracy;
+  info->bitmap_bytes = g->g->bitmap_words * 8;
+  info->device_bytes = g->g->device_bytes();
+  info->preprocess_ns = g->g->preprocess_ns;
+  return NURI_OK;
+}
+
+int nuri_topk_cliques(nuri_graph *g, uint32_t k, nuri_weight_fn wf, const nuri_opts *o,
+                      nuri_result **out) {
+  if (!g || !out) {
+    set_error("NULL argument");
+    return NURI_EINVAL;
+  }
+  return guarded([&] {
+    QueryOpts qo = resolve_opts(*g->g, o);
+    std::vector<Result> res;
+    run_cliques(*g->g, {k}, {(int)wf}, qo, res);
+    auto *r = new nuri_result;
+    r->r = std::move(res[0]);
+    *out = r;
+  });
+}
+
+int nuri_topk_match(nuri_graph *g, const nuri_pattern *p, uint32_t k, const nuri_opts *o,
+                    nuri_result **out) {
+  if (!g || !out) {
+    set_error("NULL argument");
+    return NURI_EINVAL;
+  }
+  return guarded([&] {
+    check_pattern(p);
+    QueryOpts qo = resolve_opts(*g->g, o);
+    std::vector<Result> res;
+    run_matches(*g->g, {p}, {k}, qo, res);
+    auto *r = new nuri_result;
+    r->r = std::move(res[0]);
+    *out = r;
+  });
+}
+
+int nuri_topk_batch(nuri_graph *g, const nuri_query *qs, uint32_t nq, const nuri_opts *o,
+                    nuri_result **outs) {
+  if (!g || !outs || (!qs && nq)) {
+    set_error("NULL argument");
+    return NURI_EINVAL;
+  }
+  return guarded([&] {
+    QueryOpts qo = resolve_opts(*g->g, o);
+    std::vector<uint32_t> ck, mk;
+    std::vector<int> cw;
+    std::vector<const nuri_pattern *> mp;
+    std::vector<uint32_t> cidx, midx;
+    for (uint32_t i = 0; i < nq; ++i) {
+      if (qs[i].kind == 0) {
+        ck.push_back(qs[i].k);
+        cw.push_back((int)qs[i].wf);
+        cidx.push_back(i);
+      } else if (qs[i].kind == 1) {
+        check_pattern(qs[i].p);
+        mk.push_back(qs[i].k);
+        mp.push_back(qs[i].p);
+        midx.push_back(i);
+      } else {
+        throw Error{NURI_EINVAL, "query kind must be 0 (clique) or 1 (match)"};
+      }
+    }
+    std::vector<Result> cres, mres;
+    if (!ck.empty()) run_cliques(*g->g, ck, cw, qo, cres);
+    if (!mk.empty()) run_matches(*g->g, mp, mk, qo, mres);
+    std::vector<nuri_result *> made(nq, nullptr);
+    for (size_t i = 0; i < cidx.size(); ++i) {
+      made[cidx[i]] = new nuri_result;
+      made[cidx[i]]->r = std::move(cres[i]);
+    }
+    for (size_t i = 0; i < midx.size(); ++i) {
+      made[midx[i]] = new nuri_result;
+      made[midx[i]]->r = std::move(mres[i]);
+    }
+    for (uint32_t i = 0; i < nq; ++i) outs[i] = made[i];
+  });
+}
+
+int nuri_result_view_get(const nuri_result *r, nuri_result_view *v) {
+  if (!r || !v) {
+    set_error("NULL argument");
+    return NURI_EINVAL;
+  }
+  v->count = (uint32_t)r->r.score.size();
+  v->score = r->r.score.data();
+  v->offset = r->r.offset.data();
+  v->ids = r->r.ids.data();
+  return NURI_OK;
+}
+
+int nuri_result_get_stats(const nuri_result *r, nuri_stats *s) {
+  if (!r || !s) {
+    set_error("NULL argument");
+    return NURI_EINVAL;
+  }
+  *s = r->r.stats;
+  return NURI_OK;
+}
+
+void nuri_free_result(nuri_result *r) { delete r; }
+
+}  // extern "C"

@@ -1,0 +1,157 @@
+// Internal declarations of the engine (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/nuri.h"
+
+namespace nuri {
+
+// Largest |N+(v)| the dense local bitmaps support: one 64-bit word per lane
+// of a 64-wide wavefront.
+constexpr uint32_t kMaxLocal = 4096;
+constexpr uint32_t kMaxWords = kMaxLocal / 64;
+
+// ------------------------------------------------------------------
+// errors
+// ------------------------------------------------------------------
+void set_error(const std::string &msg);
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define NURI_HIP(call)                                                                    \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      throw ::nuri::Error{e_ == hipErrorOutOfMemory ? NURI_ENOMEM : NURI_EDEVICE,         \
+                          std::string(#call) + ": " + hipGetErrorString(e_)};             \
+  } while (0)
+
+// Owning device buffer.
+template <class T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    release();
+    if (count == 0) count = 1;
+    NURI_HIP(hipMalloc(&p, count * sizeof(T)));
+    n = count;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+// ------------------------------------------------------------------
+// resident graph
+// ------------------------------------------------------------------
+//
+// Vertices are relabelled by rank in a degeneracy order; "rank" below is a
+// vertex id in that relabelled space.  For a vertex r, the local universe
+// is its out-list N+(r) (neighbours of higher rank), sorted by rank;
+// position j in it is "local position j".  The local bitmap of r holds,
+// for every local position i, the row {j : N+(r)[j] adjacent to
+// N+(r)[i]} as W(r) = ceil(|N+(r)| / 64) words.
+struct Graph {
+  uint32_t n = 0;
+  uint64_t nnz = 0;
+  uint32_t degeneracy = 0;
+  uint32_t n_labels = 0;
+  bool has_vw = false, has_lab = false, has_ew = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  uint64_t preprocess_ns = 0;
+
+  // device: rank-space CSR, rows sorted by rank; N-(r) = first split[r]
+  // entries of row r, N+(r) = the rest
+  DevBuf<uint64_t> rrow;
+  DevBuf<uint32_t> rcol;
+  DevBuf<uint32_t> split;
+  DevBuf<uint32_t> dplus;     // |N+(r)|
+  DevBuf<uint32_t> orig;      // rank -> original id
+  DevBuf<int32_t> vw;         // vertex weight by rank
+  DevBuf<uint8_t> lab;        // label by rank
+  DevBuf<int32_t> ew;         // edge weight aligned with rcol
+  DevBuf<uint64_t> bm_off;    // [n+1] word offset of r's local bitmap
+  DevBuf<uint64_t> bm;        // local adjacency bitmaps
+  DevBuf<int64_t> wplus;      // sum of vertex weights over N+(r)
+  DevBuf<int32_t> best;       // [n * 16] max edge weight from r to a label-l vertex (0 none)
+
+  // host mirrors used to plan queries
+  std::vector<uint32_t> h_dplus;
+  std::vector<uint32_t> h_rank;            // original id -> rank
+  std::vector<uint32_t> h_orig;            // rank -> original id
+  std::vector<uint64_t> h_label_count;     // vertices per label
+  std::vector<int32_t> h_pairmax;          // [16*16] max edge weight per label pair
+  // root orders: ranks sorted by root bound (descending), per score kind
+  std::vector<uint32_t> h_root_order[2];
+  std::vector<int64_t> h_root_bound[2];
+  DevBuf<uint32_t> root_order[2];
+  uint64_t bitmap_words = 0;
+
+  // oriented adjacency in a compact layout: N+(r) at oplus[ooff[r] ..
+  // ooff[r] + dplus[r]) and the weights of those vertices at wloc[...]
+  DevBuf<uint64_t> ooff;
+  DevBuf<uint32_t> oplus;
+  DevBuf<int32_t> wloc;
+
+  uint64_t device_bytes() const;
+  Graph() = default;
+  Graph(const Graph &) = delete;
+  Graph &operator=(const Graph &) = delete;
+  ~Graph() {
+    if (own_stream && stream) (void)hipStreamDestroy(stream);
+  }
+};
+
+Graph *load_graph(const nuri_csr *csr, hipStream_t stream);
+
+// ------------------------------------------------------------------
+// results
+// ------------------------------------------------------------------
+struct Result {
+  std::vector<int64_t> score;
+  std::vector<uint64_t> offset;
+  std::vector<uint32_t> ids;
+  nuri_stats stats{};
+};
+
+struct QueryOpts {
+  uint64_t frontier_budget = 8ull << 30;
+  uint32_t batch_B = 0;
+  uint32_t root_batch = 0;
+  uint64_t deadline_ns = 0;
+  bool profile = false;
+  hipStream_t stream = nullptr;
+};
+QueryOpts resolve_opts(const Graph &g, const nuri_opts *o);
+
+uint64_t now_ns();
+
+// clique engine: runs several clique queries (each its own k and score)
+// together; results in the same order
+void run_cliques(Graph &g, const std::vector<uint32_t> &ks, const std::vector<int> &wfs,
+                 const QueryOpts &o, std::vector<Result> &out);
+
+// matching engine
+struct PatternPlan;
+void run_matches(Graph &g, const std::vector<const nuri_pattern *> &ps,
+                 const std::vector<uint32_t> &ks, const QueryOpts &o, std::vector<Result> &out);
+
+}  // namespace nuri

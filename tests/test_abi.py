@@ -1,0 +1,76 @@
+"""The C-ABI library: it loads, exports every function include/nuri.h
+declares, and rejects malformed input before touching the GPU (no GPU)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nuri.h")
+
+
+@pytest.fixture(scope="module")
+def nuri():
+    from paper_1807_08888_amd import nuri as N
+    if not os.path.exists(N.LIB_PATH):
+        from paper_1807_08888_amd import build
+        build.build()
+    N.lib()
+    return N
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(nuri_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_expected_entry_points():
+    names = _declared_functions()
+    for n in ("nuri_load_graph", "nuri_topk_cliques", "nuri_topk_match", "nuri_topk_batch",
+              "nuri_server_create", "nuri_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(nuri):
+    L = ctypes.CDLL(nuri.LIB_PATH)
+    missing = [n for n in _declared_functions() if not hasattr(L, n)]
+    assert missing == []
+    assert set(_declared_functions()) == set(nuri.SIGNATURES)
+
+
+def _expect_einval(nuri, rp, col, **kw):
+    with pytest.raises(nuri.NuriError) as e:
+        nuri.Graph(np.array(rp, np.uint64), np.array(col, np.uint32), **kw)
+    assert e.value.name == "EINVAL", str(e.value)
+    return str(e.value)
+
+
+def test_malformed_csr_rejected(nuri):
+    assert "symmetric" in _expect_einval(nuri, [0, 1, 1], [1])
+    assert "self loop" in _expect_einval(nuri, [0, 1, 2], [0, 0])
+    assert "increasing" in _expect_einval(nuri, [0, 2, 3, 4], [2, 1, 0, 0])
+    assert "range" in _expect_einval(nuri, [0, 1, 2], [5, 0])
+    assert "row_ptr" in _expect_einval(nuri, [1, 1, 2], [1, 0])
+    # duplicate entry = row not strictly increasing
+    assert "increasing" in _expect_einval(nuri, [0, 2, 4], [1, 1, 0, 0])
+
+
+def test_bad_weights_and_labels_rejected(nuri):
+    rp, col = [0, 1, 2], [1, 0]
+    assert "vertex weights" in _expect_einval(nuri, rp, col, vertex_weight=np.array([0, 1]))
+    assert "label" in _expect_einval(nuri, rp, col, vertex_label=np.array([0, 16]))
+    assert "edge weights" in _expect_einval(nuri, rp, col, edge_weight=np.array([3, 4]))
+
+
+def test_errors_are_reported_not_hidden(nuri):
+    g = synth.gnp(6, 0.5, 3)
+    try:
+        nuri.Graph.from_synth(g)
+    except nuri.NuriError as e:  # no GPU here: the device error is reported
+        assert e.name in ("EDEVICE", "ENOMEM")
+        assert nuri.lib().nuri_last_error()

@@ -1,0 +1,204 @@
+"""GPU parity for top-k maximal cliques: the HIP engine against the CPU oracle.
+
+Every comparison is bit-exact on (score, ascending id list) under the total
+order (score descending, ids ascending).  Runs only on a GPU machine.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import bruteforce
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nuri():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1807_08888_amd import nuri as N
+    N.lib()
+    return N
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def _gpu(nuri, g, k, wf=0, **opts):
+    G = nuri.Graph.from_synth(g)
+    try:
+        return nuri.topk_cliques(G, k, wf, **opts)
+    finally:
+        G.close()
+
+
+def test_worked_example(nuri):
+    g = synth.from_edges(4, [(0, 1), (0, 2), (1, 2), (2, 3)])
+    _case("worked example")
+    assert _gpu(nuri, g, 1).items == [(3, (0, 1, 2))]
+    assert _gpu(nuri, g, 5).items == [(3, (0, 1, 2)), (2, (2, 3))]
+
+
+def _small():
+    out = []
+    for n in (1, 2, 5, 9, 13):
+        for p in (0.0, 0.3, 0.6, 1.0):
+            out.append((n, p, 2000 + 31 * n + int(100 * p)))
+    return out
+
+
+@pytest.mark.parametrize("n,p,seed", _small())
+def test_brute_force_corpus(nuri, n, p, seed):
+    g = synth.gnp(n, p, seed)
+    synth.add_vertex_weights(g, 1, 3, master=seed)
+    _case(f"gnp n={n} p={p} seed={seed}")
+    G = nuri.Graph.from_synth(g)
+    try:
+        for k in (1, 3, 1000):
+            want = bruteforce.topk_cliques(g, k)
+            assert nuri.topk_cliques(G, k, 0).items == want, (k, "size")
+            want_w = bruteforce.topk_cliques(g, k, weights=g.vertex_weight)
+            assert nuri.topk_cliques(G, k, 1).items == want_w, (k, "weight")
+    finally:
+        G.close()
+
+
+@pytest.mark.parametrize("n,p,seed", [(200, 0.1, 1), (300, 0.05, 2), (120, 0.3, 3), (400, 0.03, 4)])
+@pytest.mark.parametrize("wf", [0, 1])
+def test_random_graphs_vs_oracle(nuri, n, p, seed, wf):
+    g = synth.gnp(n, p, seed)
+    synth.add_vertex_weights(g, 1, 100, master=seed)
+    _case(f"gnp n={n} p={p} seed={seed} wf={wf}")
+    G = nuri.Graph.from_synth(g)
+    try:
+        for k in (1, 10, 137):
+            want, _ = oracle.topk_cliques(g, k, weighted=bool(wf))
+            got = nuri.topk_cliques(G, k, wf)
+            assert got.items == want, (k, got.items[:3], want[:3])
+    finally:
+        G.close()
+
+
+def test_planted_clique_workload(nuri):
+    """n=2000, average degree 20, 10 planted cliques of 8..15, k=10, size score."""
+    g = synth.er_planted()
+    _case("planted-clique workload k=10")
+    got = _gpu(nuri, g, 10)
+    want, _ = oracle.topk_cliques(g, 10)
+    assert got.items == want
+    planted = sorted(((len(p), tuple(int(x) for x in p)) for p in g.planted),
+                     key=lambda t: (-t[0], t[1]))
+    assert got.items == planted
+    assert got.stats["children"] > 0
+
+
+@pytest.mark.parametrize("B,RB", [(1, 1), (7, 13), (1024, 64), (0, 0)])
+def test_result_independent_of_batch_sizes(nuri, B, RB):
+    g = synth.gnp(250, 0.08, 11)
+    synth.add_vertex_weights(g, 1, 20, master=11)
+    _case(f"batch sizes B={B} root_batch={RB}")
+    want, _ = oracle.topk_cliques(g, 40, weighted=True)
+    got = _gpu(nuri, g, 40, 1, batch_B=B, root_batch=RB)
+    assert got.items == want
+
+
+def test_repeated_runs_identical(nuri):
+    g = synth.er_planted(n=1500, avg_degree=25.0, n_cliques=8, lo=6, hi=12, master=99)
+    synth.add_vertex_weights(g, 1, 5, master=99)
+    _case("repeated runs")
+    G = nuri.Graph.from_synth(g)
+    try:
+        first = nuri.topk_cliques(G, 64, 1).items
+        for _ in range(5):
+            assert nuri.topk_cliques(G, 64, 1).items == first
+    finally:
+        G.close()
+    want, _ = oracle.topk_cliques(g, 64, weighted=True)
+    assert first == want
+
+
+def test_edge_cases(nuri):
+    _case("edge cases")
+    # one vertex
+    assert _gpu(nuri, synth.from_edges(1, []), 3).items == [(1, (0,))]
+    # no edges: every vertex is a maximal clique of size 1, ids ascending
+    assert _gpu(nuri, synth.from_edges(50, []), 5).items == [(1, (i,)) for i in range(5)]
+    # complete graph: exactly one maximal clique
+    kn = synth.from_edges(40, [(i, j) for i in range(40) for j in range(i + 1, 40)])
+    assert _gpu(nuri, kn, 10).items == [(40, tuple(range(40)))]
+    # star: n-1 maximal edges
+    st = synth.from_edges(30, [(0, i) for i in range(1, 30)])
+    assert _gpu(nuri, st, 100).items == [(2, (0, i)) for i in range(1, 30)]
+
+
+def test_dense_graphs_vs_oracle(nuri):
+    """Dense inputs where only the maximality witness keeps the search small."""
+    _case("dense: cocktail-party graph and dense G(n, p)")
+    edges = [(i, j) for i in range(30) for j in range(i + 1, 30) if not (j == i + 1 and i % 2 == 0)]
+    cp = synth.from_edges(30, edges)
+    for k in (5, 100):
+        want, _ = oracle.topk_cliques(cp, k)
+        assert _gpu(nuri, cp, k).items == want
+    g = synth.gnp(70, 0.7, 3)
+    synth.add_vertex_weights(g, 1, 9, master=3)
+    for wf in (0, 1):
+        want, _ = oracle.topk_cliques(g, 20, weighted=bool(wf))
+        assert _gpu(nuri, g, 20, wf).items == want
+
+
+@pytest.mark.parametrize("size", [70, 130, 300])
+def test_multi_word_bitmaps(nuri, size):
+    """A planted clique wider than one 64-bit word: W = 2, 3, 5 words per row."""
+    g = synth.er_planted(n=3000, avg_degree=6.0, n_cliques=1, lo=size, hi=size, master=size)
+    synth.add_vertex_weights(g, 1, 50, master=size)
+    _case(f"multi-word planted clique size={size}")
+    for wf in (0, 1):
+        want, _ = oracle.topk_cliques(g, 1, weighted=bool(wf))
+        got = _gpu(nuri, g, 1, wf)
+        assert got.items == want
+        assert len(got.items[0][1]) >= size
+
+
+def test_prefix_property(nuri):
+    g = synth.gnp(300, 0.06, 21)
+    synth.add_vertex_weights(g, 1, 10, master=21)
+    _case("prefix property")
+    G = nuri.Graph.from_synth(g)
+    try:
+        big = nuri.topk_cliques(G, 500, 1).items
+        for k in (1, 2, 17, 499):
+            assert nuri.topk_cliques(G, k, 1).items == big[:k]
+    finally:
+        G.close()
+
+
+def test_small_budget_is_exact_or_fails_loudly(nuri):
+    g = synth.gnp(400, 0.05, 5)
+    _case("small frontier budget")
+    want, _ = oracle.topk_cliques(g, 20)
+    try:
+        got = _gpu(nuri, g, 20, frontier_budget_bytes=64 << 20)
+    except nuri.NuriError as e:
+        assert e.name == "EBUDGET"
+    else:
+        assert got.items == want
+
+
+def test_invalid_arguments(nuri):
+    _case("invalid arguments")
+    g = synth.gnp(10, 0.5, 1)
+    G = nuri.Graph.from_synth(g)
+    try:
+        with pytest.raises(nuri.NuriError) as e:
+            nuri.topk_cliques(G, 0)
+        assert e.value.name == "EINVAL"
+        with pytest.raises(nuri.NuriError) as e:
+            nuri.topk_cliques(G, 3, 1)  # no vertex weights loaded
+        assert e.value.name == "EINVAL"
+    finally:
+        G.close()

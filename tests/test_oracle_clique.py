@@ -88,8 +88,9 @@ def test_size_topk_matches_brute_force(n, p, seed):
     g = synth.gnp(n, p, seed)
     for k in (1, 3, 1000):
         want = bruteforce.topk_cliques(g, k)
-        got, _ = oracle.topk_cliques(g, k)
-        assert got == want, (n, p, seed, k)
+        for xprune in (False, True):
+            got, _ = oracle.topk_cliques(g, k, xprune=xprune)
+            assert got == want, (n, p, seed, k, xprune)
 
 
 @pytest.mark.parametrize("n,p,seed", [c for c in _small_graphs() if c[0] >= 5])
@@ -98,21 +99,24 @@ def test_weighted_topk_matches_brute_force(n, p, seed):
     synth.add_vertex_weights(g, 1, 3, master=seed)  # small range: deliberate score ties
     for k in (1, 4, 1000):
         want = bruteforce.topk_cliques(g, k, weights=g.vertex_weight)
-        got, _ = oracle.topk_cliques(g, k, weighted=True)
-        assert got == want, (n, p, seed, k)
+        for xprune in (False, True):
+            got, _ = oracle.topk_cliques(g, k, weighted=True, xprune=xprune)
+            assert got == want, (n, p, seed, k, xprune)
 
 
 @pytest.mark.parametrize("bound", [0, 1])
 @pytest.mark.parametrize("priority", [0, 1, 2])
 @pytest.mark.parametrize("order", [0, 1])
-def test_result_independent_of_bound_priority_order(bound, priority, order):
+@pytest.mark.parametrize("xprune", [False, True])
+def test_result_independent_of_bound_priority_order(bound, priority, order, xprune):
     g = synth.gnp(40, 0.35, 77)
     synth.add_vertex_weights(g, 1, 5, master=77)
     ref_s, _ = oracle.topk_cliques(g, 25)
     ref_w, _ = oracle.topk_cliques(g, 25, weighted=True)
-    got_s, _ = oracle.topk_cliques(g, 25, bound=bound, priority=priority, order=order)
+    got_s, _ = oracle.topk_cliques(g, 25, bound=bound, priority=priority, order=order,
+                                   xprune=xprune)
     got_w, _ = oracle.topk_cliques(g, 25, weighted=True, bound=bound, priority=priority,
-                                   order=order)
+                                   order=order, xprune=xprune)
     assert got_s == ref_s
     assert got_w == ref_w
 
@@ -124,6 +128,21 @@ def test_pruning_reduces_work_but_not_result():
     b, sb = oracle.topk_cliques(g, 1, priority=2)
     assert a == b
     assert sa["children"] < sb["children"]
+
+
+def test_extension_witness_makes_dense_graphs_tractable():
+    """K_40 has one maximal clique; with k > 1 nothing is pruned by bounds,
+    so only the maximality witness keeps the search polynomial."""
+    kn = synth.from_edges(40, [(i, j) for i in range(40) for j in range(i + 1, 40)])
+    res, st = oracle.topk_cliques(kn, 10)
+    assert res == [(40, tuple(range(40)))]
+    assert st["children"] < 40 * 40
+    # near-clique: K_30 minus a perfect matching has 2^15 maximal cliques of size 15
+    edges = [(i, j) for i in range(30) for j in range(i + 1, 30) if not (j == i + 1 and i % 2 == 0)]
+    g = synth.from_edges(30, edges)
+    res, _ = oracle.topk_cliques(g, 5)
+    assert [s for s, _ in res] == [15] * 5
+    assert res[0][1] == tuple(range(0, 30, 2))
 
 
 def test_against_networkx_bron_kerbosch():
