@@ -62,6 +62,8 @@ def main() -> int:
     ap.add_argument("--k", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy first (scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -84,6 +86,15 @@ def main() -> int:
     G = nuri.Graph.from_synth(g, stream=stream)
     info = G.info()
     _log(f"loaded: {info}")
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        _log("copy calibration: 1 GiB read + 1 GiB written")
 
     def one():
         return nuri.topk_cliques(G, args.k, nuri.SCORE_SIZE, profile=True, stream=stream)

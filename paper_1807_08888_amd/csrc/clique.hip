@@ -38,12 +38,11 @@
 #include <cstddef>
 #include <cstring>
 
-#include "nuri_internal.h"
+#include "device_common.h"
 
 namespace nuri {
 namespace {
 
-typedef unsigned long long u64;
 
 struct CRec {
   long long score;
@@ -63,12 +62,6 @@ struct LRec {  // a child with an empty candidate set, awaiting the maximality c
   uint16_t qid;
 };
 
-struct Cand {  // a maximal clique offered to the result set
-  long long score;
-  uint32_t qid;
-  uint32_t len;
-};
-
 struct QCfg {  // per query, written by the host each step
   CRec *hdr;
   u64 *words;
@@ -80,22 +73,16 @@ struct QCfg {  // per query, written by the host each step
   uint32_t k;
 };
 
-struct QCtr {  // per query, device counters
-  // per step (cleared before each step)
+struct QStep {  // per query, this step's counters (zeroed by the step upload)
   unsigned int n_out, n_kept;
   u64 out_words, out_cost_children, out_cost_words;
   long long out_max_bound;
-  unsigned int overflow, pad;
-  // cumulative
-  u64 popped, expanded, children, pruned_pop, pruned_new, leaves, offered, logical_bytes;
+  u64 out_max_cc;  // largest children bound of one appended record
+  unsigned int out_max_w, overflow;
 };
 
-struct QRes {  // per query result state
-  long long theta;  // score of the k-th result; LLONG_MIN while fewer than k results
-  unsigned int tk_n, cur;
-  long long *tk_score[2];
-  unsigned int *tk_len[2];
-  unsigned int *tk_ids[2];  // stride lmax
+struct QCtr {  // per query, cumulative counters
+  u64 popped, expanded, children, pruned_pop, pruned_new, leaves, offered, logical_bytes;
 };
 
 struct GView {
@@ -109,10 +96,11 @@ struct GView {
 
 struct SelSeg {  // one query's level to take records from this step
   uint32_t qid, begin, count, take_all;
-  uint32_t shift, nbins_used;
+  uint32_t shift, temp_off;
   long long top;  // upper bound of every bound in the level
-  uint32_t temp_off, max_records;
-  u64 max_children, max_words;
+  u64 max_records, max_children, max_words;
+  u64 maxcc;      // largest children bound of one record in the level
+  u64 wpc;        // bitmap words per child, at most, in the level (2 W)
 };
 
 struct RootSeg {
@@ -120,240 +108,188 @@ struct RootSeg {
   uint32_t first, count;  // positions in the root order
 };
 
-constexpr int kBins = 2048;
-constexpr uint32_t kCandChunk = 2048;
-
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// bits of word w whose position w*64+b is greater than pos (pos may be -1)
-__device__ inline u64 gt_mask(int w, int pos) {
-  int lo = w * 64;
-  if (pos < lo) return ~0ull;
-  if (pos >= lo + 63) return 0ull;
-  return ~0ull << (pos - lo + 1);
-}
-
-// bits of word w whose position is below d
-__device__ inline u64 lt_mask(int w, uint32_t d) {
-  int lo = w * 64;
-  if ((int)d >= lo + 64) return ~0ull;
-  if ((int)d <= lo) return 0ull;
-  return (1ull << (d - lo)) - 1ull;
-}
-
-__device__ inline uint32_t words_of(uint32_t d) { return (d + 63) >> 6; }
-
-// exclusive prefix sum over the 64 lanes of a wave
-__device__ inline uint32_t wave_excl_scan(uint32_t x, int lane) {
-  uint32_t inc = x;
-  for (int off = 1; off < 64; off <<= 1) {
-    uint32_t t = __shfl_up(inc, off, 64);
-    if (lane >= off) inc += t;
-  }
-  return inc - x;
-}
-
-__device__ inline u64 wave_sum(u64 x) {
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
-
-__device__ inline long long wave_max(long long x) {
-  for (int off = 32; off > 0; off >>= 1) {
-    long long y = __shfl_xor(x, off, 64);
-    x = y > x ? y : x;
-  }
-  return x;
-}
-
 // ------------------------------------------------------------------
 // unit subgraphs (Algorithm 1, lines 1-3), taken in root-bound order
+// grid: (x, segment)
 // ------------------------------------------------------------------
-__global__ void k_make_roots(GView g, const RootSeg *segs, uint32_t nseg, CRec *batch,
-                             unsigned int *batch_count) {
-  // one block per segment chunk of 256 roots is simpler than a map: loop
-  for (uint32_t s = 0; s < nseg; ++s) {
-    RootSeg sg = segs[s];
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sg.count;
-         i += gridDim.x * blockDim.x) {
-      uint32_t r = g.root_order[sg.kind][sg.first + i];
-      CRec c;
-      c.score = sg.kind ? (long long)g.vw[r] : 1;
-      c.bound = sg.kind ? c.score + g.wplus[r] : 1 + (long long)g.dplus[r];
-      c.woff = 0;
-      c.root = r;
-      c.last = -1;
-      c.qid = (uint16_t)sg.qid;
-      unsigned int slot = atomicAdd(batch_count, 1u);
-      batch[slot] = c;
-    }
+__global__ void k_make_roots(GView g, const RootSeg *segs, CRec *batch, StepHdr *hdr) {
+  const RootSeg sg = segs[blockIdx.y];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sg.count;
+       i += gridDim.x * blockDim.x) {
+    uint32_t r = g.root_order[sg.kind][sg.first + i];
+    CRec c;
+    c.score = sg.kind ? (long long)g.vw[r] : 1;
+    c.bound = sg.kind ? c.score + g.wplus[r] : 1 + (long long)g.dplus[r];
+    c.woff = 0;
+    c.root = r;
+    c.last = -1;
+    c.qid = (uint16_t)sg.qid;
+    batch[atomicAdd(&hdr->batch_count, 1u)] = c;
   }
 }
 
 // ------------------------------------------------------------------
-// select: histogram of bounds, threshold, partition
+// select: histogram of bounds, threshold, partition.  grid: (x, segment)
 // ------------------------------------------------------------------
-// Record cost bounds: a record at `last` in a universe of d can create at
-// most d-last-1 children, each 2W words.
-__device__ inline void rec_cost(const GView &g, const CRec &c, u64 &children, u64 &words) {
-  uint32_t d = g.dplus[c.root];
-  u64 ch = (u64)(d - (uint32_t)(c.last + 1));
-  children = ch;
-  words = ch * 2 * words_of(d);
+// A record at `last` in a universe of d can create at most d-last-1
+// children.
+__device__ inline u64 rec_children(const GView &g, const CRec &c) {
+  return (u64)(g.dplus[c.root] - (uint32_t)(c.last + 1));
 }
 
-__device__ inline int bin_of(long long bound, long long top, uint32_t shift) {
-  long long gap = (top - bound) >> shift;
-  long long b = kBins - 1 - gap;
-  return b < 0 ? 0 : (b > kBins - 1 ? kBins - 1 : (int)b);
-}
-
-__global__ void k_sel_hist(GView g, const SelSeg *segs, const uint32_t *blk_seg,
-                           const uint32_t *blk_off, const QCfg *cfg, const QRes *res,
-                           unsigned int *hist, u64 *hchild, u64 *hword, u64 *hmaxc, u64 *hmaxw) {
-  uint32_t s = blk_seg[blockIdx.x];
-  SelSeg sg = segs[s];
+// per-block histograms in LDS, flushed with one atomic per non-empty bin
+__global__ void __launch_bounds__(256)
+    k_sel_hist(GView g, const SelSeg *segs, const QCfg *cfg, const QRes *res, unsigned int *hist,
+               u64 *hchild) {
+  __shared__ unsigned int s_h[kBins];
+  __shared__ u64 s_c[kBins];
+  const uint32_t s = blockIdx.y;
+  const SelSeg sg = segs[s];
   if (sg.take_all) return;
-  uint32_t i = blk_off[blockIdx.x] + threadIdx.x;
-  if (i >= sg.count) return;
-  const CRec c = cfg[sg.qid].hdr[sg.begin + i];
-  if (c.bound < res[sg.qid].theta) return;
-  int b = bin_of(c.bound, sg.top, sg.shift);
-  u64 ch, w;
-  rec_cost(g, c, ch, w);
-  size_t o = (size_t)s * kBins + b;
-  atomicAdd(&hist[o], 1u);
-  atomicAdd(&hchild[o], ch);
-  atomicAdd(&hword[o], w);
-  atomicMax(&hmaxc[o], ch);
-  atomicMax(&hmaxw[o], w);
-}
-
-// one wave per segment: scan bins from the top until a limit is reached
-__global__ void k_sel_thresh(const SelSeg *segs, uint32_t nseg, const unsigned int *hist,
-                             const u64 *hchild, const u64 *hword, const u64 *hmaxc,
-                             const u64 *hmaxw, int *thr, unsigned int *quota) {
-  uint32_t s = blockIdx.x;
-  if (s >= nseg || threadIdx.x != 0) return;
-  SelSeg sg = segs[s];
-  if (sg.take_all) return;
-  u64 n = 0, c = 0, w = 0;
-  int t = -1;
-  unsigned int q = 0;
-  for (int b = kBins - 1; b >= 0; --b) {
-    size_t o = (size_t)s * kBins + b;
-    u64 hn = hist[o];
-    if (!hn) continue;
-    if (n + hn <= sg.max_records && c + hchild[o] <= sg.max_children &&
-        w + hword[o] <= sg.max_words) {
-      n += hn;
-      c += hchild[o];
-      w += hword[o];
-      continue;
-    }
-    u64 qa = sg.max_records - n;
-    u64 mc = hmaxc[o] ? (sg.max_children - c) / hmaxc[o] : qa;
-    u64 mw = hmaxw[o] ? (sg.max_words - w) / hmaxw[o] : qa;
-    qa = qa < mc ? qa : mc;
-    qa = qa < mw ? qa : mw;
-    if (qa == 0 && n == 0) qa = 1;  // the host guarantees one record always fits
-    t = b;
-    q = (unsigned int)(qa < hn ? qa : hn);
-    break;
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) {
+    s_h[b] = 0;
+    s_c[b] = 0;
   }
-  thr[s] = t;
-  quota[s] = q;
+  __syncthreads();
+  const long long theta = res[sg.qid].theta;
+  const CRec *h = cfg[sg.qid].hdr + sg.begin;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sg.count;
+       i += gridDim.x * blockDim.x) {
+    const CRec c = h[i];
+    if (c.bound < theta) continue;
+    int b = bin_of(c.bound, sg.top, sg.shift);
+    atomicAdd(&s_h[b], 1u);
+    atomicAdd(&s_c[b], rec_children(g, c));
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x)
+    if (s_h[b]) {
+      atomicAdd(&hist[(size_t)s * kBins + b], s_h[b]);
+      atomicAdd(&hchild[(size_t)s * kBins + b], s_c[b]);
+    }
 }
 
-__global__ void k_sel_part(GView g, const SelSeg *segs, const uint32_t *blk_seg,
-                           const uint32_t *blk_off, const QCfg *cfg, const QRes *res,
-                           const int *thr, const unsigned int *quota, unsigned int *taken,
-                           CRec *batch, unsigned int *batch_count, CRec *temp,
-                           unsigned int *temp_count, QCtr *ctr) {
-  uint32_t s = blk_seg[blockIdx.x];
-  SelSeg sg = segs[s];
-  uint32_t i = blk_off[blockIdx.x] + threadIdx.x;
-  bool valid = i < sg.count;
-  CRec c;
-  int where = 0;  // 0 none, 1 batch, 2 keep, 3 pruned
-  if (valid) {
-    c = cfg[sg.qid].hdr[sg.begin + i];
-    if (c.bound < res[sg.qid].theta) {
+// one thread per segment: scan bins from the top until a limit is reached,
+// then clear the bins for the next step
+__global__ void k_sel_thresh(const SelSeg *segs, uint32_t nseg, unsigned int *hist, u64 *hchild,
+                             int *thr, unsigned int *quota) {
+  const uint32_t s = blockIdx.x;
+  if (s >= nseg) return;
+  const SelSeg sg = segs[s];
+  if (threadIdx.x == 0 && !sg.take_all) {
+    u64 n = 0, c = 0;
+    int t = -1;
+    unsigned int q = 0;
+    for (int b = kBins - 1; b >= 0; --b) {
+      size_t o = (size_t)s * kBins + b;
+      u64 hn = hist[o];
+      if (!hn) continue;
+      u64 hc = hchild[o];
+      if (n + hn <= sg.max_records && c + hc <= sg.max_children &&
+          (c + hc) * sg.wpc <= sg.max_words) {
+        n += hn;
+        c += hc;
+        continue;
+      }
+      u64 qa = sg.max_records - n;
+      u64 mc = sg.maxcc ? (sg.max_children - c) / sg.maxcc : qa;
+      u64 mw = sg.maxcc ? (sg.max_words - c * sg.wpc) / (sg.maxcc * sg.wpc) : qa;
+      qa = qa < mc ? qa : mc;
+      qa = qa < mw ? qa : mw;
+      if (qa == 0 && n == 0) qa = 1;  // the host guarantees one record always fits
+      t = b;
+      q = (unsigned int)(qa < hn ? qa : hn);
+      break;
+    }
+    thr[s] = t;
+    quota[s] = q;
+  }
+  __syncthreads();
+  if (!sg.take_all)
+    for (int b = threadIdx.x; b < kBins; b += blockDim.x) {
+      hist[(size_t)s * kBins + b] = 0;
+      hchild[(size_t)s * kBins + b] = 0;
+    }
+}
+
+__global__ void k_sel_part(const SelSeg *segs, const QCfg *cfg, const QRes *res, const int *thr,
+                           const unsigned int *quota, unsigned int *taken, CRec *batch,
+                           StepHdr *hdr, CRec *temp, unsigned int *temp_count, QCtr *ctr) {
+  const uint32_t s = blockIdx.y;
+  const SelSeg sg = segs[s];
+  const long long theta = res[sg.qid].theta;
+  const CRec *h = cfg[sg.qid].hdr + sg.begin;
+  const int t = sg.take_all ? -1 : thr[s];
+  const unsigned int qt = sg.take_all ? 0 : quota[s];
+  unsigned int pruned = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sg.count;
+       i += gridDim.x * blockDim.x) {
+    const CRec c = h[i];
+    int where;  // 1 batch, 2 keep, 3 pruned
+    if (c.bound < theta) {
       where = 3;
     } else if (sg.take_all) {
       where = 1;
     } else {
       int b = bin_of(c.bound, sg.top, sg.shift);
-      int t = thr[s];
       if (b > t) where = 1;
       else if (b < t) where = 2;
-      else where = atomicAdd(&taken[s], 1u) < quota[s] ? 1 : 2;
+      else where = atomicAdd(&taken[s], 1u) < qt ? 1 : 2;
     }
+    if (where == 1) batch[atomicAdd(&hdr->batch_count, 1u)] = c;
+    else if (where == 2) temp[sg.temp_off + atomicAdd(&temp_count[s], 1u)] = c;
+    else ++pruned;
   }
-  if (where == 1) batch[atomicAdd(batch_count, 1u)] = c;
-  if (where == 2) temp[sg.temp_off + atomicAdd(&temp_count[s], 1u)] = c;
-  if (where == 3) {
-    atomicAdd(&ctr[sg.qid].popped, 1ull);
-    atomicAdd(&ctr[sg.qid].pruned_pop, 1ull);
+  if (pruned) {
+    atomicAdd(&ctr[sg.qid].popped, (u64)pruned);
+    atomicAdd(&ctr[sg.qid].pruned_pop, (u64)pruned);
   }
 }
 
-// clear the per-step counters of every query
-__global__ void k_reset_step(QCtr *ctr, uint32_t nq) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nq) return;
-  QCtr &c = ctr[i];
-  c.n_out = c.n_kept = 0;
-  c.out_words = c.out_cost_children = c.out_cost_words = 0;
-  c.out_max_bound = LLONG_MIN;
-  c.overflow = 0;
-}
-
-__global__ void k_copy_back(const SelSeg *segs, uint32_t nseg, const QCfg *cfg, const CRec *temp,
-                            const unsigned int *temp_count, QCtr *ctr) {
-  for (uint32_t s = 0; s < nseg; ++s) {
-    SelSeg sg = segs[s];
-    unsigned int kept = sg.take_all ? 0u : temp_count[s];
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < kept;
-         i += gridDim.x * blockDim.x)
-      cfg[sg.qid].hdr[sg.begin + i] = temp[sg.temp_off + i];
-    if (blockIdx.x == 0 && threadIdx.x == 0) ctr[sg.qid].n_kept = kept;
-  }
+__global__ void k_copy_back(const SelSeg *segs, const QCfg *cfg, const CRec *temp,
+                            const unsigned int *temp_count, QStep *qs) {
+  const uint32_t s = blockIdx.y;
+  const SelSeg sg = segs[s];
+  const unsigned int kept = sg.take_all ? 0u : temp_count[s];
+  CRec *h = cfg[sg.qid].hdr + sg.begin;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < kept; i += gridDim.x * blockDim.x)
+    h[i] = temp[sg.temp_off + i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) qs[sg.qid].n_kept = kept;
 }
 
 // ------------------------------------------------------------------
 // expand (Algorithm 1, lines 11-16)
 // ------------------------------------------------------------------
 // One wavefront per record.  The record's candidate positions are listed
-// in LDS; its children are then processed 64/G at a time, G = the power of
-// two >= W lanes per child, each lane ANDing one word of the parent's
-// candidate bitmap with one word of the child vertex's local adjacency
-// row.  Group reductions give |P'| (or w(P')); survivors are compacted
-// with a ballot and one atomic per wave and written with coalesced stores.
+// in LDS.  Child idx (the idx-th candidate) can reach at most
+// score + (weight of candidates idx, idx+1, ...), so every child past the
+// first idx where that falls below the k-th score is dominated before it
+// is built (the Carraghan-Pardalos cutoff); those are counted as created
+// and pruned without touching memory.  The remaining children are
+// processed 64/G at a time, G = the power of two >= W lanes per child,
+// each lane ANDing one word of the parent's bitmaps with one word of the
+// child vertex's local adjacency row.  Group reductions give |P'| (or
+// w(P')); survivors are compacted with a ballot and one atomic per wave
+// and written with coalesced stores.
 constexpr int kExpandWaves = 4;
 
 __global__ void __launch_bounds__(64 * kExpandWaves)
-    k_expand(GView g, const CRec *__restrict__ batch, const unsigned int *batch_count,
-             const QCfg *__restrict__ cfg, QCtr *ctr, const QRes *__restrict__ res, LRec *leaves,
-             unsigned int *leaf_count, u64 *leaf_words, u64 *leaf_word_count, uint32_t leaf_cap,
-             u64 leaf_word_cap) {
+    k_expand(GView g, const CRec *__restrict__ batch, StepHdr *hdr, const QCfg *__restrict__ cfg,
+             QStep *qs, QCtr *ctr, const QRes *__restrict__ res, LRec *leaves, u64 *leaf_words,
+             uint32_t leaf_cap, u64 leaf_word_cap) {
   __shared__ uint16_t s_list[kExpandWaves][kMaxLocal];
   __shared__ u64 s_pw[kExpandWaves][kMaxWords];
   __shared__ u64 s_vw[kExpandWaves][kMaxWords];
   __shared__ u64 s_xw[kExpandWaves][kMaxWords];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t rec = blockIdx.x * kExpandWaves + wv;
-  if (rec >= *batch_count) return;
+  if (rec >= hdr->batch_count) return;
   const CRec p = batch[rec];
   const uint32_t q = p.qid;
   const QCfg cf = cfg[q];
   const long long theta = res[q].theta;
-  u64 st_popped = 1, st_pruned_pop = 0, st_expanded = 0, st_children = 0, st_pruned_new = 0,
-      st_leaves = 0, st_bytes = 0, st_cost_c = 0, st_cost_w = 0;
+  u64 st_pruned_pop = 0, st_expanded = 0, st_children = 0, st_pruned_new = 0, st_leaves = 0,
+      st_bytes = 0, st_cost_c = 0, st_cost_w = 0, st_max_cc = 0;
   long long st_maxb = LLONG_MIN;
 
   const uint32_t r = p.root;
@@ -365,7 +301,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     // a unit subgraph with no later neighbour: itself a leaf
     st_leaves = 1;
     if (p.score >= theta && lane == 0) {
-      unsigned int slot = atomicAdd(leaf_count, 1u);
+      unsigned int slot = atomicAdd(&hdr->leaf_count, 1u);
       if (slot < leaf_cap) {
         LRec l;
         l.score = p.score;
@@ -375,11 +311,13 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         l.qid = (uint16_t)q;
         leaves[slot] = l;
       } else {
-        atomicAdd(&ctr[q].overflow, 1u);
+        atomicAdd(&qs[q].overflow, 1u);
       }
     }
   } else {
     const int last = p.last;
+    const bool weighted = cf.weighted != 0;
+    const int32_t *wl = g.wloc + g.ooff[r];
     u64 word = 0, xword = 0;
     if (lane < (int)W) {
       word = last < 0 ? lt_mask(lane, d) : cf.words[p.woff + lane];
@@ -392,40 +330,70 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       s_vw[wv][lane] = vwd;
       s_xw[wv][lane] = xword;
     }
-    // list the candidate positions in increasing order
+    // list the candidate positions in increasing order, and the weight of
+    // this lane's share of them
     uint32_t c = __popcll(pw);
     uint32_t off = wave_excl_scan(c, lane);
-    uint32_t nchild = __shfl(off + c, 63, 64);
+    const uint32_t nchild = __shfl(off + c, 63, 64);
+    long long lsum = 0;
     {
       u64 t = pw;
       uint32_t o = off;
       while (t) {
         int b = __ffsll((long long)t) - 1;
         s_list[wv][o++] = (uint16_t)(lane * 64 + b);
+        lsum += weighted ? (long long)wl[lane * 64 + b] : 1ll;
         t &= t - 1;
       }
+    }
+    // cutoff: first idx whose prefix weight exceeds total + score - theta
+    uint32_t n_eff = nchild;
+    if (theta != LLONG_MIN) {
+      const long long lexcl = wave_excl_scan64(lsum, lane);
+      const long long total = __shfl(lexcl + lsum, 63, 64);
+      const long long R = total + p.score - theta;
+      uint32_t cut = 0xFFFFFFFFu;
+      if (R < 0) {
+        cut = 0;
+      } else if (c && lexcl + lsum > R) {
+        long long run = lexcl;
+        uint32_t idx = off;
+        u64 t = pw;
+        while (t) {
+          if (run > R) {
+            cut = idx;
+            break;
+          }
+          int b = __ffsll((long long)t) - 1;
+          run += weighted ? (long long)wl[lane * 64 + b] : 1ll;
+          ++idx;
+          t &= t - 1;
+        }
+      }
+      cut = wave_min_u32(cut);
+      if (cut < n_eff) n_eff = cut;
     }
     wave_sync();
     if (last >= 0 && lane == 0) st_bytes += 32 + 16ull * W;  // the parent record
     if (nchild) st_expanded = 1;
+    st_children = nchild;
+    st_pruned_new = nchild - n_eff;
     const u64 *rows = g.bm + g.bm_off[r];
-    const int32_t *wl = g.wloc + g.ooff[r];
-    const bool weighted = cf.weighted != 0;
     uint32_t G = 1;
     while (G < W) G <<= 1;
     const uint32_t per = 64 / G;
     const int wi = lane & (G - 1);
     const int gl = lane & ~(int)(G - 1);  // lane of this group's leader
-    for (uint32_t base = 0; base < nchild; base += per) {
+    for (uint32_t base = 0; base < n_eff; base += per) {
       const uint32_t ci = base + lane / G;
-      const bool valid = ci < nchild;
+      const bool valid = ci < n_eff;
       const uint32_t j = valid ? s_list[wv][ci] : 0;
       u64 a = 0, xc = 0;
       if (valid && wi < (int)W) {
         const u64 row = rows[(u64)j * W + wi];
         const u64 pv = s_pw[wv][wi];
-        a = pv & row & gt_mask(wi, (int)j);                              // P'
-        xc = (s_xw[wv][wi] | (pv & ~gt_mask(wi, (int)j - 1))) & row;     // X'
+        a = pv & row & gt_mask(wi, (int)j);                           // P'
+        xc = (s_xw[wv][wi] | (pv & ~gt_mask(wi, (int)j - 1))) & row;  // X'
       }
       // extension witness: the first vertex of X'; if it is adjacent to all
       // of P', no clique below this child is maximal
@@ -464,7 +432,6 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       const u64 lm = __ballot(leader);
       const u64 km = __ballot(leader && keep);
       const u64 fm = __ballot(leader && offer);
-      st_children += __popcll(lm);
       st_pruned_new += __popcll(__ballot(leader && prune));
       st_leaves += __popcll(__ballot(leader && leaf));
       if (lane == 0) st_bytes += 8ull * W * __popcll(lm);  // adjacency rows read
@@ -476,8 +443,8 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         unsigned int h0 = 0;
         u64 w0 = 0;
         if (lane == 0) {
-          h0 = atomicAdd(&ctr[q].n_out, nk);
-          w0 = atomicAdd(&ctr[q].out_words, (u64)nk * 2 * W);
+          h0 = atomicAdd(&qs[q].n_out, nk);
+          w0 = atomicAdd(&qs[q].out_words, (u64)nk * 2 * W);
         }
         h0 = __shfl(h0, 0, 64);
         w0 = __shfl(w0, 0, 64);
@@ -501,12 +468,13 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
               cf.hdr[slot_h] = ch;
             }
           } else if (wi == 0) {
-            atomicAdd(&ctr[q].overflow, 1u);
+            atomicAdd(&qs[q].overflow, 1u);
           }
           if (wi == 0) {
             u64 cc = (u64)(d - j - 1);
             st_cost_c += cc;
             st_cost_w += cc * 2 * W;
+            st_max_cc = cc > st_max_cc ? cc : st_max_cc;
             st_maxb = bound2 > st_maxb ? bound2 : st_maxb;
             st_bytes += 32 + 16ull * W;
           }
@@ -517,8 +485,8 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         unsigned int l0 = 0;
         u64 w0 = 0;
         if (lane == 0) {
-          l0 = atomicAdd(leaf_count, nf);
-          w0 = atomicAdd(leaf_word_count, (u64)nf * W);
+          l0 = atomicAdd(&hdr->leaf_count, nf);
+          w0 = atomicAdd(&hdr->leaf_word_count, (u64)nf * W);
         }
         l0 = __shfl(l0, 0, 64);
         w0 = __shfl(w0, 0, 64);
@@ -539,7 +507,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
               st_bytes += 24 + 8ull * W;
             }
           } else if (wi == 0) {
-            atomicAdd(&ctr[q].overflow, 1u);
+            atomicAdd(&qs[q].overflow, 1u);
           }
         }
       }
@@ -549,19 +517,25 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   st_cost_c = wave_sum(st_cost_c);
   st_cost_w = wave_sum(st_cost_w);
   st_bytes = wave_sum(st_bytes);
+  st_max_cc = wave_max_u64(st_max_cc);
   st_maxb = wave_max(st_maxb);
   if (lane == 0) {
     QCtr &C = ctr[q];
-    atomicAdd(&C.popped, st_popped);
+    atomicAdd(&C.popped, 1ull);
     if (st_pruned_pop) atomicAdd(&C.pruned_pop, st_pruned_pop);
     if (st_expanded) atomicAdd(&C.expanded, st_expanded);
     if (st_children) atomicAdd(&C.children, st_children);
     if (st_pruned_new) atomicAdd(&C.pruned_new, st_pruned_new);
     if (st_leaves) atomicAdd(&C.leaves, st_leaves);
     if (st_bytes) atomicAdd(&C.logical_bytes, st_bytes);
-    if (st_cost_c) atomicAdd(&C.out_cost_children, st_cost_c);
-    if (st_cost_w) atomicAdd(&C.out_cost_words, st_cost_w);
-    if (st_maxb != LLONG_MIN) atomicMax(&C.out_max_bound, st_maxb);
+    QStep &S = qs[q];
+    if (st_cost_c) {
+      atomicAdd(&S.out_cost_children, st_cost_c);
+      atomicAdd(&S.out_cost_words, st_cost_w);
+      atomicMax(&S.out_max_cc, st_max_cc);
+      atomicMax(&S.out_max_w, W);
+    }
+    if (st_maxb != LLONG_MIN) atomicMax(&S.out_max_bound, st_maxb);
   }
 }
 
@@ -693,85 +667,6 @@ __global__ void __launch_bounds__(64)
 }
 
 // ------------------------------------------------------------------
-// top-k merge (Algorithm 1, lines 6-10) under the total order
-// (score descending, then ascending id list lexicographically)
-// ------------------------------------------------------------------
-__device__ inline bool before(long long sa, const uint32_t *a, uint32_t la, long long sb,
-                              const uint32_t *b, uint32_t lb) {
-  if (sa != sb) return sa > sb;
-  uint32_t n = la < lb ? la : lb;
-  for (uint32_t i = 0; i < n; ++i)
-    if (a[i] != b[i]) return a[i] < b[i];
-  return la < lb;
-}
-
-__global__ void __launch_bounds__(1024)
-    k_merge(const Cand *cands, const unsigned int *cand_count, const uint32_t *cand_ids,
-            uint32_t lmax, QRes *res, const uint32_t *ks) {
-  __shared__ uint32_t s_idx[kCandChunk];
-  __shared__ unsigned int s_n;
-  const uint32_t q = blockIdx.x;
-  if (threadIdx.x == 0) s_n = 0;
-  __syncthreads();
-  const uint32_t nc_all = *cand_count;
-  for (uint32_t i = threadIdx.x; i < nc_all; i += blockDim.x)
-    if (cands[i].qid == q) s_idx[atomicAdd(&s_n, 1u)] = i;
-  __syncthreads();
-  const uint32_t nc = s_n;
-  if (nc == 0) return;
-  QRes R = res[q];
-  const uint32_t k = ks[q];
-  const uint32_t cur = R.cur, alt = cur ^ 1u;
-  const uint32_t N = R.tk_n + nc;
-  for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
-    long long si;
-    const uint32_t *ai;
-    uint32_t li;
-    if (i < R.tk_n) {
-      si = R.tk_score[cur][i];
-      ai = R.tk_ids[cur] + (u64)i * lmax;
-      li = R.tk_len[cur][i];
-    } else {
-      uint32_t c = s_idx[i - R.tk_n];
-      si = cands[c].score;
-      ai = cand_ids + (u64)c * lmax;
-      li = cands[c].len;
-    }
-    uint32_t rank = 0;
-    for (uint32_t j = 0; j < N && rank < k; ++j) {
-      if (j == i) continue;
-      long long sj;
-      const uint32_t *aj;
-      uint32_t lj;
-      if (j < R.tk_n) {
-        sj = R.tk_score[cur][j];
-        aj = R.tk_ids[cur] + (u64)j * lmax;
-        lj = R.tk_len[cur][j];
-      } else {
-        uint32_t c = s_idx[j - R.tk_n];
-        sj = cands[c].score;
-        aj = cand_ids + (u64)c * lmax;
-        lj = cands[c].len;
-      }
-      rank += before(sj, aj, lj, si, ai, li);
-    }
-    if (rank < k) {
-      R.tk_score[alt][rank] = si;
-      R.tk_len[alt][rank] = li;
-      uint32_t *dst = R.tk_ids[alt] + (u64)rank * lmax;
-      for (uint32_t t = 0; t < li; ++t) dst[t] = ai[t];
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t nn = N < k ? N : k;
-    res[q].tk_n = nn;
-    res[q].cur = alt;
-    res[q].theta = nn == k ? R.tk_score[alt][k - 1] : LLONG_MIN;
-  }
-}
-
-// ------------------------------------------------------------------
 // host side
 // ------------------------------------------------------------------
 struct Level {
@@ -779,6 +674,8 @@ struct Level {
   u64 wbegin = 0, wend = 0;
   u64 cost_children = 0, cost_words = 0;
   long long max_bound = LLONG_MIN;
+  u64 maxcc = 0;
+  uint32_t maxw = 0;
 };
 
 struct QHost {
@@ -797,44 +694,67 @@ struct QHost {
   int sel_seg = -1;
 };
 
+// Layout of the per-step block that one host-to-device copy uploads and
+// one device-to-host copy (of its first part) reads back.
+struct StepLayout {
+  size_t qs, cfg, seg, rseg, taken, tempc, thr, quota, total;
+  explicit StepLayout(uint32_t nq) {
+    size_t o = sizeof(StepHdr);
+    qs = o;
+    o += nq * sizeof(QStep);
+    cfg = o;
+    o += nq * sizeof(QCfg);
+    seg = o;
+    o += nq * sizeof(SelSeg);
+    rseg = o;
+    o += nq * sizeof(RootSeg);
+    taken = o;
+    o += nq * 4;
+    tempc = o;
+    o += nq * 4;
+    thr = o;
+    o += nq * 4;
+    quota = o;
+    o += nq * 4;
+    total = (o + 255) & ~size_t(255);
+  }
+  size_t readback() const { return cfg; }  // StepHdr + QStep[nq]
+};
+
 struct Engine {
   Graph &g;
   const QueryOpts &o;
   hipStream_t s;
-  uint32_t nq;
-  uint32_t lmax;
+  uint32_t nq = 0;
+  uint32_t lmax = 0;
   std::vector<QHost> qh;
+  std::vector<QCfg> cfg;
 
   DevBuf<CRec> hdr;
   DevBuf<u64> words;
-  DevBuf<QCfg> d_cfg;
   DevBuf<QCtr> d_ctr;
   DevBuf<QRes> d_res;
   DevBuf<uint32_t> d_k;
   DevBuf<long long> tk_score;
   DevBuf<unsigned int> tk_len, tk_ids;
   DevBuf<CRec> batch, temp;
-  DevBuf<unsigned int> counters;  // [0] batch, [1] leaf, [2] cand
-  DevBuf<u64> leaf_word_count;
   DevBuf<LRec> leaves;
   DevBuf<u64> leaf_words;
   DevBuf<Cand> cands;
   DevBuf<uint32_t> cand_ids;
-  DevBuf<SelSeg> d_seg;
-  DevBuf<RootSeg> d_rseg;
-  DevBuf<uint32_t> d_blk_seg, d_blk_off;
-  DevBuf<unsigned int> d_hist, d_taken, d_tempc, d_quota;
-  DevBuf<u64> d_hchild, d_hword, d_hmaxc, d_hmaxw;
-  DevBuf<int> d_thr;
-  std::vector<QCfg> h_cfg;
+  DevBuf<unsigned int> d_hist;
+  DevBuf<u64> d_hchild;
+  DevBuf<unsigned char> d_step;
+  PinBuf<unsigned char> h_step;
+  PinBuf<QRes> h_res;
   std::vector<QCtr> h_ctr;
-  std::vector<QRes> h_res;
   uint32_t batch_cap = 0, leaf_cap = 0;
   u64 leaf_word_cap = 0;
   uint32_t B = 0, root_B = 0;
   u64 step_children = 0, step_words = 0;
   uint64_t steps = 0, launches = 0, expand_ns = 0, peak_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::unique_ptr<StepLayout> L;
 
   Engine(Graph &g_, const QueryOpts &o_) : g(g_), o(o_), s(o_.stream ? o_.stream : g_.stream) {}
   ~Engine() {
@@ -861,10 +781,21 @@ struct Engine {
     return v;
   }
 
+  StepHdr *sh() { return (StepHdr *)h_step.p; }
+  QStep *sq() { return (QStep *)(h_step.p + L->qs); }
+  SelSeg *sseg() { return (SelSeg *)(h_step.p + L->seg); }
+  RootSeg *srseg() { return (RootSeg *)(h_step.p + L->rseg); }
+  template <class T>
+  T *dev(size_t off) {
+    return (T *)(d_step.p + off);
+  }
+
   void setup(const std::vector<uint32_t> &ks, const std::vector<int> &kinds) {
     nq = (uint32_t)ks.size();
     lmax = g.degeneracy + 1;
     qh.resize(nq);
+    cfg.resize(nq);
+    L.reset(new StepLayout(nq));
     // frontier budget: a third for headers, the rest for bitmap words,
     // split evenly between the queries
     u64 budget = o.frontier_budget;
@@ -874,14 +805,12 @@ struct Engine {
     hdr_per_q = std::min<u64>(hdr_per_q, 0x7FFFFFFFull);
     hdr.alloc(hdr_per_q * nq);
     words.alloc(word_per_q * nq);
-    h_cfg.resize(nq);
-    h_ctr.assign(nq, QCtr{});
-    h_res.resize(nq);
     u64 tk_total = 0;
     for (uint32_t i = 0; i < nq; ++i) tk_total += ks[i];
     tk_score.alloc(2 * tk_total);
     tk_len.alloc(2 * tk_total);
     tk_ids.alloc(2 * tk_total * lmax);
+    h_res.alloc(nq);
     u64 tko = 0;
     for (uint32_t i = 0; i < nq; ++i) {
       QHost &Q = qh[i];
@@ -889,7 +818,7 @@ struct Engine {
       Q.kind = kinds[i];
       Q.hdr_cap = (uint32_t)hdr_per_q;
       Q.word_cap = word_per_q;
-      QCfg &c = h_cfg[i];
+      QCfg &c = cfg[i];
       c.hdr = hdr.p + (u64)i * hdr_per_q;
       c.words = words.p + (u64)i * word_per_q;
       c.out_word = 0;
@@ -898,7 +827,7 @@ struct Engine {
       c.hdr_cap = (uint32_t)hdr_per_q;
       c.weighted = kinds[i];
       c.k = ks[i];
-      QRes &R = h_res[i];
+      QRes &R = h_res.p[i];
       R.theta = LLONG_MIN;
       R.tk_n = 0;
       R.cur = 0;
@@ -909,13 +838,13 @@ struct Engine {
       }
       tko += ks[i];
     }
-    d_cfg.alloc(nq);
     d_ctr.alloc(nq);
     d_res.alloc(nq);
     d_k.alloc(nq);
-    NURI_HIP(hipMemcpyAsync(d_res.p, h_res.data(), nq * sizeof(QRes), hipMemcpyHostToDevice, s));
+    NURI_HIP(hipMemcpyAsync(d_res.p, h_res.p, nq * sizeof(QRes), hipMemcpyHostToDevice, s));
     NURI_HIP(hipMemcpyAsync(d_k.p, ks.data(), nq * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     NURI_HIP(hipMemsetAsync(d_ctr.p, 0, nq * sizeof(QCtr), s));
+    h_ctr.assign(nq, QCtr{});
     // per-step limits
     B = o.batch_B ? o.batch_B : 16384;
     root_B = o.root_batch ? o.root_batch : 8192;
@@ -927,38 +856,38 @@ struct Engine {
     leaf_word_cap = step_words;
     leaves.alloc(leaf_cap);
     leaf_words.alloc(leaf_word_cap);
-    counters.alloc(4);
-    leaf_word_count.alloc(1);
     cands.alloc(kCandChunk);
     cand_ids.alloc((u64)kCandChunk * lmax);
-    d_seg.alloc(nq);
-    d_rseg.alloc(nq);
     d_hist.alloc((u64)nq * kBins);
     d_hchild.alloc((u64)nq * kBins);
-    d_hword.alloc((u64)nq * kBins);
-    d_hmaxc.alloc((u64)nq * kBins);
-    d_hmaxw.alloc((u64)nq * kBins);
-    d_thr.alloc(nq);
-    d_quota.alloc(nq);
-    d_taken.alloc(nq);
-    d_tempc.alloc(nq);
+    NURI_HIP(hipMemsetAsync(d_hist.p, 0, d_hist.bytes(), s));
+    NURI_HIP(hipMemsetAsync(d_hchild.p, 0, d_hchild.bytes(), s));
+    d_step.alloc(L->total);
+    h_step.alloc(L->total);
     if (o.profile) {
       NURI_HIP(hipEventCreate(&ev0));
       NURI_HIP(hipEventCreate(&ev1));
     }
   }
 
-  // largest possible output of one record: d * (header + W words)
+  // largest possible output of one record
   u64 max_rec_children() const { return g.degeneracy; }
   u64 max_rec_words() const { return (u64)g.degeneracy * 2 * ((g.degeneracy + 63) / 64); }
 
-  // plan this step for every live query; returns false if nothing to do
-  bool plan(std::vector<SelSeg> &segs, std::vector<RootSeg> &rsegs, uint32_t &batch_ub,
-            u64 &temp_need) {
-    segs.clear();
-    rsegs.clear();
+  // plan this step for every live query into the staging block; returns
+  // false when every query is done
+  bool plan(uint32_t &nseg, uint32_t &nrseg, uint32_t &batch_ub, u64 &temp_need,
+            uint32_t &max_seg_count, uint32_t &max_rseg_count) {
+    nseg = nrseg = 0;
     batch_ub = 0;
     temp_need = 0;
+    max_seg_count = max_rseg_count = 0;
+    uint32_t live = 0;
+    for (auto &Q : qh) live += !Q.done;
+    if (!live) return false;
+    // each live query may use an equal share of this step's output limits
+    const u64 share_c = std::max<u64>(step_children / live, max_rec_children());
+    const u64 share_w = std::max<u64>(step_words / live, max_rec_words());
     u64 left_c = step_children, left_w = step_words;
     bool any = false;
     for (uint32_t i = 0; i < nq; ++i) {
@@ -967,23 +896,22 @@ struct Engine {
       Q.sel_seg = -1;
       if (Q.done) continue;
       while (!Q.stack.empty() && Q.stack.back().count == 0) Q.stack.pop_back();
+      const u64 cap_c = std::min(left_c, share_c), cap_w = std::min(left_w, share_w);
       if (Q.stack.empty()) {
         // unit subgraphs: the next roots in bound order with bound >= theta
         const auto &rb = g.h_root_bound[Q.kind];
         const auto &ro = g.h_root_order[Q.kind];
         u64 end = g.n;
-        if (Q.theta != LLONG_MIN) {
-          // first position with bound < theta (bounds are non-increasing)
+        if (Q.theta != LLONG_MIN)
           end = std::lower_bound(rb.begin(), rb.end(), Q.theta,
                                  [](long long a, long long t) { return a >= t; }) -
                 rb.begin();
-        }
         if (Q.cursor >= end) {
           Q.done = true;
           continue;
         }
         u64 cc = 0, cw = 0, cnt = 0;
-        u64 lim_c = std::min<u64>(left_c, Q.hdr_cap), lim_w = std::min<u64>(left_w, Q.word_cap);
+        const u64 lim_c = std::min<u64>(cap_c, Q.hdr_cap), lim_w = std::min<u64>(cap_w, Q.word_cap);
         while (Q.cursor + cnt < end && cnt < root_B && batch_ub + cnt < batch_cap) {
           uint32_t r = ro[Q.cursor + cnt];
           u64 d = g.h_dplus[r];
@@ -993,145 +921,135 @@ struct Engine {
           cw += w;
           ++cnt;
         }
-        if (cc > lim_c || cw > lim_w)
+        if (cc > Q.hdr_cap || cw > Q.word_cap)
           throw Error{NURI_EBUDGET, "frontier budget too small for one unit subgraph"};
         if (cnt == 0) continue;
-        RootSeg rs;
+        RootSeg &rs = srseg()[nrseg++];
         rs.qid = i;
         rs.kind = Q.kind;
         rs.first = (uint32_t)Q.cursor;
         rs.count = (uint32_t)cnt;
-        rsegs.push_back(rs);
+        max_rseg_count = std::max(max_rseg_count, rs.count);
         Q.cursor += cnt;
         Q.plan = 1;
         Q.new_begin = 0;
         Q.new_wbegin = 0;
         batch_ub += (uint32_t)cnt;
-        left_c -= cc;
-        left_w -= cw;
+        left_c -= std::min(left_c, cc);
+        left_w -= std::min(left_w, cw);
         any = true;
         continue;
       }
-      Level &L = Q.stack.back();
-      u64 free_h = Q.hdr_cap - (u64)(L.begin + L.count);
-      u64 free_w = Q.word_cap - L.wend;
-      u64 lim_c = std::min<u64>(left_c, free_h), lim_w = std::min<u64>(left_w, free_w);
-      if (lim_c < max_rec_children() || lim_w < max_rec_words()) {
-        if (left_c < step_children || left_w < step_words) continue;  // retry next step
-        throw Error{NURI_EBUDGET, "frontier budget exhausted"};
-      }
-      uint32_t room = batch_cap - batch_ub;
+      Level &Lv = Q.stack.back();
+      const u64 free_h = Q.hdr_cap - (u64)(Lv.begin + Lv.count);
+      const u64 free_w = Q.word_cap - Lv.wend;
+      const u64 lim_c = std::min<u64>(cap_c, free_h), lim_w = std::min<u64>(cap_w, free_w);
+      // one record of this level must always fit
+      const u64 rec_c = std::max<u64>(1, Lv.maxcc), rec_w = rec_c * 2 * std::max(1u, Lv.maxw);
+      if (free_h < rec_c || free_w < rec_w) throw Error{NURI_EBUDGET, "frontier budget exhausted"};
+      if (lim_c < rec_c || lim_w < rec_w) continue;  // next step
+      const uint32_t room = batch_cap - batch_ub;
       if (room == 0) continue;
-      SelSeg sg{};
+      SelSeg &sg = sseg()[nseg];
+      sg = SelSeg{};
       sg.qid = i;
-      sg.begin = L.begin;
-      sg.count = L.count;
+      sg.begin = Lv.begin;
+      sg.count = Lv.count;
       sg.max_records = std::min<u64>(B, room);
       sg.max_children = lim_c;
       sg.max_words = lim_w;
-      sg.take_all = L.count <= sg.max_records && L.cost_children <= lim_c && L.cost_words <= lim_w;
-      sg.top = L.max_bound;
-      long long floor_b = Q.theta == LLONG_MIN ? 0 : Q.theta;
-      long long span = L.max_bound - floor_b;
+      sg.take_all =
+          Lv.count <= sg.max_records && Lv.cost_children <= lim_c && Lv.cost_words <= lim_w;
+      sg.top = Lv.max_bound;
+      sg.maxcc = Lv.maxcc;
+      sg.wpc = 2ull * Lv.maxw;
+      const long long floor_b = Q.theta == LLONG_MIN ? 0 : Q.theta;
+      const long long span = Lv.max_bound - floor_b;
       uint32_t shift = 0;
       while (span > 0 && (span >> shift) >= kBins - 1) ++shift;
       sg.shift = shift;
       sg.temp_off = (uint32_t)temp_need;
-      if (!sg.take_all) temp_need += L.count;
-      Q.sel_seg = (int)segs.size();
-      segs.push_back(sg);
+      if (!sg.take_all) temp_need += Lv.count;
+      max_seg_count = std::max(max_seg_count, Lv.count);
+      Q.sel_seg = (int)nseg++;
       Q.plan = 2;
-      Q.new_begin = L.begin + L.count;
-      Q.new_wbegin = L.wend;
-      u64 take = sg.take_all ? L.count : sg.max_records;
-      batch_ub += (uint32_t)take;
-      u64 uc = sg.take_all ? L.cost_children : lim_c;
-      u64 uw = sg.take_all ? L.cost_words : lim_w;
+      Q.new_begin = Lv.begin + Lv.count;
+      Q.new_wbegin = Lv.wend;
+      batch_ub += (uint32_t)(sg.take_all ? Lv.count : sg.max_records);
+      const u64 uc = sg.take_all ? Lv.cost_children : lim_c;
+      const u64 uw = sg.take_all ? Lv.cost_words : lim_w;
       left_c -= std::min(left_c, uc);
       left_w -= std::min(left_w, uw);
       any = true;
     }
+    if (!any) {
+      // every live query waits on budget that only it can free: cannot happen
+      // unless the per-query budget is below one record's output
+      for (auto &Q : qh)
+        if (!Q.done) throw Error{NURI_EBUDGET, "frontier budget too small to make progress"};
+    }
     return any;
   }
 
-  void step(const std::vector<SelSeg> &segs, const std::vector<RootSeg> &rsegs, uint32_t batch_ub,
-            u64 temp_need) {
+  void step(uint32_t nseg, uint32_t nrseg, uint32_t batch_ub, u64 temp_need,
+            uint32_t max_seg_count, uint32_t max_rseg_count) {
     GView gv = view();
+    // counters start at zero; configuration for this step
+    memset(h_step.p, 0, L->cfg);
     for (uint32_t i = 0; i < nq; ++i) {
-      h_cfg[i].out_hdr = qh[i].new_begin;
-      h_cfg[i].out_word = qh[i].new_wbegin;
+      cfg[i].out_hdr = qh[i].new_begin;
+      cfg[i].out_word = qh[i].new_wbegin;
+      sq()[i].out_max_bound = LLONG_MIN;
     }
-    NURI_HIP(hipMemcpyAsync(d_cfg.p, h_cfg.data(), nq * sizeof(QCfg), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_reset_step, dim3((nq + 255) / 256), dim3(256), 0, s, d_ctr.p, nq);
-    NURI_HIP(hipGetLastError());
-    NURI_HIP(hipMemsetAsync(counters.p, 0, 4 * sizeof(unsigned int), s));
-    NURI_HIP(hipMemsetAsync(leaf_word_count.p, 0, sizeof(u64), s));
-    if (!rsegs.empty()) {
-      NURI_HIP(hipMemcpyAsync(d_rseg.p, rsegs.data(), rsegs.size() * sizeof(RootSeg),
-                              hipMemcpyHostToDevice, s));
-      uint32_t mx = 0;
-      for (auto &r : rsegs) mx = std::max(mx, r.count);
-      uint32_t blocks = std::min<uint32_t>((mx + 255) / 256, 4096);
-      hipLaunchKernelGGL(k_make_roots, dim3(std::max(1u, blocks)), dim3(256), 0, s, gv,
-                         d_rseg.p, (uint32_t)rsegs.size(), batch.p, counters.p);
+    memcpy(h_step.p + L->cfg, cfg.data(), nq * sizeof(QCfg));
+    memset(h_step.p + L->taken, 0, 8ull * nq);  // taken, tempc
+    NURI_HIP(hipMemcpyAsync(d_step.p, h_step.p, L->total, hipMemcpyHostToDevice, s));
+    StepHdr *dh = dev<StepHdr>(0);
+    QStep *dqs = dev<QStep>(L->qs);
+    QCfg *dcfg = dev<QCfg>(L->cfg);
+    SelSeg *dseg = dev<SelSeg>(L->seg);
+    if (nrseg) {
+      uint32_t bx = std::min<uint32_t>((max_rseg_count + 255) / 256, 1024);
+      hipLaunchKernelGGL(k_make_roots, dim3(std::max(1u, bx), nrseg), dim3(256), 0, s, gv,
+                         dev<RootSeg>(L->rseg), batch.p, dh);
       NURI_HIP(hipGetLastError());
     }
-    if (!segs.empty()) {
-      uint32_t ns = (uint32_t)segs.size();
-      NURI_HIP(hipMemcpyAsync(d_seg.p, segs.data(), ns * sizeof(SelSeg), hipMemcpyHostToDevice, s));
-      std::vector<uint32_t> bs, bo;
+    if (nseg) {
       bool any_sel = false;
-      for (uint32_t i = 0; i < ns; ++i) {
-        for (uint32_t off = 0; off < segs[i].count; off += 256) {
-          bs.push_back(i);
-          bo.push_back(off);
-        }
-        any_sel |= !segs[i].take_all;
-      }
-      if (d_blk_seg.n < bs.size()) {
-        d_blk_seg.alloc(bs.size() * 2);
-        d_blk_off.alloc(bs.size() * 2);
-      }
-      NURI_HIP(hipMemcpyAsync(d_blk_seg.p, bs.data(), bs.size() * 4, hipMemcpyHostToDevice, s));
-      NURI_HIP(hipMemcpyAsync(d_blk_off.p, bo.data(), bo.size() * 4, hipMemcpyHostToDevice, s));
+      for (uint32_t i = 0; i < nseg; ++i) any_sel |= !sseg()[i].take_all;
       if (temp_need && temp.n < temp_need) temp.alloc(temp_need * 2);
-      NURI_HIP(hipMemsetAsync(d_taken.p, 0, ns * 4, s));
-      NURI_HIP(hipMemsetAsync(d_tempc.p, 0, ns * 4, s));
+      uint32_t bx = std::min<uint32_t>((max_seg_count + 255) / 256, 2048);
+      bx = std::max(1u, bx);
       if (any_sel) {
-        NURI_HIP(hipMemsetAsync(d_hist.p, 0, (u64)ns * kBins * 4, s));
-        NURI_HIP(hipMemsetAsync(d_hchild.p, 0, (u64)ns * kBins * 8, s));
-        NURI_HIP(hipMemsetAsync(d_hword.p, 0, (u64)ns * kBins * 8, s));
-        NURI_HIP(hipMemsetAsync(d_hmaxc.p, 0, (u64)ns * kBins * 8, s));
-        NURI_HIP(hipMemsetAsync(d_hmaxw.p, 0, (u64)ns * kBins * 8, s));
-        hipLaunchKernelGGL(k_sel_hist, dim3((uint32_t)bs.size()), dim3(256), 0, s, gv, d_seg.p,
-                           d_blk_seg.p, d_blk_off.p, d_cfg.p, d_res.p, d_hist.p, d_hchild.p,
-                           d_hword.p, d_hmaxc.p, d_hmaxw.p);
+        hipLaunchKernelGGL(k_sel_hist, dim3(std::min(bx, 512u), nseg), dim3(256), 0, s, gv, dseg,
+                           dcfg, d_res.p, d_hist.p, d_hchild.p);
         NURI_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_sel_thresh, dim3(ns), dim3(64), 0, s, d_seg.p, ns, d_hist.p,
-                           d_hchild.p, d_hword.p, d_hmaxc.p, d_hmaxw.p, d_thr.p, d_quota.p);
+        hipLaunchKernelGGL(k_sel_thresh, dim3(nseg), dim3(256), 0, s, dseg, nseg, d_hist.p,
+                           d_hchild.p, dev<int>(L->thr), dev<unsigned int>(L->quota));
         NURI_HIP(hipGetLastError());
       }
-      hipLaunchKernelGGL(k_sel_part, dim3((uint32_t)bs.size()), dim3(256), 0, s, gv, d_seg.p,
-                         d_blk_seg.p, d_blk_off.p, d_cfg.p, d_res.p, d_thr.p, d_quota.p,
-                         d_taken.p, batch.p, counters.p, temp.p, d_tempc.p, d_ctr.p);
+      hipLaunchKernelGGL(k_sel_part, dim3(bx, nseg), dim3(256), 0, s, dseg, dcfg, d_res.p,
+                         dev<int>(L->thr), dev<unsigned int>(L->quota),
+                         dev<unsigned int>(L->taken), batch.p, dh, temp.p,
+                         dev<unsigned int>(L->tempc), d_ctr.p);
       NURI_HIP(hipGetLastError());
-      hipLaunchKernelGGL(k_copy_back, dim3(1024), dim3(256), 0, s, d_seg.p, ns, d_cfg.p, temp.p,
-                         d_tempc.p, d_ctr.p);
-      NURI_HIP(hipGetLastError());
+      if (any_sel) {
+        hipLaunchKernelGGL(k_copy_back, dim3(bx, nseg), dim3(256), 0, s, dseg, dcfg, temp.p,
+                           dev<unsigned int>(L->tempc), dqs);
+        NURI_HIP(hipGetLastError());
+      }
     }
     if (batch_ub) {
       if (o.profile) NURI_HIP(hipEventRecord(ev0, s));
       uint32_t blocks = (batch_ub + kExpandWaves - 1) / kExpandWaves;
-      hipLaunchKernelGGL(k_expand, dim3(blocks), dim3(64 * kExpandWaves), 0, s, gv, batch.p,
-                         counters.p, d_cfg.p, d_ctr.p, d_res.p, leaves.p, counters.p + 1,
-                         leaf_words.p, leaf_word_count.p, leaf_cap, leaf_word_cap);
+      hipLaunchKernelGGL(k_expand, dim3(blocks), dim3(64 * kExpandWaves), 0, s, gv, batch.p, dh,
+                         dcfg, dqs, d_ctr.p, d_res.p, leaves.p, leaf_words.p, leaf_cap,
+                         leaf_word_cap);
       NURI_HIP(hipGetLastError());
       if (o.profile) NURI_HIP(hipEventRecord(ev1, s));
       launches++;
     }
-    unsigned int hc[4];
-    NURI_HIP(hipMemcpyAsync(h_ctr.data(), d_ctr.p, nq * sizeof(QCtr), hipMemcpyDeviceToHost, s));
-    NURI_HIP(hipMemcpyAsync(hc, counters.p, sizeof(hc), hipMemcpyDeviceToHost, s));
+    NURI_HIP(hipMemcpyAsync(h_step.p, d_step.p, L->readback(), hipMemcpyDeviceToHost, s));
     NURI_HIP(hipStreamSynchronize(s));
     if (o.profile && batch_ub) {
       float ms = 0;
@@ -1143,17 +1061,11 @@ struct Engine {
     u64 live = 0;
     for (uint32_t i = 0; i < nq; ++i) {
       QHost &Q = qh[i];
-      const QCtr &c = h_ctr[i];
-      if (c.overflow)
-        throw Error{NURI_EBUDGET, "frontier overflow (internal accounting error)"};
+      const QStep &c = sq()[i];
+      if (c.overflow) throw Error{NURI_EBUDGET, "frontier overflow (internal accounting error)"};
       if (Q.plan == 2) {
-        Level &L = Q.stack.back();
-        const SelSeg &sg = segs[Q.sel_seg];
-        if (sg.take_all) {
-          L.count = 0;
-        } else {
-          L.count = c.n_kept;
-        }
+        Level &Lv = Q.stack.back();
+        Lv.count = sseg()[Q.sel_seg].take_all ? 0 : c.n_kept;
       }
       if (Q.plan && c.n_out) {
         Level N;
@@ -1164,6 +1076,8 @@ struct Engine {
         N.cost_children = c.out_cost_children;
         N.cost_words = c.out_cost_words;
         N.max_bound = c.out_max_bound;
+        N.maxcc = c.out_max_cc;
+        N.maxw = c.out_max_w;
         Q.stack.push_back(N);
       }
       if (!Q.stack.empty()) {
@@ -1173,48 +1087,52 @@ struct Engine {
     }
     peak_bytes = std::max<uint64_t>(peak_bytes, live);
     // leaves -> maximality check -> merge, in chunks
-    uint32_t nleaf = hc[1];
+    const uint32_t nleaf = sh()->leaf_count;
     if (nleaf > leaf_cap) throw Error{NURI_EBUDGET, "leaf buffer overflow (internal)"};
-    for (uint32_t f = 0; f < nleaf; f += kCandChunk) {
-      uint32_t cnt = std::min<uint32_t>(kCandChunk, nleaf - f);
-      NURI_HIP(hipMemsetAsync(counters.p + 2, 0, sizeof(unsigned int), s));
-      hipLaunchKernelGGL(k_leaf_check, dim3(cnt), dim3(64), 0, s, gv, leaves.p, f,
-                         leaf_words.p, d_res.p, cands.p, counters.p + 2, cand_ids.p, lmax,
-                         d_ctr.p);
-      NURI_HIP(hipGetLastError());
-      hipLaunchKernelGGL(k_merge, dim3(nq), dim3(1024), 0, s, cands.p, counters.p + 2,
-                         cand_ids.p, lmax, d_res.p, d_k.p);
-      NURI_HIP(hipGetLastError());
-    }
     if (nleaf) {
-      NURI_HIP(hipMemcpyAsync(h_res.data(), d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
+      uint32_t kmax = 0;
+      for (auto &Q : qh) kmax = std::max(kmax, Q.k);
+      const uint32_t mx = (kmax + kCandChunk + 255) / 256;
+      for (uint32_t f = 0; f < nleaf; f += kCandChunk) {
+        const uint32_t cnt = std::min<uint32_t>(kCandChunk, nleaf - f);
+        NURI_HIP(hipMemsetAsync(&dh->cand_count, 0, sizeof(unsigned int), s));
+        hipLaunchKernelGGL(k_leaf_check, dim3(cnt), dim3(64), 0, s, gv, leaves.p, f,
+                           leaf_words.p, d_res.p, cands.p, &dh->cand_count, cand_ids.p, lmax,
+                           d_ctr.p);
+        NURI_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_merge_rank, dim3(mx, nq), dim3(256), 0, s, cands.p, dh, cand_ids.p,
+                           lmax, d_res.p, d_k.p);
+        NURI_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_merge_finish, dim3(nq), dim3(256), 0, s, cands.p, dh, d_res.p,
+                           d_k.p);
+        NURI_HIP(hipGetLastError());
+      }
+      NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
       NURI_HIP(hipStreamSynchronize(s));
-      for (uint32_t i = 0; i < nq; ++i) qh[i].theta = h_res[i].theta;
+      for (uint32_t i = 0; i < nq; ++i) qh[i].theta = h_res.p[i].theta;
     }
   }
 
   void run() {
-    std::vector<SelSeg> segs;
-    std::vector<RootSeg> rsegs;
-    uint32_t batch_ub;
+    uint32_t nseg, nrseg, batch_ub, mseg, mrseg;
     u64 temp_need;
-    uint64_t t0 = now_ns();
-    while (plan(segs, rsegs, batch_ub, temp_need)) {
+    const uint64_t t0 = now_ns();
+    while (plan(nseg, nrseg, batch_ub, temp_need, mseg, mrseg)) {
       if (o.deadline_ns && now_ns() - t0 > o.deadline_ns)
         throw Error{NURI_ETIMEOUT, "query deadline passed"};
-      step(segs, rsegs, batch_ub, temp_need);
+      step(nseg, nrseg, batch_ub, temp_need, mseg, mrseg);
     }
   }
 
   void collect(std::vector<Result> &out, uint64_t wall) {
-    NURI_HIP(hipMemcpyAsync(h_res.data(), d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
+    NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
     NURI_HIP(hipMemcpyAsync(h_ctr.data(), d_ctr.p, nq * sizeof(QCtr), hipMemcpyDeviceToHost, s));
     NURI_HIP(hipStreamSynchronize(s));
     out.resize(nq);
     for (uint32_t i = 0; i < nq; ++i) {
-      const QRes &R = h_res[i];
+      const QRes &R = h_res.p[i];
       Result &res = out[i];
-      uint32_t n = R.tk_n;
+      const uint32_t n = R.tk_n;
       std::vector<long long> sc(n);
       std::vector<unsigned int> ln(n), ids((u64)n * lmax);
       if (n) {
@@ -1256,7 +1174,8 @@ struct Engine {
 
 void run_cliques(Graph &g, const std::vector<uint32_t> &ks, const std::vector<int> &kinds,
                  const QueryOpts &o, std::vector<Result> &out) {
-  uint64_t t0 = now_ns();
+  const uint64_t t0 = now_ns();
+  if (ks.empty()) return;
   if (ks.size() > 65535) throw Error{NURI_EINVAL, "at most 65535 queries per batch"};
   for (size_t i = 0; i < ks.size(); ++i) {
     if (ks[i] == 0) throw Error{NURI_EINVAL, "k must be >= 1"};

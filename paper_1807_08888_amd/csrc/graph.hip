@@ -177,7 +177,8 @@ __global__ void __launch_bounds__(256) k_build_bitmaps(
 
 uint64_t Graph::device_bytes() const {
   return rrow.bytes() + rcol.bytes() + split.bytes() + dplus.bytes() + orig.bytes() + vw.bytes() +
-         lab.bytes() + ew.bytes() + bm_off.bytes() + bm.bytes() + wplus.bytes() + best.bytes() +
+         bm_off.bytes() + bm.bytes() + wplus.bytes() + best.bytes() +
+         orow.bytes() + lcol.bytes() + lew.bytes() + loff.bytes() + lab_vert.bytes() +
          root_order[0].bytes() + root_order[1].bytes() + ooff.bytes() + oplus.bytes() +
          wloc.bytes();
 }
@@ -222,22 +223,19 @@ Graph *load_graph(const nuri_csr *csr, hipStream_t stream) {
     rrow[r + 1] = rrow[r] + (c.row_ptr[v + 1] - c.row_ptr[v]);
   }
   std::vector<uint32_t> rcol(c.nnz), split(n), dplus(n);
-  std::vector<int32_t> ew(c.edge_weight ? c.nnz : 0);
   parallel_chunks(n, [&](uint64_t b, uint64_t e) {
-    std::vector<std::pair<uint32_t, int32_t>> tmp;
+    std::vector<uint32_t> tmp;
     for (uint64_t r = b; r < e; ++r) {
       uint32_t v = g.h_orig[r];
       uint64_t k0 = c.row_ptr[v], k1 = c.row_ptr[v + 1];
       tmp.clear();
-      for (uint64_t k = k0; k < k1; ++k)
-        tmp.emplace_back(g.h_rank[c.col_idx[k]], c.edge_weight ? c.edge_weight[k] : 1);
+      for (uint64_t k = k0; k < k1; ++k) tmp.push_back(g.h_rank[c.col_idx[k]]);
       std::sort(tmp.begin(), tmp.end());
       uint64_t o = rrow[r];
       uint32_t s = 0;
       for (size_t i = 0; i < tmp.size(); ++i) {
-        rcol[o + i] = tmp[i].first;
-        if (c.edge_weight) ew[o + i] = tmp[i].second;
-        if (tmp[i].first < r) ++s;
+        rcol[o + i] = tmp[i];
+        if (tmp[i] < r) ++s;
       }
       split[r] = s;
       dplus[r] = (uint32_t)tmp.size() - s;
@@ -273,28 +271,56 @@ Graph *load_graph(const nuri_csr *csr, hipStream_t stream) {
     }
     wplus[r] = s;
   }
-  std::vector<uint8_t> labr(c.vertex_label ? n : 0);
   g.h_label_count.assign(NURI_MAX_LABELS, 0);
-  if (c.vertex_label) {
-    for (uint32_t r = 0; r < n; ++r) {
-      labr[r] = c.vertex_label[g.h_orig[r]];
-      g.h_label_count[labr[r]]++;
-    }
-  }
-  // 1-hop index: best[r][l] = max weight of an edge from r to a label-l
-  // vertex; pairmax[l1][l2] = max weight over edges with that label pair
+  if (c.vertex_label)
+    for (uint32_t v = 0; v < n; ++v) g.h_label_count[c.vertex_label[v]]++;
+  // 1-hop index for matching (the one-hop form of the per-vertex index of
+  // Section 4.3, Listing 3): best[v][l] = max weight of an edge from v to a
+  // label-l vertex; pairmax[l1][l2] = max weight over edges with that label
+  // pair.  Rows re-sorted by (label, id) give each label's neighbours as
+  // one sorted segment.
   std::vector<int32_t> best(c.vertex_label ? (size_t)n * NURI_MAX_LABELS : 0, 0);
+  std::vector<uint32_t> lcol(c.vertex_label ? c.nnz : 0), loff(c.vertex_label ? (size_t)n * 17 : 0);
+  std::vector<int32_t> lew(c.vertex_label ? c.nnz : 0);
+  std::vector<uint32_t> lab_vert;
   g.h_pairmax.assign(NURI_MAX_LABELS * NURI_MAX_LABELS, 0);
+  g.h_lab_off.assign(NURI_MAX_LABELS + 1, 0);
   if (c.vertex_label) {
-    for (uint32_t r = 0; r < n; ++r)
-      for (uint64_t k = rrow[r]; k < rrow[r + 1]; ++k) {
-        uint32_t u = rcol[k];
-        int32_t w = c.edge_weight ? ew[k] : 1;
-        int32_t &b = best[(size_t)r * NURI_MAX_LABELS + labr[u]];
-        if (w > b) b = w;
-        int32_t &pm = g.h_pairmax[labr[r] * NURI_MAX_LABELS + labr[u]];
+    const uint8_t *L = c.vertex_label;
+    parallel_chunks(n, [&](uint64_t b, uint64_t e) {
+      std::vector<std::pair<uint64_t, int32_t>> tmp;
+      for (uint64_t v = b; v < e; ++v) {
+        uint64_t k0 = c.row_ptr[v], k1 = c.row_ptr[v + 1];
+        tmp.clear();
+        for (uint64_t k = k0; k < k1; ++k) {
+          uint32_t u = c.col_idx[k];
+          tmp.emplace_back(((uint64_t)L[u] << 32) | u, c.edge_weight ? c.edge_weight[k] : 1);
+        }
+        std::sort(tmp.begin(), tmp.end());
+        uint32_t *lo = &loff[v * 17];
+        for (int l = 0; l <= NURI_MAX_LABELS; ++l) lo[l] = 0;
+        for (size_t i = 0; i < tmp.size(); ++i) {
+          uint32_t u = (uint32_t)tmp[i].first, lu = (uint32_t)(tmp[i].first >> 32);
+          lcol[k0 + i] = u;
+          lew[k0 + i] = tmp[i].second;
+          lo[lu + 1]++;
+          int32_t &bb = best[v * NURI_MAX_LABELS + lu];
+          if (tmp[i].second > bb) bb = tmp[i].second;
+        }
+        for (int l = 0; l < NURI_MAX_LABELS; ++l) lo[l + 1] += lo[l];
+      }
+    });
+    for (uint32_t v = 0; v < n; ++v)
+      for (int l = 0; l < NURI_MAX_LABELS; ++l) {
+        int32_t w = best[(size_t)v * NURI_MAX_LABELS + l];
+        int32_t &pm = g.h_pairmax[L[v] * NURI_MAX_LABELS + l];
         if (w > pm) pm = w;
       }
+    for (uint32_t v = 0; v < n; ++v) g.h_lab_off[L[v] + 1]++;
+    for (int l = 0; l < NURI_MAX_LABELS; ++l) g.h_lab_off[l + 1] += g.h_lab_off[l];
+    lab_vert.resize(n);
+    std::vector<uint64_t> fill(g.h_lab_off.begin(), g.h_lab_off.end() - 1);
+    for (uint32_t v = 0; v < n; ++v) lab_vert[fill[L[v]]++] = v;
   }
   // root orders by bound, descending (ties: smaller rank first)
   for (int kind = 0; kind < 2; ++kind) {
@@ -317,14 +343,19 @@ Graph *load_graph(const nuri_csr *csr, hipStream_t stream) {
   upload(g.dplus, dplus.data(), n, s);
   upload(g.orig, g.h_orig.data(), n, s);
   upload(g.vw, vwr.data(), n, s);
-  upload(g.lab, labr.data(), labr.size(), s);
-  upload(g.ew, ew.data(), ew.size(), s);
   upload(g.bm_off, bm_off.data(), n + 1, s);
   upload(g.wplus, wplus.data(), n, s);
   upload(g.ooff, ooff.data(), n + 1, s);
   upload(g.oplus, oplus.data(), oplus.size(), s);
   upload(g.wloc, wloc.data(), wloc.size(), s);
-  upload(g.best, best.data(), best.size(), s);
+  if (c.vertex_label) {
+    upload(g.orow, c.row_ptr, (size_t)n + 1, s);
+    upload(g.lcol, lcol.data(), lcol.size(), s);
+    upload(g.lew, lew.data(), lew.size(), s);
+    upload(g.loff, loff.data(), loff.size(), s);
+    upload(g.best, best.data(), best.size(), s);
+    upload(g.lab_vert, lab_vert.data(), lab_vert.size(), s);
+  }
   for (int kind = 0; kind < 2; ++kind)
     upload(g.root_order[kind], g.h_root_order[kind].data(), n, s);
   g.bm.alloc(g.bitmap_words);

@@ -1,12 +1,1006 @@
-// Top-k labelled subgraph matching on the GPU (placeholder until the
-// matching kernels land).
-#include "nuri_internal.h"
+// Top-k labelled subgraph matching on the GPU.
+//
+// The paper's basic computational model (Algorithm 1, Section 3.2) with the
+// subgraph-isomorphism user functions of Section 4.3, scored by the sum of
+// matched edge weights:
+//
+//   targeted expansion  a partial match grows by one pattern vertex at a
+//                       time (in a fixed matching order), taking only data
+//                       vertices with the right label that are adjacent to
+//                       every already-matched pattern neighbour (Ullmann-
+//                       style refinement) and distinct from the matched ones;
+//   bound               score + an upper bound for every pattern edge not yet
+//                       matched, from a one-hop index (the Section 4.3 index
+//                       at hop 1): max edge weight from a matched vertex to
+//                       a label, or from any vertex of one label to another;
+//   priority            (matched vertices, bound): the deepest level first,
+//                       highest bound first within it;
+//   dominated           bound < score of the k-th result (strict).
+//
+// Matches are non-induced.  Embeddings with the same image are one result:
+// symmetry-breaking constraints mu(i) < mu(j), for j in the orbit of i under
+// the automorphisms fixing 0..i-1, keep exactly the lexicographically
+// smallest tuple of each orbit.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <numeric>
+
+#include "device_common.h"
 
 namespace nuri {
+namespace {
 
-void run_matches(Graph &, const std::vector<const nuri_pattern *> &,
-                 const std::vector<uint32_t> &, const QueryOpts &, std::vector<Result> &) {
-  throw Error{NURI_EINVAL, "labelled matching is not available in this build"};
+constexpr int QM = NURI_MAX_PATTERN;
+
+struct MRec {  // 64 B partial match
+  long long score;
+  long long bound;
+  uint32_t mu[QM];    // data vertex (original id) per pattern vertex; valid if matched
+  uint32_t qid;
+  uint32_t depth;     // matched vertices: order[0..depth-1]
+  uint32_t nchild;    // upper bound on its children (smallest anchor segment)
+  uint32_t pad;
+};
+static_assert(sizeof(MRec) == 64, "match record must stay 64 bytes");
+
+struct MPlan {  // per query pattern plan
+  uint32_t q, k;
+  uint8_t label[QM];
+  uint8_t order[QM];  // matching order
+  uint8_t pos[QM];    // position of each pattern vertex in the order
+  uint8_t nbr[QM];    // pattern adjacency bitmasks
+  uint8_t sb_lt[QM];  // sb_lt[a] bit b: a result needs mu(a) < mu(b)
+  int32_t pmx[QM][QM];  // max data edge weight for the label pair of pattern edge {a,b}
+  long long rest0;    // bound contribution of edges not touching order[0], all unmatched
+};
+
+struct MView {
+  const uint64_t *orow;
+  const uint32_t *lcol;
+  const int32_t *lew;
+  const uint32_t *loff;
+  const int32_t *best;
+  const uint32_t *lab_vert;
+};
+
+struct MCfg {  // per query, per step
+  MRec *hdr;
+  uint32_t out_hdr, hdr_cap;
+};
+
+struct MStep {  // per query, this step's counters
+  unsigned int n_out, n_kept, overflow, pad;
+  u64 out_cost;        // sum of nchild over appended records
+  long long out_max_bound;
+  u64 out_max_cost;
+};
+
+struct MCtr {
+  u64 popped, expanded, children, pruned_pop, pruned_new, leaves, offered, logical_bytes;
+};
+
+struct MSeg {
+  uint32_t qid, begin, count, take_all;
+  uint32_t shift, temp_off;
+  long long top;
+  u64 max_records, max_children, maxcost;
+};
+
+__device__ inline uint32_t seg_len(const MView &m, uint32_t v, uint32_t l) {
+  const uint32_t *lo = m.loff + (u64)v * 17;
+  return lo[l + 1] - lo[l];
+}
+
+// index of x in the label-l segment of row v, or -1
+__device__ inline long long seg_find(const MView &m, uint32_t v, uint32_t l, uint32_t x) {
+  const uint32_t *lo = m.loff + (u64)v * 17;
+  u64 a = m.orow[v] + lo[l], z = m.orow[v] + lo[l + 1];
+  while (a < z) {
+    u64 mid = (a + z) >> 1;
+    if (m.lcol[mid] < x) a = mid + 1; else z = mid;
+  }
+  return (a < m.orow[v] + lo[l + 1] && m.lcol[a] == x) ? (long long)a : -1ll;
+}
+
+// upper bound on the children of a record whose next pattern vertex is a
+__device__ inline uint32_t child_bound(const MView &m, const MPlan &P, const MRec &r) {
+  if (r.depth >= P.q) return 0;
+  const uint32_t a = P.order[r.depth];
+  uint32_t best = 0xFFFFFFFFu;
+  for (uint32_t i = 0; i < r.depth; ++i) {
+    const uint32_t b = P.order[i];
+    if (P.nbr[a] >> b & 1) {
+      uint32_t s = seg_len(m, r.mu[b], P.label[a]);
+      best = s < best ? s : best;
+    }
+  }
+  return best == 0xFFFFFFFFu ? 0 : best;
+}
+
+// ------------------------------------------------------------------
+// unit subgraphs: every vertex with the label of order[0] (lines 1-3)
+// grid: (x, query)
+// ------------------------------------------------------------------
+__global__ void k_match_roots(MView m, const MPlan *plans, const uint64_t *lab_off, MCfg *cfg,
+                              MStep *ms) {
+  const uint32_t q = blockIdx.y;
+  const MPlan &P = plans[q];
+  const uint32_t a0 = P.order[0];
+  const uint32_t l0 = P.label[a0];
+  const u64 b = lab_off[l0], e = lab_off[l0 + 1];
+  for (u64 i = b + blockIdx.x * (u64)blockDim.x + threadIdx.x; i < e;
+       i += (u64)gridDim.x * blockDim.x) {
+    const uint32_t v = m.lab_vert[i];
+    long long bound = P.rest0;
+    bool ok = true;
+    for (uint32_t u = 0; u < P.q; ++u)
+      if (P.nbr[a0] >> u & 1) {
+        int32_t w = m.best[(u64)v * NURI_MAX_LABELS + P.label[u]];
+        ok &= w > 0;
+        bound += w;
+      }
+    if (!ok) continue;
+    MRec r;
+    r.score = 0;
+    r.bound = bound;
+    for (int t = 0; t < QM; ++t) r.mu[t] = 0;
+    r.mu[a0] = v;
+    r.qid = q;
+    r.depth = 1;
+    r.nchild = child_bound(m, P, r);
+    r.pad = 0;
+    if (r.nchild == 0 && P.q > 1) continue;
+    unsigned int slot = atomicAdd(&ms[q].n_out, 1u);
+    if (slot < cfg[q].hdr_cap) {
+      cfg[q].hdr[slot] = r;
+      atomicAdd(&ms[q].out_cost, (u64)r.nchild);
+      atomicMax(&ms[q].out_max_bound, r.bound);
+      atomicMax(&ms[q].out_max_cost, (u64)r.nchild);
+    } else {
+      atomicAdd(&ms[q].overflow, 1u);
+    }
+  }
+}
+
+// ------------------------------------------------------------------
+// select (as for cliques): histogram of bounds, threshold, partition
+// ------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+    k_msel_hist(const MSeg *segs, const MCfg *cfg, const QRes *res, unsigned int *hist,
+                u64 *hcost) {
+  __shared__ unsigned int s_h[kBins];
+  __shared__ u64 s_c[kBins];
+  const uint32_t s = blockIdx.y;
+  const MSeg sg = segs[s];
+  if (sg.take_all) return;
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) {
+    s_h[b] = 0;
+    s_c[b] = 0;
+  }
+  __syncthreads();
+  const long long theta = res[sg.qid].theta;
+  const MRec *h = cfg[sg.qid].hdr + sg.begin;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sg.count;
+       i += gridDim.x * blockDim.x) {
+    const long long bound = h[i].bound;
+    if (bound < theta) continue;
+    int b = bin_of(bound, sg.top, sg.shift);
+    atomicAdd(&s_h[b], 1u);
+    atomicAdd(&s_c[b], (u64)h[i].nchild);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x)
+    if (s_h[b]) {
+      atomicAdd(&hist[(size_t)s * kBins + b], s_h[b]);
+      atomicAdd(&hcost[(size_t)s * kBins + b], s_c[b]);
+    }
+}
+
+__global__ void k_msel_thresh(const MSeg *segs, uint32_t nseg, unsigned int *hist, u64 *hcost,
+                              int *thr, unsigned int *quota) {
+  const uint32_t s = blockIdx.x;
+  if (s >= nseg) return;
+  const MSeg sg = segs[s];
+  if (threadIdx.x == 0 && !sg.take_all) {
+    u64 n = 0, c = 0;
+    int t = -1;
+    unsigned int q = 0;
+    for (int b = kBins - 1; b >= 0; --b) {
+      size_t o = (size_t)s * kBins + b;
+      u64 hn = hist[o];
+      if (!hn) continue;
+      u64 hc = hcost[o];
+      if (n + hn <= sg.max_records && c + hc <= sg.max_children) {
+        n += hn;
+        c += hc;
+        continue;
+      }
+      u64 qa = sg.max_records - n;
+      u64 mc = sg.maxcost ? (sg.max_children - c) / sg.maxcost : qa;
+      qa = qa < mc ? qa : mc;
+      if (qa == 0 && n == 0) qa = 1;  // the host guarantees one record always fits
+      t = b;
+      q = (unsigned int)(qa < hn ? qa : hn);
+      break;
+    }
+    thr[s] = t;
+    quota[s] = q;
+  }
+  __syncthreads();
+  if (!sg.take_all)
+    for (int b = threadIdx.x; b < kBins; b += blockDim.x) {
+      hist[(size_t)s * kBins + b] = 0;
+      hcost[(size_t)s * kBins + b] = 0;
+    }
+}
+
+__global__ void k_msel_part(const MSeg *segs, const MCfg *cfg, const QRes *res, const int *thr,
+                            const unsigned int *quota, unsigned int *taken, MRec *batch,
+                            StepHdr *hdr, MRec *temp, unsigned int *temp_count, MCtr *ctr) {
+  const uint32_t s = blockIdx.y;
+  const MSeg sg = segs[s];
+  const long long theta = res[sg.qid].theta;
+  const MRec *h = cfg[sg.qid].hdr + sg.begin;
+  const int t = sg.take_all ? -1 : thr[s];
+  const unsigned int qt = sg.take_all ? 0 : quota[s];
+  unsigned int pruned = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sg.count;
+       i += gridDim.x * blockDim.x) {
+    const MRec c = h[i];
+    int where;
+    if (c.bound < theta) {
+      where = 3;
+    } else if (sg.take_all) {
+      where = 1;
+    } else {
+      int b = bin_of(c.bound, sg.top, sg.shift);
+      if (b > t) where = 1;
+      else if (b < t) where = 2;
+      else where = atomicAdd(&taken[s], 1u) < qt ? 1 : 2;
+    }
+    if (where == 1) batch[atomicAdd(&hdr->batch_count, 1u)] = c;
+    else if (where == 2) temp[sg.temp_off + atomicAdd(&temp_count[s], 1u)] = c;
+    else ++pruned;
+  }
+  if (pruned) {
+    atomicAdd(&ctr[sg.qid].popped, (u64)pruned);
+    atomicAdd(&ctr[sg.qid].pruned_pop, (u64)pruned);
+  }
+}
+
+__global__ void k_mcopy_back(const MSeg *segs, const MCfg *cfg, const MRec *temp,
+                             const unsigned int *temp_count, MStep *ms) {
+  const uint32_t s = blockIdx.y;
+  const MSeg sg = segs[s];
+  const unsigned int kept = sg.take_all ? 0u : temp_count[s];
+  MRec *h = cfg[sg.qid].hdr + sg.begin;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < kept; i += gridDim.x * blockDim.x)
+    h[i] = temp[sg.temp_off + i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) ms[sg.qid].n_kept = kept;
+}
+
+// ------------------------------------------------------------------
+// expand (Algorithm 1, lines 11-16)
+// ------------------------------------------------------------------
+// One wavefront per record; lanes walk the candidates of the smallest
+// label segment among the matched neighbours of the next pattern vertex a
+// (coalesced reads of ids and weights), and test each candidate against
+// the other matched neighbours by binary search in their label-a segments.
+constexpr int kMatchWaves = 4;
+
+__global__ void __launch_bounds__(64 * kMatchWaves)
+    k_match_expand(MView m, const MPlan *plans, const MRec *__restrict__ batch, StepHdr *hdr,
+                   const MCfg *cfg, MStep *ms, MCtr *ctr, const QRes *res, Cand *cands,
+                   uint32_t *cand_ids, uint32_t cand_cap) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t rec = blockIdx.x * kMatchWaves + wv;
+  if (rec >= hdr->batch_count) return;
+  const MRec p = batch[rec];
+  const uint32_t q = p.qid;
+  const MPlan &P = plans[q];
+  const MCfg cf = cfg[q];
+  const long long theta = res[q].theta;
+  u64 st_children = 0, st_pruned_new = 0, st_leaves = 0, st_offered = 0, st_bytes = 0,
+      st_cost = 0, st_maxcost = 0;
+  long long st_maxb = LLONG_MIN;
+  const bool pruned_pop = p.bound < theta;
+  if (!pruned_pop && p.depth < P.q) {
+    const uint32_t a = P.order[p.depth];
+    const uint32_t la = P.label[a];
+    // anchor: the matched neighbour of a with the shortest label-la segment
+    uint32_t anchor = QM, alen = 0xFFFFFFFFu;
+    for (uint32_t i = 0; i < p.depth; ++i) {
+      const uint32_t b = P.order[i];
+      if (P.nbr[a] >> b & 1) {
+        uint32_t s = seg_len(m, p.mu[b], la);
+        if (s < alen) {
+          alen = s;
+          anchor = b;
+        }
+      }
+    }
+    if (anchor == QM) alen = 0;  // cannot happen for a connected pattern
+    const uint32_t av = anchor == QM ? 0 : p.mu[anchor];
+    const u64 base = m.orow[av] + m.loff[(u64)av * 17 + la];
+    const bool last = p.depth + 1 == P.q;
+    // the anchor's own bound term is replaced by the candidate's weight
+    long long bound0 = p.bound;
+    for (uint32_t i = 0; i < p.depth; ++i) {
+      const uint32_t b = P.order[i];
+      if (P.nbr[a] >> b & 1) bound0 -= m.best[(u64)p.mu[b] * NURI_MAX_LABELS + la];
+    }
+    for (uint32_t u = 0; u < P.q; ++u)
+      if ((P.nbr[a] >> u & 1) && P.pos[u] > p.depth) bound0 -= P.pmx[a][u];
+    if (lane == 0) {
+      st_children = alen;
+      st_bytes += 64 + 8ull * alen;
+    }
+    for (uint32_t t0 = 0; t0 < alen; t0 += 64) {
+      const uint32_t t = t0 + lane;
+      bool ok = t < alen;
+      uint32_t c = 0;
+      long long score2 = p.score, bound2 = bound0;
+      if (ok) {
+        c = m.lcol[base + t];
+        const int32_t wa = m.lew[base + t];
+        score2 += wa;
+        bound2 += wa;
+        // injectivity and symmetry breaking against every matched vertex
+        for (uint32_t i = 0; i < p.depth && ok; ++i) {
+          const uint32_t b = P.order[i];
+          const uint32_t mb = p.mu[b];
+          ok = c != mb;
+          if ((P.sb_lt[a] >> b & 1) && !(c < mb)) ok = false;
+          if ((P.sb_lt[b] >> a & 1) && !(mb < c)) ok = false;
+        }
+        // adjacency to the other matched neighbours
+        for (uint32_t i = 0; i < p.depth && ok; ++i) {
+          const uint32_t b = P.order[i];
+          if (b == anchor || !(P.nbr[a] >> b & 1)) continue;
+          long long at = seg_find(m, p.mu[b], la, c);
+          if (at < 0) {
+            ok = false;
+          } else {
+            const int32_t w = m.lew[at];
+            score2 += w;
+            bound2 += w;
+          }
+        }
+        // edges from a to unmatched pattern vertices: one-hop bound from c
+        for (uint32_t u = 0; u < P.q && ok; ++u)
+          if ((P.nbr[a] >> u & 1) && P.pos[u] > p.depth) {
+            const int32_t w = m.best[(u64)c * NURI_MAX_LABELS + P.label[u]];
+            if (w <= 0) ok = false;
+            bound2 += w;
+          }
+      }
+      const bool valid = t < alen;
+      const bool prune = valid && (!ok || bound2 < theta);
+      const bool complete = ok && !prune && last;
+      const bool offer = complete && score2 >= theta;
+      const bool keep = ok && !prune && !last;
+      st_pruned_new += __popcll(__ballot(prune));
+      st_leaves += __popcll(__ballot(complete));
+      // children
+      MRec ch;
+      uint32_t nch = 0;
+      if (keep) {
+        ch = p;
+        ch.mu[a] = c;
+        ch.score = score2;
+        ch.bound = bound2;
+        ch.depth = p.depth + 1;
+        nch = child_bound(m, P, ch);
+        ch.nchild = nch;
+      }
+      const bool keep2 = keep && nch > 0;  // a child with no possible candidate is dead
+      st_pruned_new += __popcll(__ballot(keep && !keep2));
+      const u64 km = __ballot(keep2);
+      if (km) {
+        unsigned int h0 = 0;
+        if (lane == 0) h0 = atomicAdd(&ms[q].n_out, (unsigned int)__popcll(km));
+        h0 = __shfl(h0, 0, 64);
+        if (keep2) {
+          const uint32_t rk = __popcll(km & ((1ull << lane) - 1ull));
+          const u64 slot = (u64)cf.out_hdr + h0 + rk;
+          if (slot < cf.hdr_cap) {
+            cf.hdr[slot] = ch;
+            st_cost += nch;
+            st_maxcost = nch > st_maxcost ? nch : st_maxcost;
+            st_maxb = bound2 > st_maxb ? bound2 : st_maxb;
+            st_bytes += 64;
+          } else {
+            atomicAdd(&ms[q].overflow, 1u);
+          }
+        }
+      }
+      const u64 fm = __ballot(offer);
+      if (fm) {
+        unsigned int c0 = 0;
+        if (lane == 0) c0 = atomicAdd(&hdr->leaf_count, (unsigned int)__popcll(fm));
+        c0 = __shfl(c0, 0, 64);
+        if (offer) {
+          const uint32_t slot = c0 + __popcll(fm & ((1ull << lane) - 1ull));
+          if (slot < cand_cap) {
+            Cand cd;
+            cd.score = score2;
+            cd.qid = q;
+            cd.len = P.q;
+            cands[slot] = cd;
+            uint32_t *dst = cand_ids + (u64)slot * QM;
+            for (uint32_t i = 0; i < P.q; ++i) dst[i] = (i == a) ? c : p.mu[i];
+            st_offered++;
+          } else {
+            atomicAdd(&ms[q].overflow, 1u);
+          }
+        }
+      }
+    }
+  }
+  st_cost = wave_sum(st_cost);
+  st_maxcost = wave_max_u64(st_maxcost);
+  st_bytes = wave_sum(st_bytes);
+  st_offered = wave_sum(st_offered);
+  st_maxb = wave_max(st_maxb);
+  if (lane == 0) {
+    MCtr &C = ctr[q];
+    atomicAdd(&C.popped, 1ull);
+    if (pruned_pop) atomicAdd(&C.pruned_pop, 1ull);
+    if (st_children) {
+      atomicAdd(&C.expanded, 1ull);
+      atomicAdd(&C.children, st_children);
+    }
+    if (st_pruned_new) atomicAdd(&C.pruned_new, st_pruned_new);
+    if (st_leaves) atomicAdd(&C.leaves, st_leaves);
+    if (st_offered) atomicAdd(&C.offered, st_offered);
+    if (st_bytes) atomicAdd(&C.logical_bytes, st_bytes);
+    if (st_cost) {
+      atomicAdd(&ms[q].out_cost, st_cost);
+      atomicMax(&ms[q].out_max_cost, st_maxcost);
+    }
+    if (st_maxb != LLONG_MIN) atomicMax(&ms[q].out_max_bound, st_maxb);
+  }
+}
+
+// ------------------------------------------------------------------
+// host: pattern planning
+// ------------------------------------------------------------------
+void plan_pattern(const Graph &g, const nuri_pattern &pt, uint32_t k, MPlan &P) {
+  const uint32_t q = pt.q;
+  if (q < 2 || q > (uint32_t)QM) throw Error{NURI_EINVAL, "pattern size must be 2..8"};
+  if (k == 0) throw Error{NURI_EINVAL, "k must be >= 1"};
+  memset(&P, 0, sizeof(P));
+  P.q = q;
+  P.k = k;
+  uint8_t adj[QM][QM] = {};
+  for (uint32_t a = 0; a < q; ++a) {
+    if (pt.label[a] >= NURI_MAX_LABELS) throw Error{NURI_EINVAL, "pattern label out of range"};
+    P.label[a] = pt.label[a];
+  }
+  for (uint32_t e = 0; e < pt.n_edges; ++e) {
+    uint32_t a = pt.edges[2 * e], b = pt.edges[2 * e + 1];
+    if (a >= q || b >= q || a == b) throw Error{NURI_EINVAL, "bad pattern edge"};
+    if (adj[a][b]) throw Error{NURI_EINVAL, "duplicate pattern edge"};
+    adj[a][b] = adj[b][a] = 1;
+  }
+  for (uint32_t a = 0; a < q; ++a)
+    for (uint32_t b = 0; b < q; ++b)
+      if (adj[a][b]) P.nbr[a] |= (uint8_t)(1u << b);
+  // connectivity
+  uint32_t seen = 1, grow = 1;
+  while (grow) {
+    grow = 0;
+    for (uint32_t a = 0; a < q; ++a)
+      if ((seen >> a & 1) && (P.nbr[a] & ~seen)) {
+        seen |= P.nbr[a];
+        grow = 1;
+      }
+  }
+  if (seen != (1u << q) - 1) throw Error{NURI_EINVAL, "pattern must be connected"};
+  // automorphisms (brute force over q! permutations)
+  std::vector<std::vector<uint8_t>> aut;
+  std::vector<uint8_t> perm(q);
+  std::iota(perm.begin(), perm.end(), 0);
+  do {
+    bool ok = true;
+    for (uint32_t a = 0; a < q && ok; ++a) ok = P.label[perm[a]] == P.label[a];
+    for (uint32_t a = 0; a < q && ok; ++a)
+      for (uint32_t b = a + 1; b < q && ok; ++b)
+        if (adj[a][b]) ok = adj[perm[a]][perm[b]];
+    if (ok) aut.push_back(perm);
+  } while (std::next_permutation(perm.begin(), perm.end()));
+  // symmetry breaking: mu(i) < mu(j) for j in the orbit of i under the
+  // automorphisms that fix 0..i-1
+  for (uint32_t i = 0; i < q; ++i)
+    for (const auto &s : aut) {
+      bool fixes = true;
+      for (uint32_t t = 0; t < i && fixes; ++t) fixes = s[t] == t;
+      if (fixes && s[i] != i) P.sb_lt[i] |= (uint8_t)(1u << s[i]);
+    }
+  // matching order: rarest label first (ties: larger degree, smaller id),
+  // then most edges into the ordered prefix (ties: smaller id)
+  uint32_t used = 0;
+  auto deg = [&](uint32_t a) { return (uint32_t)__builtin_popcount(P.nbr[a]); };
+  uint32_t first = 0;
+  for (uint32_t a = 1; a < q; ++a) {
+    uint64_t ca = g.h_label_count[P.label[a]], cb = g.h_label_count[P.label[first]];
+    if (ca < cb || (ca == cb && deg(a) > deg(first))) first = a;
+  }
+  P.order[0] = (uint8_t)first;
+  used = 1u << first;
+  for (uint32_t i = 1; i < q; ++i) {
+    uint32_t pick = q, pc = 0;
+    for (uint32_t a = 0; a < q; ++a) {
+      if (used >> a & 1) continue;
+      uint32_t c = __builtin_popcount(P.nbr[a] & used);
+      if (pick == q || c > pc) {
+        pick = a;
+        pc = c;
+      }
+    }
+    P.order[i] = (uint8_t)pick;
+    used |= 1u << pick;
+  }
+  for (uint32_t i = 0; i < q; ++i) P.pos[P.order[i]] = (uint8_t)i;
+  // label-pair maxima of the pattern edges, and the bound part of the
+  // edges that do not touch order[0]
+  P.rest0 = 0;
+  bool possible = true;
+  for (uint32_t a = 0; a < q; ++a)
+    for (uint32_t b = 0; b < q; ++b)
+      if (adj[a][b]) {
+        P.pmx[a][b] = g.h_pairmax[P.label[a] * NURI_MAX_LABELS + P.label[b]];
+        if (P.pmx[a][b] <= 0) possible = false;
+        if (a < b && a != first && b != first) P.rest0 += P.pmx[a][b];
+      }
+  if (!possible) P.rest0 = LLONG_MIN / 4;  // marks: no match can exist
+}
+
+// ------------------------------------------------------------------
+// host: engine
+// ------------------------------------------------------------------
+struct MLevel {
+  uint32_t begin = 0, count = 0;
+  u64 cost = 0, maxcost = 0;
+  long long max_bound = LLONG_MIN;
+};
+
+struct MQHost {
+  uint32_t k = 1;
+  std::vector<MLevel> stack;
+  bool rooted = false, done = false, impossible = false;
+  long long theta = LLONG_MIN;
+  uint32_t hdr_cap = 0;
+  int plan = 0;
+  uint32_t new_begin = 0;
+  int seg = -1;
+};
+
+struct MStepLayout {
+  size_t ms, cfg, seg, taken, tempc, thr, quota, total;
+  explicit MStepLayout(uint32_t nq) {
+    size_t o = sizeof(StepHdr);
+    ms = o;
+    o += nq * sizeof(MStep);
+    cfg = o;
+    o += nq * sizeof(MCfg);
+    seg = o;
+    o += nq * sizeof(MSeg);
+    taken = o;
+    o += nq * 4;
+    tempc = o;
+    o += nq * 4;
+    thr = o;
+    o += nq * 4;
+    quota = o;
+    o += nq * 4;
+    total = (o + 255) & ~size_t(255);
+  }
+  size_t readback() const { return cfg; }
+};
+
+struct MatchEngine {
+  Graph &g;
+  const QueryOpts &o;
+  hipStream_t s;
+  uint32_t nq = 0;
+  std::vector<MQHost> qh;
+  std::vector<MPlan> plans;
+  std::vector<MCfg> cfg;
+  DevBuf<MPlan> d_plans;
+  DevBuf<uint64_t> d_lab_off;
+  DevBuf<MRec> hdr, batch, temp;
+  DevBuf<MCtr> d_ctr;
+  DevBuf<QRes> d_res;
+  DevBuf<uint32_t> d_k;
+  DevBuf<long long> tk_score;
+  DevBuf<unsigned int> tk_len, tk_ids;
+  DevBuf<Cand> cands;
+  DevBuf<uint32_t> cand_ids;
+  DevBuf<unsigned int> d_hist;
+  DevBuf<u64> d_hcost;
+  DevBuf<unsigned char> d_step;
+  PinBuf<unsigned char> h_step;
+  PinBuf<QRes> h_res;
+  std::vector<MCtr> h_ctr;
+  std::unique_ptr<MStepLayout> L;
+  uint32_t batch_cap = 0, cand_cap = 0, B = 0;
+  u64 step_children = 0;
+  uint64_t steps = 0, launches = 0, expand_ns = 0, peak_bytes = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  MatchEngine(Graph &g_, const QueryOpts &o_) : g(g_), o(o_), s(o_.stream ? o_.stream : g_.stream) {}
+  ~MatchEngine() {
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+  }
+
+  MView view() const {
+    MView v;
+    v.orow = g.orow.p;
+    v.lcol = g.lcol.p;
+    v.lew = g.lew.p;
+    v.loff = g.loff.p;
+    v.best = g.best.p;
+    v.lab_vert = g.lab_vert.p;
+    return v;
+  }
+  StepHdr *sh() { return (StepHdr *)h_step.p; }
+  MStep *sms() { return (MStep *)(h_step.p + L->ms); }
+  MSeg *sseg() { return (MSeg *)(h_step.p + L->seg); }
+  template <class T>
+  T *dev(size_t off) {
+    return (T *)(d_step.p + off);
+  }
+
+  void setup(const std::vector<const nuri_pattern *> &ps, const std::vector<uint32_t> &ks) {
+    nq = (uint32_t)ps.size();
+    qh.resize(nq);
+    plans.resize(nq);
+    cfg.resize(nq);
+    L.reset(new MStepLayout(nq));
+    for (uint32_t i = 0; i < nq; ++i) {
+      plan_pattern(g, *ps[i], ks[i], plans[i]);
+      qh[i].k = ks[i];
+      qh[i].impossible = plans[i].rest0 == LLONG_MIN / 4;
+      qh[i].done = qh[i].impossible;
+    }
+    u64 per_q = o.frontier_budget / nq;
+    u64 hdr_per_q = std::max<u64>(4096, per_q / sizeof(MRec));
+    hdr_per_q = std::min<u64>(hdr_per_q, 0x7FFFFFFFull);
+    hdr.alloc(hdr_per_q * nq);
+    for (uint32_t i = 0; i < nq; ++i) {
+      qh[i].hdr_cap = (uint32_t)hdr_per_q;
+      cfg[i].hdr = hdr.p + (u64)i * hdr_per_q;
+      cfg[i].hdr_cap = (uint32_t)hdr_per_q;
+      cfg[i].out_hdr = 0;
+    }
+    d_plans.alloc(nq);
+    NURI_HIP(hipMemcpyAsync(d_plans.p, plans.data(), nq * sizeof(MPlan), hipMemcpyHostToDevice, s));
+    d_lab_off.alloc(NURI_MAX_LABELS + 1);
+    NURI_HIP(hipMemcpyAsync(d_lab_off.p, g.h_lab_off.data(), (NURI_MAX_LABELS + 1) * 8,
+                            hipMemcpyHostToDevice, s));
+    u64 tk_total = 0;
+    for (uint32_t i = 0; i < nq; ++i) tk_total += ks[i];
+    tk_score.alloc(2 * tk_total);
+    tk_len.alloc(2 * tk_total);
+    tk_ids.alloc(2 * tk_total * QM);
+    h_res.alloc(nq);
+    u64 tko = 0;
+    for (uint32_t i = 0; i < nq; ++i) {
+      QRes &R = h_res.p[i];
+      R.theta = LLONG_MIN;
+      R.tk_n = 0;
+      R.cur = 0;
+      for (int b = 0; b < 2; ++b) {
+        R.tk_score[b] = tk_score.p + 2 * tko + (u64)b * ks[i];
+        R.tk_len[b] = tk_len.p + 2 * tko + (u64)b * ks[i];
+        R.tk_ids[b] = tk_ids.p + (2 * tko + (u64)b * ks[i]) * QM;
+      }
+      tko += ks[i];
+    }
+    d_ctr.alloc(nq);
+    d_res.alloc(nq);
+    d_k.alloc(nq);
+    NURI_HIP(hipMemcpyAsync(d_res.p, h_res.p, nq * sizeof(QRes), hipMemcpyHostToDevice, s));
+    NURI_HIP(hipMemcpyAsync(d_k.p, ks.data(), nq * 4, hipMemcpyHostToDevice, s));
+    NURI_HIP(hipMemsetAsync(d_ctr.p, 0, nq * sizeof(MCtr), s));
+    h_ctr.assign(nq, MCtr{});
+    B = o.batch_B ? o.batch_B : 16384;
+    step_children = std::max<u64>(1ull << 16, std::min<u64>(o.frontier_budget / 8 / sizeof(MRec),
+                                                            8ull << 20));
+    cand_cap = (uint32_t)std::min<u64>(step_children, 1ull << 22);
+    batch_cap = (uint32_t)std::min<u64>((u64)nq * B, 1u << 24);
+    batch.alloc(batch_cap);
+    cands.alloc(cand_cap);
+    cand_ids.alloc((u64)cand_cap * QM);
+    d_hist.alloc((u64)nq * kBins);
+    d_hcost.alloc((u64)nq * kBins);
+    NURI_HIP(hipMemsetAsync(d_hist.p, 0, d_hist.bytes(), s));
+    NURI_HIP(hipMemsetAsync(d_hcost.p, 0, d_hcost.bytes(), s));
+    d_step.alloc(L->total);
+    h_step.alloc(L->total);
+    if (o.profile) {
+      NURI_HIP(hipEventCreate(&ev0));
+      NURI_HIP(hipEventCreate(&ev1));
+    }
+  }
+
+  void upload_step() {
+    for (uint32_t i = 0; i < nq; ++i) {
+      cfg[i].out_hdr = qh[i].new_begin;
+      sms()[i].out_max_bound = LLONG_MIN;
+    }
+    memcpy(h_step.p + L->cfg, cfg.data(), nq * sizeof(MCfg));
+    memset(h_step.p + L->taken, 0, 8ull * nq);
+    NURI_HIP(hipMemcpyAsync(d_step.p, h_step.p, L->total, hipMemcpyHostToDevice, s));
+  }
+
+  void read_step() {
+    NURI_HIP(hipMemcpyAsync(h_step.p, d_step.p, L->readback(), hipMemcpyDeviceToHost, s));
+    NURI_HIP(hipStreamSynchronize(s));
+  }
+
+  // every query's unit subgraphs become its first level, sorted by nothing:
+  // the select step orders them by bound
+  void make_roots() {
+    memset(h_step.p, 0, L->cfg);
+    for (uint32_t i = 0; i < nq; ++i) qh[i].new_begin = 0;
+    upload_step();
+    uint32_t maxn = 1;
+    for (int l = 0; l < NURI_MAX_LABELS; ++l)
+      maxn = std::max<uint32_t>(maxn, (uint32_t)(g.h_lab_off[l + 1] - g.h_lab_off[l]));
+    const uint32_t bx = std::min<uint32_t>((maxn + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_match_roots, dim3(bx, nq), dim3(256), 0, s, view(), d_plans.p,
+                       d_lab_off.p, dev<MCfg>(L->cfg), dev<MStep>(L->ms));
+    NURI_HIP(hipGetLastError());
+    read_step();
+    for (uint32_t i = 0; i < nq; ++i) {
+      MQHost &Q = qh[i];
+      const MStep &c = sms()[i];
+      if (c.overflow) throw Error{NURI_EBUDGET, "frontier budget too small for the unit subgraphs"};
+      Q.rooted = true;
+      if (Q.done) continue;
+      if (c.n_out) {
+        MLevel Lv;
+        Lv.begin = 0;
+        Lv.count = c.n_out;
+        Lv.cost = c.out_cost;
+        Lv.maxcost = c.out_max_cost;
+        Lv.max_bound = c.out_max_bound;
+        Q.stack.push_back(Lv);
+      } else {
+        Q.done = true;
+      }
+    }
+  }
+
+  bool plan(uint32_t &nseg, uint32_t &batch_ub, u64 &temp_need, uint32_t &max_count,
+            bool &any_sel) {
+    nseg = 0;
+    batch_ub = 0;
+    temp_need = 0;
+    max_count = 0;
+    any_sel = false;
+    uint32_t live = 0;
+    for (auto &Q : qh) live += !Q.done;
+    if (!live) return false;
+    const u64 share = std::max<u64>(step_children / live, 1);
+    u64 left = step_children, left_cand = cand_cap;
+    bool any = false;
+    for (uint32_t i = 0; i < nq; ++i) {
+      MQHost &Q = qh[i];
+      Q.plan = 0;
+      Q.seg = -1;
+      if (Q.done) continue;
+      while (!Q.stack.empty() && Q.stack.back().count == 0) Q.stack.pop_back();
+      if (Q.stack.empty()) {
+        Q.done = true;
+        continue;
+      }
+      MLevel &Lv = Q.stack.back();
+      const u64 free_h = Q.hdr_cap - (u64)(Lv.begin + Lv.count);
+      const uint32_t depth = (uint32_t)Q.stack.size();  // records at this level match `depth` vertices
+      const bool to_leaves = depth + 1 == plans[i].q;   // children are complete matches
+      u64 lim = std::min<u64>(std::min(left, share), to_leaves ? left_cand : free_h);
+      const u64 rec = std::max<u64>(1, Lv.maxcost);
+      if ((to_leaves ? cand_cap : free_h) < rec)
+        throw Error{NURI_EBUDGET, "frontier budget exhausted"};
+      if (lim < rec) continue;
+      const uint32_t room = batch_cap - batch_ub;
+      if (room == 0) continue;
+      MSeg &sg = sseg()[nseg];
+      sg = MSeg{};
+      sg.qid = i;
+      sg.begin = Lv.begin;
+      sg.count = Lv.count;
+      sg.max_records = std::min<u64>(B, room);
+      sg.max_children = lim;
+      sg.maxcost = Lv.maxcost;
+      sg.take_all = Lv.count <= sg.max_records && Lv.cost <= lim;
+      sg.top = Lv.max_bound;
+      const long long floor_b = Q.theta == LLONG_MIN ? 0 : Q.theta;
+      const long long span = Lv.max_bound - floor_b;
+      uint32_t shift = 0;
+      while (span > 0 && (span >> shift) >= kBins - 1) ++shift;
+      sg.shift = shift;
+      sg.temp_off = (uint32_t)temp_need;
+      if (!sg.take_all) {
+        temp_need += Lv.count;
+        any_sel = true;
+      }
+      max_count = std::max(max_count, Lv.count);
+      Q.seg = (int)nseg++;
+      Q.plan = 1;
+      Q.new_begin = Lv.begin + Lv.count;
+      batch_ub += (uint32_t)(sg.take_all ? Lv.count : sg.max_records);
+      const u64 used = sg.take_all ? Lv.cost : lim;
+      left -= std::min(left, used);
+      if (to_leaves) left_cand -= std::min(left_cand, used);
+      any = true;
+    }
+    if (!any)
+      for (auto &Q : qh)
+        if (!Q.done) throw Error{NURI_EBUDGET, "frontier budget too small to make progress"};
+    return any;
+  }
+
+  void step(uint32_t nseg, uint32_t batch_ub, u64 temp_need, uint32_t max_count, bool any_sel) {
+    memset(h_step.p, 0, L->cfg);
+    upload_step();
+    StepHdr *dh = dev<StepHdr>(0);
+    MStep *dms = dev<MStep>(L->ms);
+    MCfg *dcfg = dev<MCfg>(L->cfg);
+    MSeg *dseg = dev<MSeg>(L->seg);
+    if (temp_need && temp.n < temp_need) temp.alloc(temp_need * 2);
+    const uint32_t bx = std::max(1u, std::min<uint32_t>((max_count + 255) / 256, 2048));
+    if (any_sel) {
+      hipLaunchKernelGGL(k_msel_hist, dim3(std::min(bx, 512u), nseg), dim3(256), 0, s, dseg, dcfg,
+                         d_res.p, d_hist.p, d_hcost.p);
+      NURI_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_msel_thresh, dim3(nseg), dim3(256), 0, s, dseg, nseg, d_hist.p,
+                         d_hcost.p, dev<int>(L->thr), dev<unsigned int>(L->quota));
+      NURI_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_msel_part, dim3(bx, nseg), dim3(256), 0, s, dseg, dcfg, d_res.p,
+                       dev<int>(L->thr), dev<unsigned int>(L->quota), dev<unsigned int>(L->taken),
+                       batch.p, dh, temp.p, dev<unsigned int>(L->tempc), d_ctr.p);
+    NURI_HIP(hipGetLastError());
+    if (any_sel) {
+      hipLaunchKernelGGL(k_mcopy_back, dim3(bx, nseg), dim3(256), 0, s, dseg, dcfg, temp.p,
+                         dev<unsigned int>(L->tempc), dms);
+      NURI_HIP(hipGetLastError());
+    }
+    if (o.profile) NURI_HIP(hipEventRecord(ev0, s));
+    hipLaunchKernelGGL(k_match_expand, dim3((batch_ub + kMatchWaves - 1) / kMatchWaves),
+                       dim3(64 * kMatchWaves), 0, s, view(), d_plans.p, batch.p, dh, dcfg, dms,
+                       d_ctr.p, d_res.p, cands.p, cand_ids.p, cand_cap);
+    NURI_HIP(hipGetLastError());
+    if (o.profile) NURI_HIP(hipEventRecord(ev1, s));
+    launches++;
+    read_step();
+    if (o.profile) {
+      float ms = 0;
+      NURI_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+      expand_ns += (uint64_t)(ms * 1e6);
+    }
+    steps++;
+    u64 live = 0;
+    for (uint32_t i = 0; i < nq; ++i) {
+      MQHost &Q = qh[i];
+      const MStep &c = sms()[i];
+      if (c.overflow) throw Error{NURI_EBUDGET, "frontier overflow (internal accounting error)"};
+      if (!Q.plan) continue;
+      MLevel &Lv = Q.stack.back();
+      Lv.count = sseg()[Q.seg].take_all ? 0 : c.n_kept;
+      if (c.n_out) {
+        MLevel N;
+        N.begin = Q.new_begin;
+        N.count = c.n_out;
+        N.cost = c.out_cost;
+        N.maxcost = c.out_max_cost;
+        N.max_bound = c.out_max_bound;
+        Q.stack.push_back(N);
+      }
+      const MLevel &T = Q.stack.back();
+      live += (u64)(T.begin + T.count) * sizeof(MRec);
+    }
+    peak_bytes = std::max<uint64_t>(peak_bytes, live);
+    // complete matches -> top-k merge in chunks (the threshold rises between chunks)
+    const uint32_t ncand = sh()->leaf_count;
+    if (ncand > cand_cap) throw Error{NURI_EBUDGET, "candidate buffer overflow (internal)"};
+    if (ncand) {
+      uint32_t kmax = 0;
+      for (auto &Q : qh) kmax = std::max(kmax, Q.k);
+      const uint32_t mx = (kmax + kCandChunk + 255) / 256;
+      for (uint32_t f = 0; f < ncand; f += kCandChunk) {
+        const uint32_t cnt = std::min<uint32_t>(kCandChunk, ncand - f);
+        // the merge kernels read a chunk through StepHdr::cand_count
+        NURI_HIP(hipMemcpyAsync(&dh->cand_count, &cnt, sizeof(cnt), hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_merge_rank, dim3(mx, nq), dim3(256), 0, s, cands.p + f, dh,
+                           cand_ids.p + (u64)f * QM, (uint32_t)QM, d_res.p, d_k.p);
+        NURI_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_merge_finish, dim3(nq), dim3(256), 0, s, cands.p + f, dh, d_res.p,
+                           d_k.p);
+        NURI_HIP(hipGetLastError());
+        NURI_HIP(hipStreamSynchronize(s));  // `cnt` lives on this stack frame
+      }
+      NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
+      NURI_HIP(hipStreamSynchronize(s));
+      for (uint32_t i = 0; i < nq; ++i) qh[i].theta = h_res.p[i].theta;
+    }
+  }
+
+  void run() {
+    make_roots();
+    uint32_t nseg, batch_ub, maxc;
+    u64 temp_need;
+    bool any_sel;
+    const uint64_t t0 = now_ns();
+    while (plan(nseg, batch_ub, temp_need, maxc, any_sel)) {
+      if (o.deadline_ns && now_ns() - t0 > o.deadline_ns)
+        throw Error{NURI_ETIMEOUT, "query deadline passed"};
+      step(nseg, batch_ub, temp_need, maxc, any_sel);
+    }
+  }
+
+  void collect(std::vector<Result> &out, uint64_t wall) {
+    NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
+    NURI_HIP(hipMemcpyAsync(h_ctr.data(), d_ctr.p, nq * sizeof(MCtr), hipMemcpyDeviceToHost, s));
+    NURI_HIP(hipStreamSynchronize(s));
+    out.resize(nq);
+    for (uint32_t i = 0; i < nq; ++i) {
+      const QRes &R = h_res.p[i];
+      Result &res = out[i];
+      const uint32_t n = R.tk_n, q = plans[i].q;
+      std::vector<long long> sc(n);
+      std::vector<unsigned int> ids((u64)n * QM);
+      if (n) {
+        NURI_HIP(hipMemcpyAsync(sc.data(), R.tk_score[R.cur], n * 8, hipMemcpyDeviceToHost, s));
+        NURI_HIP(hipMemcpyAsync(ids.data(), R.tk_ids[R.cur], (u64)n * QM * 4,
+                                hipMemcpyDeviceToHost, s));
+        NURI_HIP(hipStreamSynchronize(s));
+      }
+      res.score.assign(sc.begin(), sc.end());
+      res.offset.assign(1, 0);
+      res.ids.clear();
+      for (uint32_t t = 0; t < n; ++t) {
+        res.ids.insert(res.ids.end(), ids.begin() + (u64)t * QM, ids.begin() + (u64)t * QM + q);
+        res.offset.push_back(res.ids.size());
+      }
+      const MCtr &c = h_ctr[i];
+      nuri_stats &st = res.stats;
+      memset(&st, 0, sizeof(st));
+      st.steps = steps;
+      st.popped = c.popped;
+      st.expanded = c.expanded;
+      st.children = c.children;
+      st.pruned_at_pop = c.pruned_pop;
+      st.pruned_at_creation = c.pruned_new;
+      st.leaves = c.leaves;
+      st.offered = c.offered;
+      st.frontier_peak_bytes = peak_bytes;
+      st.logical_bytes = c.logical_bytes;
+      st.expand_launches = launches;
+      st.expand_ns = expand_ns;
+      st.wall_ns = wall;
+    }
+  }
+};
+
+}  // namespace
+
+void run_matches(Graph &g, const std::vector<const nuri_pattern *> &ps,
+                 const std::vector<uint32_t> &ks, const QueryOpts &o, std::vector<Result> &out) {
+  const uint64_t t0 = now_ns();
+  if (ps.empty()) return;
+  if (!g.has_lab) throw Error{NURI_EINVAL, "labelled matching needs vertex labels"};
+  if (ps.size() > 65535) throw Error{NURI_EINVAL, "at most 65535 queries per batch"};
+  MatchEngine e(g, o);
+  e.setup(ps, ks);
+  e.run();
+  e.collect(out, now_ns() - t0);
 }
 
 }  // namespace nuri

@@ -86,12 +86,19 @@ struct Graph {
   DevBuf<uint32_t> dplus;     // |N+(r)|
   DevBuf<uint32_t> orig;      // rank -> original id
   DevBuf<int32_t> vw;         // vertex weight by rank
-  DevBuf<uint8_t> lab;        // label by rank
-  DevBuf<int32_t> ew;         // edge weight aligned with rcol
   DevBuf<uint64_t> bm_off;    // [n+1] word offset of r's local bitmap
   DevBuf<uint64_t> bm;        // local adjacency bitmaps
   DevBuf<int64_t> wplus;      // sum of vertex weights over N+(r)
-  DevBuf<int32_t> best;       // [n * 16] max edge weight from r to a label-l vertex (0 none)
+
+  // labelled matching works on original ids: every row of the input CSR
+  // re-sorted by (label, id), with per-row label segment offsets
+  DevBuf<uint64_t> orow;      // [n+1] = the input row_ptr
+  DevBuf<uint32_t> lcol;      // [nnz] neighbours sorted by (label, id)
+  DevBuf<int32_t> lew;        // [nnz] edge weights aligned with lcol
+  DevBuf<uint32_t> loff;      // [n * 17] label l of row v: lcol[orow[v] + loff[17v+l] .. 17v+l+1)
+  DevBuf<int32_t> best;       // [n * 16] max edge weight from v to a label-l vertex (0: none)
+  DevBuf<uint32_t> lab_vert;  // vertices grouped by label, ascending ids within a label
+  std::vector<uint64_t> h_lab_off;  // [17] offsets of the label groups in lab_vert
 
   // host mirrors used to plan queries
   std::vector<uint32_t> h_dplus;

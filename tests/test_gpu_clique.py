@@ -202,3 +202,21 @@ def test_invalid_arguments(nuri):
         assert e.value.name == "EINVAL"
     finally:
         G.close()
+
+
+def test_batch_equals_single_queries(nuri):
+    """Many clique queries (different k and scores) share every launch."""
+    g = synth.er_planted(n=3000, avg_degree=18.0, n_cliques=12, lo=6, hi=14, master=5)
+    synth.add_vertex_weights(g, 1, 100, master=5)
+    _case("clique batch of 24 queries")
+    ks = [1 + (7 * i) % 97 for i in range(24)]
+    wfs = [i % 2 for i in range(24)]
+    G = nuri.Graph.from_synth(g)
+    try:
+        outs = nuri.topk_batch(G, [{"kind": "clique", "k": k, "weight_fn": w}
+                                   for k, w in zip(ks, wfs)])
+        for i, (k, w) in enumerate(zip(ks, wfs)):
+            want, _ = oracle.topk_cliques(g, k, weighted=bool(w))
+            assert outs[i].items == want, i
+    finally:
+        G.close()
