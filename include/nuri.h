@@ -123,10 +123,15 @@ typedef struct {
  * Tuning and limits; pass NULL for defaults.  None of these changes a
  * result, only speed, memory and whether the call may fail.
  *   frontier_budget_bytes  device bytes for the frontier of partial
- *                          subgraphs (0 = 8 GiB); NURI_EBUDGET if the
- *                          search cannot proceed within it
+ *                          subgraphs (0 = 40% of the free device memory,
+ *                          at most 64 GiB); NURI_EBUDGET if the search
+ *                          cannot proceed within it
  *   batch_B                records expanded per step (0 = automatic)
  *   root_batch             unit subgraphs expanded per step (0 = automatic)
+ *   bound                  clique bound used to skip children before they
+ *                          are built: 0 automatic, 1 Carraghan-Pardalos
+ *                          (|V| + |P|, or the weight analogue) only,
+ *                          2 also colour classes of P for every record
  *   deadline_ns            wall-clock limit per call (0 = none)
  *   profile                1: time every expansion launch with HIP events
  *                          (reported in nuri_stats)
@@ -136,6 +141,7 @@ typedef struct {
   uint64_t frontier_budget_bytes;
   uint32_t batch_B;
   uint32_t root_batch;
+  uint32_t bound;
   uint64_t deadline_ns;
   uint32_t profile;
   void *hip_stream;

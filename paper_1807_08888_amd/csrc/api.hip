@@ -1,17 +1,12 @@
 // C ABI entry points (include/nuri.h): argument checks, handle ownership,
 // error codes and the thread-local error message.
+#include <algorithm>
 #include <cstring>
 #include <exception>
 #include <new>
 
 #include "nuri_internal.h"
 
-struct nuri_graph {
-  nuri::Graph *g;
-};
-struct nuri_result {
-  nuri::Result r;
-};
 
 namespace nuri {
 
@@ -19,13 +14,25 @@ static thread_local std::string t_err;
 
 void set_error(const std::string &msg) { t_err = msg; }
 
+// Default frontier budget: 40% of the free device memory, at most 64 GiB.
+static uint64_t default_budget() {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || free_b == 0) return 8ull << 30;
+  uint64_t b = (uint64_t)(free_b * 0.4);
+  b = std::min<uint64_t>(b, 64ull << 30);
+  return std::max<uint64_t>(b, 256ull << 20);
+}
+
 QueryOpts resolve_opts(const Graph &g, const nuri_opts *o) {
   QueryOpts q;
   q.stream = g.stream;
+  q.frontier_budget = default_budget();
   if (!o) return q;
   if (o->frontier_budget_bytes) q.frontier_budget = o->frontier_budget_bytes;
   q.batch_B = o->batch_B;
   q.root_batch = o->root_batch;
+  if (o->bound > 2) throw Error{NURI_EINVAL, "bound must be 0, 1 or 2"};
+  q.bound = o->bound;
   q.deadline_ns = o->deadline_ns;
   q.profile = o->profile != 0;
   if (o->hip_stream) q.stream = (hipStream_t)o->hip_stream;

@@ -71,6 +71,9 @@ struct QCfg {  // per query, written by the host each step
   uint32_t hdr_cap;
   uint32_t weighted;
   uint32_t k;
+  uint32_t colour_min;  // colour cutoff for records with at least this many live
+                        // children after the size cutoff (0 = never)
+  uint32_t pad;
 };
 
 struct QStep {  // per query, this step's counters (zeroed by the step upload)
@@ -372,6 +375,56 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       }
       cut = wave_min_u32(cut);
       if (cut < n_eff) n_eff = cut;
+      // colour-class cutoff (a tighter bound than Carraghan-Pardalos, the
+      // direction the paper leaves to future work): split the candidates
+      // into independent sets, each built greedily from the highest
+      // remaining position down.  The first vertex of class c is the
+      // highest uncoloured one, so class tops decrease; a clique in the
+      // subtree of child j uses at most one vertex of each class that
+      // reaches position j, so child j can score at most
+      // score + (sum of the max weights of classes whose top is >= j).
+      // Classes are built until that sum reaches theta - score; children
+      // above the top of the last class built are dominated.
+      const long long need = theta - p.score;
+      if (cf.colour_min && n_eff >= cf.colour_min && need > 0) {
+        const u64 *crow = g.bm + g.bm_off[r];
+        u64 U = pw, Q = 0;
+        long long run = 0;
+        int cut_pos = -1;  // children at positions <= cut_pos survive
+        while (__ballot(U != 0)) {
+          Q = U;
+          long long cmax = 0;
+          int top = -1;
+          while (__ballot(Q != 0)) {
+            int hb = (Q != 0) ? lane * 64 + 63 - (int)__clzll(Q) : -1;
+            for (int o2 = 32; o2 > 0; o2 >>= 1) {
+              int y = __shfl_xor(hb, o2, 64);
+              hb = y > hb ? y : hb;
+            }
+            if (top < 0) top = hb;
+            const long long wv2 = weighted ? (long long)wl[hb] : 1ll;
+            cmax = wv2 > cmax ? wv2 : cmax;
+            if (lane == (hb >> 6)) {
+              const u64 bit = 1ull << (hb & 63);
+              U &= ~bit;
+              Q &= ~bit;
+            }
+            if (lane < (int)W) Q &= ~crow[(u64)hb * W + lane];
+          }
+          run += cmax;
+          if (run >= need) {
+            cut_pos = top;
+            break;
+          }
+        }
+        // children surviving: candidates at positions <= cut_pos
+        uint32_t keep_n = 0;
+        if (cut_pos >= 0) {
+          const u64 m = (lane < (int)W) ? (pw & ~gt_mask(lane, cut_pos)) : 0ull;
+          keep_n = (uint32_t)wave_sum((u64)__popcll(m));
+        }
+        if (keep_n < n_eff) n_eff = keep_n;
+              }
     }
     wave_sync();
     if (last >= 0 && lane == 0) st_bytes += 32 + 16ull * W;  // the parent record
@@ -679,19 +732,29 @@ struct Level {
 };
 
 struct QHost {
+  bool active = false;  // the slot holds a query
+  bool done = true;     // the query needs no more steps
+  int error = 0;        // nuri_status of a failed query
+  std::string errmsg;
   uint32_t k = 1;
   int kind = 0;  // 0 size, 1 vertex weight
   std::vector<Level> stack;
   uint64_t cursor = 0;
   long long theta = LLONG_MIN;
-  bool done = false;
   uint32_t hdr_cap = 0;
   u64 word_cap = 0;
+  uint64_t t_admit = 0, steps = 0, expand_ns = 0, launches = 0, peak_bytes = 0;
   // this step
   int plan = 0;  // 0 idle, 1 roots, 2 level
   uint32_t new_begin = 0;
   u64 new_wbegin = 0;
   int sel_seg = -1;
+};
+
+// per-slot top-k buffers (two of each, switched by every merge)
+struct SlotTopk {
+  PoolBuf<long long> score;
+  PoolBuf<unsigned int> len, ids;
 };
 
 // Layout of the per-step block that one host-to-device copy uploads and
@@ -723,36 +786,36 @@ struct StepLayout {
 
 struct Engine {
   Graph &g;
-  const QueryOpts &o;
+  QueryOpts o;
   hipStream_t s;
-  uint32_t nq = 0;
+  bool server_mode = false;  // per-query failures mark the query instead of throwing
+  uint32_t nq = 0;           // slots
   uint32_t lmax = 0;
   std::vector<QHost> qh;
   std::vector<QCfg> cfg;
+  std::vector<std::unique_ptr<SlotTopk>> tk;
 
-  DevBuf<CRec> hdr;
-  DevBuf<u64> words;
-  DevBuf<QCtr> d_ctr;
-  DevBuf<QRes> d_res;
-  DevBuf<uint32_t> d_k;
-  DevBuf<long long> tk_score;
-  DevBuf<unsigned int> tk_len, tk_ids;
-  DevBuf<CRec> batch, temp;
-  DevBuf<LRec> leaves;
-  DevBuf<u64> leaf_words;
-  DevBuf<Cand> cands;
-  DevBuf<uint32_t> cand_ids;
-  DevBuf<unsigned int> d_hist;
-  DevBuf<u64> d_hchild;
-  DevBuf<unsigned char> d_step;
+  PoolBuf<CRec> hdr;
+  PoolBuf<u64> words;
+  PoolBuf<QCtr> d_ctr;
+  PoolBuf<QRes> d_res;
+  PoolBuf<uint32_t> d_k;
+  PoolBuf<CRec> batch, temp;
+  PoolBuf<LRec> leaves;
+  PoolBuf<u64> leaf_words;
+  PoolBuf<Cand> cands;
+  PoolBuf<uint32_t> cand_ids;
+  PoolBuf<unsigned int> d_hist;
+  PoolBuf<u64> d_hchild;
+  PoolBuf<unsigned char> d_step;
   PinBuf<unsigned char> h_step;
   PinBuf<QRes> h_res;
-  std::vector<QCtr> h_ctr;
+  PinBuf<QCtr> h_ctr;
+  PinBuf<uint32_t> h_k;
   uint32_t batch_cap = 0, leaf_cap = 0;
   u64 leaf_word_cap = 0;
   uint32_t B = 0, root_B = 0;
   u64 step_children = 0, step_words = 0;
-  uint64_t steps = 0, launches = 0, expand_ns = 0, peak_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::unique_ptr<StepLayout> L;
 
@@ -790,79 +853,70 @@ struct Engine {
     return (T *)(d_step.p + off);
   }
 
-  void setup(const std::vector<uint32_t> &ks, const std::vector<int> &kinds) {
-    nq = (uint32_t)ks.size();
+  // A query failed: in a batch the whole call fails; in the server only
+  // that query does.
+  void fail(uint32_t i, int code, const std::string &msg) {
+    if (!server_mode) throw Error{code, msg};
+    qh[i].error = code;
+    qh[i].errmsg = msg;
+    qh[i].done = true;
+  }
+
+  // allocate `slots` query slots sharing the frontier budget equally
+  void setup(uint32_t slots) {
+    nq = slots;
     lmax = g.degeneracy + 1;
-    qh.resize(nq);
-    cfg.resize(nq);
+    qh.assign(nq, QHost{});
+    cfg.assign(nq, QCfg{});
+    tk.clear();
+    for (uint32_t i = 0; i < nq; ++i) tk.emplace_back(new SlotTopk);
     L.reset(new StepLayout(nq));
-    // frontier budget: a third for headers, the rest for bitmap words,
-    // split evenly between the queries
-    u64 budget = o.frontier_budget;
-    u64 per_q = budget / nq;
+    const u64 budget = o.frontier_budget;
+    const u64 per_q = budget / nq;
     u64 hdr_per_q = std::max<u64>(1024, per_q / 3 / sizeof(CRec));
-    u64 word_per_q = std::max<u64>(4096, (per_q - hdr_per_q * sizeof(CRec)) / 8);
+    const u64 word_per_q = std::max<u64>(4096, (per_q - hdr_per_q * sizeof(CRec)) / 8);
     hdr_per_q = std::min<u64>(hdr_per_q, 0x7FFFFFFFull);
-    hdr.alloc(hdr_per_q * nq);
-    words.alloc(word_per_q * nq);
-    u64 tk_total = 0;
-    for (uint32_t i = 0; i < nq; ++i) tk_total += ks[i];
-    tk_score.alloc(2 * tk_total);
-    tk_len.alloc(2 * tk_total);
-    tk_ids.alloc(2 * tk_total * lmax);
+    hdr.alloc(g.pool, hdr_per_q * nq);
+    words.alloc(g.pool, word_per_q * nq);
     h_res.alloc(nq);
-    u64 tko = 0;
+    h_ctr.alloc(nq);
+    h_k.alloc(nq);
     for (uint32_t i = 0; i < nq; ++i) {
-      QHost &Q = qh[i];
-      Q.k = ks[i];
-      Q.kind = kinds[i];
-      Q.hdr_cap = (uint32_t)hdr_per_q;
-      Q.word_cap = word_per_q;
+      qh[i].hdr_cap = (uint32_t)hdr_per_q;
+      qh[i].word_cap = word_per_q;
       QCfg &c = cfg[i];
       c.hdr = hdr.p + (u64)i * hdr_per_q;
       c.words = words.p + (u64)i * word_per_q;
-      c.out_word = 0;
       c.word_cap = word_per_q;
-      c.out_hdr = 0;
       c.hdr_cap = (uint32_t)hdr_per_q;
-      c.weighted = kinds[i];
-      c.k = ks[i];
       QRes &R = h_res.p[i];
+      memset(&R, 0, sizeof(R));
       R.theta = LLONG_MIN;
-      R.tk_n = 0;
-      R.cur = 0;
-      for (int b = 0; b < 2; ++b) {
-        R.tk_score[b] = tk_score.p + 2 * tko + (u64)b * ks[i];
-        R.tk_len[b] = tk_len.p + 2 * tko + (u64)b * ks[i];
-        R.tk_ids[b] = tk_ids.p + (2 * tko + (u64)b * ks[i]) * lmax;
-      }
-      tko += ks[i];
+      h_k.p[i] = 1;
     }
-    d_ctr.alloc(nq);
-    d_res.alloc(nq);
-    d_k.alloc(nq);
+    d_ctr.alloc(g.pool, nq);
+    d_res.alloc(g.pool, nq);
+    d_k.alloc(g.pool, nq);
     NURI_HIP(hipMemcpyAsync(d_res.p, h_res.p, nq * sizeof(QRes), hipMemcpyHostToDevice, s));
-    NURI_HIP(hipMemcpyAsync(d_k.p, ks.data(), nq * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    NURI_HIP(hipMemcpyAsync(d_k.p, h_k.p, nq * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     NURI_HIP(hipMemsetAsync(d_ctr.p, 0, nq * sizeof(QCtr), s));
-    h_ctr.assign(nq, QCtr{});
-    // per-step limits
     B = o.batch_B ? o.batch_B : 16384;
     root_B = o.root_batch ? o.root_batch : 8192;
     step_words = std::max<u64>(1ull << 20, std::min<u64>(budget / 16 / 8, 64ull << 20));
     step_children = std::max<u64>(1ull << 16, std::min<u64>(step_words, 32ull << 20));
     batch_cap = (uint32_t)std::min<u64>((u64)nq * std::max(B, root_B), 1u << 26);
-    batch.alloc(batch_cap);
+    batch.alloc(g.pool, batch_cap);
     leaf_cap = (uint32_t)step_children;
     leaf_word_cap = step_words;
-    leaves.alloc(leaf_cap);
-    leaf_words.alloc(leaf_word_cap);
-    cands.alloc(kCandChunk);
-    cand_ids.alloc((u64)kCandChunk * lmax);
-    d_hist.alloc((u64)nq * kBins);
-    d_hchild.alloc((u64)nq * kBins);
+    leaves.alloc(g.pool, leaf_cap);
+    leaf_words.alloc(g.pool, leaf_word_cap);
+    cands.alloc(g.pool, kCandChunk);
+    cand_ids.alloc(g.pool, (u64)kCandChunk * lmax);
+    d_hist.alloc(g.pool, (u64)nq * kBins);
+    d_hchild.alloc(g.pool, (u64)nq * kBins);
     NURI_HIP(hipMemsetAsync(d_hist.p, 0, d_hist.bytes(), s));
     NURI_HIP(hipMemsetAsync(d_hchild.p, 0, d_hchild.bytes(), s));
-    d_step.alloc(L->total);
+    d_step.alloc(g.pool, L->total);
     h_step.alloc(L->total);
     if (o.profile) {
       NURI_HIP(hipEventCreate(&ev0));
@@ -870,12 +924,55 @@ struct Engine {
     }
   }
 
-  // largest possible output of one record
+  // start query (k, score kind) in a free slot
+  void admit(uint32_t i, uint32_t k, int kind) {
+    QHost &Q = qh[i];
+    Q = QHost{};
+    Q.active = true;
+    Q.done = false;
+    Q.k = k;
+    Q.kind = kind;
+    Q.hdr_cap = cfg[i].hdr_cap;
+    Q.word_cap = cfg[i].word_cap;
+    Q.t_admit = now_ns();
+    QCfg &c = cfg[i];
+    c.weighted = kind;
+    c.k = k;
+    c.colour_min = o.bound == 1 ? 0u : (o.bound == 2 ? 1u : 32u);
+    c.pad = 0;
+    SlotTopk &T = *tk[i];
+    T.score.alloc(g.pool, 2ull * k);
+    T.len.alloc(g.pool, 2ull * k);
+    T.ids.alloc(g.pool, 2ull * k * lmax);
+    QRes &R = h_res.p[i];
+    R.theta = LLONG_MIN;
+    R.tk_n = 0;
+    R.cur = 0;
+    for (int b = 0; b < 2; ++b) {
+      R.tk_score[b] = T.score.p + (u64)b * k;
+      R.tk_len[b] = T.len.p + (u64)b * k;
+      R.tk_ids[b] = T.ids.p + (u64)b * k * lmax;
+    }
+    h_k.p[i] = k;
+    NURI_HIP(hipMemcpyAsync(&d_res.p[i], &h_res.p[i], sizeof(QRes), hipMemcpyHostToDevice, s));
+    NURI_HIP(hipMemcpyAsync(&d_k.p[i], &h_k.p[i], sizeof(uint32_t), hipMemcpyHostToDevice, s));
+    NURI_HIP(hipMemsetAsync(&d_ctr.p[i], 0, sizeof(QCtr), s));
+  }
+
+  bool slot_free(uint32_t i) const { return !qh[i].active; }
+  bool finished(uint32_t i) const { return qh[i].active && qh[i].done; }
+  bool any_live() const {
+    for (auto &Q : qh)
+      if (Q.active && !Q.done) return true;
+    return false;
+  }
+
+  // one record of output at most: d children of 2W words
   u64 max_rec_children() const { return g.degeneracy; }
   u64 max_rec_words() const { return (u64)g.degeneracy * 2 * ((g.degeneracy + 63) / 64); }
 
   // plan this step for every live query into the staging block; returns
-  // false when every query is done
+  // false when no query has work
   bool plan(uint32_t &nseg, uint32_t &nrseg, uint32_t &batch_ub, u64 &temp_need,
             uint32_t &max_seg_count, uint32_t &max_rseg_count) {
     nseg = nrseg = 0;
@@ -883,8 +980,9 @@ struct Engine {
     temp_need = 0;
     max_seg_count = max_rseg_count = 0;
     uint32_t live = 0;
-    for (auto &Q : qh) live += !Q.done;
+    for (auto &Q : qh) live += Q.active && !Q.done;
     if (!live) return false;
+    const uint64_t now = o.deadline_ns ? now_ns() : 0;
     // each live query may use an equal share of this step's output limits
     const u64 share_c = std::max<u64>(step_children / live, max_rec_children());
     const u64 share_w = std::max<u64>(step_words / live, max_rec_words());
@@ -894,7 +992,11 @@ struct Engine {
       QHost &Q = qh[i];
       Q.plan = 0;
       Q.sel_seg = -1;
-      if (Q.done) continue;
+      if (!Q.active || Q.done) continue;
+      if (o.deadline_ns && now - Q.t_admit > o.deadline_ns) {
+        fail(i, NURI_ETIMEOUT, "query deadline passed");
+        continue;
+      }
       while (!Q.stack.empty() && Q.stack.back().count == 0) Q.stack.pop_back();
       const u64 cap_c = std::min(left_c, share_c), cap_w = std::min(left_w, share_w);
       if (Q.stack.empty()) {
@@ -913,16 +1015,18 @@ struct Engine {
         u64 cc = 0, cw = 0, cnt = 0;
         const u64 lim_c = std::min<u64>(cap_c, Q.hdr_cap), lim_w = std::min<u64>(cap_w, Q.word_cap);
         while (Q.cursor + cnt < end && cnt < root_B && batch_ub + cnt < batch_cap) {
-          uint32_t r = ro[Q.cursor + cnt];
-          u64 d = g.h_dplus[r];
-          u64 w = d * 2 * ((d + 63) / 64);
+          const uint32_t r = ro[Q.cursor + cnt];
+          const u64 d = g.h_dplus[r];
+          const u64 w = d * 2 * ((d + 63) / 64);
           if (cnt > 0 && (cc + d > lim_c || cw + w > lim_w)) break;
           cc += d;
           cw += w;
           ++cnt;
         }
-        if (cc > Q.hdr_cap || cw > Q.word_cap)
-          throw Error{NURI_EBUDGET, "frontier budget too small for one unit subgraph"};
+        if (cc > Q.hdr_cap || cw > Q.word_cap) {
+          fail(i, NURI_EBUDGET, "frontier budget too small for one unit subgraph");
+          continue;
+        }
         if (cnt == 0) continue;
         RootSeg &rs = srseg()[nrseg++];
         rs.qid = i;
@@ -946,7 +1050,10 @@ struct Engine {
       const u64 lim_c = std::min<u64>(cap_c, free_h), lim_w = std::min<u64>(cap_w, free_w);
       // one record of this level must always fit
       const u64 rec_c = std::max<u64>(1, Lv.maxcc), rec_w = rec_c * 2 * std::max(1u, Lv.maxw);
-      if (free_h < rec_c || free_w < rec_w) throw Error{NURI_EBUDGET, "frontier budget exhausted"};
+      if (free_h < rec_c || free_w < rec_w) {
+        fail(i, NURI_EBUDGET, "frontier budget exhausted");
+        continue;
+      }
       if (lim_c < rec_c || lim_w < rec_w) continue;  // next step
       const uint32_t room = batch_cap - batch_ub;
       if (room == 0) continue;
@@ -982,12 +1089,10 @@ struct Engine {
       left_w -= std::min(left_w, uw);
       any = true;
     }
-    if (!any) {
-      // every live query waits on budget that only it can free: cannot happen
-      // unless the per-query budget is below one record's output
-      for (auto &Q : qh)
-        if (!Q.done) throw Error{NURI_EBUDGET, "frontier budget too small to make progress"};
-    }
+    if (!any)
+      for (uint32_t i = 0; i < nq; ++i)
+        if (qh[i].active && !qh[i].done)
+          fail(i, NURI_EBUDGET, "frontier budget too small to make progress");
     return any;
   }
 
@@ -1009,7 +1114,7 @@ struct Engine {
     QCfg *dcfg = dev<QCfg>(L->cfg);
     SelSeg *dseg = dev<SelSeg>(L->seg);
     if (nrseg) {
-      uint32_t bx = std::min<uint32_t>((max_rseg_count + 255) / 256, 1024);
+      const uint32_t bx = std::min<uint32_t>((max_rseg_count + 255) / 256, 1024);
       hipLaunchKernelGGL(k_make_roots, dim3(std::max(1u, bx), nrseg), dim3(256), 0, s, gv,
                          dev<RootSeg>(L->rseg), batch.p, dh);
       NURI_HIP(hipGetLastError());
@@ -1017,9 +1122,8 @@ struct Engine {
     if (nseg) {
       bool any_sel = false;
       for (uint32_t i = 0; i < nseg; ++i) any_sel |= !sseg()[i].take_all;
-      if (temp_need && temp.n < temp_need) temp.alloc(temp_need * 2);
-      uint32_t bx = std::min<uint32_t>((max_seg_count + 255) / 256, 2048);
-      bx = std::max(1u, bx);
+      if (temp_need && temp.n < temp_need) temp.alloc(g.pool, temp_need * 2);
+      const uint32_t bx = std::max(1u, std::min<uint32_t>((max_seg_count + 255) / 256, 2048));
       if (any_sel) {
         hipLaunchKernelGGL(k_sel_hist, dim3(std::min(bx, 512u), nseg), dim3(256), 0, s, gv, dseg,
                            dcfg, d_res.p, d_hist.p, d_hchild.p);
@@ -1039,35 +1143,40 @@ struct Engine {
         NURI_HIP(hipGetLastError());
       }
     }
+    uint64_t ens = 0;
     if (batch_ub) {
       if (o.profile) NURI_HIP(hipEventRecord(ev0, s));
-      uint32_t blocks = (batch_ub + kExpandWaves - 1) / kExpandWaves;
+      const uint32_t blocks = (batch_ub + kExpandWaves - 1) / kExpandWaves;
       hipLaunchKernelGGL(k_expand, dim3(blocks), dim3(64 * kExpandWaves), 0, s, gv, batch.p, dh,
                          dcfg, dqs, d_ctr.p, d_res.p, leaves.p, leaf_words.p, leaf_cap,
                          leaf_word_cap);
       NURI_HIP(hipGetLastError());
       if (o.profile) NURI_HIP(hipEventRecord(ev1, s));
-      launches++;
     }
     NURI_HIP(hipMemcpyAsync(h_step.p, d_step.p, L->readback(), hipMemcpyDeviceToHost, s));
     NURI_HIP(hipStreamSynchronize(s));
     if (o.profile && batch_ub) {
       float ms = 0;
       NURI_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-      expand_ns += (uint64_t)(ms * 1e6);
+      ens = (uint64_t)(ms * 1e6);
     }
-    steps++;
     // update the level stacks
-    u64 live = 0;
     for (uint32_t i = 0; i < nq; ++i) {
       QHost &Q = qh[i];
+      if (!Q.plan) continue;
       const QStep &c = sq()[i];
-      if (c.overflow) throw Error{NURI_EBUDGET, "frontier overflow (internal accounting error)"};
+      Q.steps++;
+      Q.launches++;
+      Q.expand_ns += ens;
+      if (c.overflow) {
+        fail(i, NURI_EBUDGET, "frontier overflow (internal accounting error)");
+        continue;
+      }
       if (Q.plan == 2) {
         Level &Lv = Q.stack.back();
         Lv.count = sseg()[Q.sel_seg].take_all ? 0 : c.n_kept;
       }
-      if (Q.plan && c.n_out) {
+      if (c.n_out) {
         Level N;
         N.begin = Q.new_begin;
         N.count = c.n_out;
@@ -1082,16 +1191,17 @@ struct Engine {
       }
       if (!Q.stack.empty()) {
         const Level &T = Q.stack.back();
-        live += (u64)(T.begin + T.count) * sizeof(CRec) + T.wend * 8;
+        Q.peak_bytes = std::max<u64>(Q.peak_bytes, (u64)(T.begin + T.count) * sizeof(CRec) +
+                                                        T.wend * 8);
       }
     }
-    peak_bytes = std::max<uint64_t>(peak_bytes, live);
     // leaves -> maximality check -> merge, in chunks
     const uint32_t nleaf = sh()->leaf_count;
     if (nleaf > leaf_cap) throw Error{NURI_EBUDGET, "leaf buffer overflow (internal)"};
     if (nleaf) {
       uint32_t kmax = 0;
-      for (auto &Q : qh) kmax = std::max(kmax, Q.k);
+      for (auto &Q : qh)
+        if (Q.active) kmax = std::max(kmax, Q.k);
       const uint32_t mx = (kmax + kCandChunk + 255) / 256;
       for (uint32_t f = 0; f < nleaf; f += kCandChunk) {
         const uint32_t cnt = std::min<uint32_t>(kCandChunk, nleaf - f);
@@ -1109,84 +1219,116 @@ struct Engine {
       }
       NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
       NURI_HIP(hipStreamSynchronize(s));
-      for (uint32_t i = 0; i < nq; ++i) qh[i].theta = h_res.p[i].theta;
+      for (uint32_t i = 0; i < nq; ++i)
+        if (qh[i].active) qh[i].theta = h_res.p[i].theta;
     }
   }
 
-  void run() {
+  // one step for every live query; false when none has work left
+  bool step_all() {
     uint32_t nseg, nrseg, batch_ub, mseg, mrseg;
     u64 temp_need;
-    const uint64_t t0 = now_ns();
-    while (plan(nseg, nrseg, batch_ub, temp_need, mseg, mrseg)) {
-      if (o.deadline_ns && now_ns() - t0 > o.deadline_ns)
-        throw Error{NURI_ETIMEOUT, "query deadline passed"};
-      step(nseg, nrseg, batch_ub, temp_need, mseg, mrseg);
-    }
+    if (!plan(nseg, nrseg, batch_ub, temp_need, mseg, mrseg)) return false;
+    step(nseg, nrseg, batch_ub, temp_need, mseg, mrseg);
+    return true;
   }
 
-  void collect(std::vector<Result> &out, uint64_t wall) {
-    NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
-    NURI_HIP(hipMemcpyAsync(h_ctr.data(), d_ctr.p, nq * sizeof(QCtr), hipMemcpyDeviceToHost, s));
+  // result of a finished query; frees its slot
+  void harvest(uint32_t i, Result &res) {
+    QHost &Q = qh[i];
+    NURI_HIP(hipMemcpyAsync(&h_res.p[i], &d_res.p[i], sizeof(QRes), hipMemcpyDeviceToHost, s));
+    NURI_HIP(hipMemcpyAsync(&h_ctr.p[i], &d_ctr.p[i], sizeof(QCtr), hipMemcpyDeviceToHost, s));
     NURI_HIP(hipStreamSynchronize(s));
-    out.resize(nq);
-    for (uint32_t i = 0; i < nq; ++i) {
-      const QRes &R = h_res.p[i];
-      Result &res = out[i];
-      const uint32_t n = R.tk_n;
-      std::vector<long long> sc(n);
-      std::vector<unsigned int> ln(n), ids((u64)n * lmax);
-      if (n) {
-        NURI_HIP(hipMemcpyAsync(sc.data(), R.tk_score[R.cur], n * 8, hipMemcpyDeviceToHost, s));
-        NURI_HIP(hipMemcpyAsync(ln.data(), R.tk_len[R.cur], n * 4, hipMemcpyDeviceToHost, s));
-        NURI_HIP(hipMemcpyAsync(ids.data(), R.tk_ids[R.cur], (u64)n * lmax * 4,
-                                hipMemcpyDeviceToHost, s));
-        NURI_HIP(hipStreamSynchronize(s));
-      }
-      res.score.assign(sc.begin(), sc.end());
-      res.offset.assign(1, 0);
-      res.ids.clear();
-      for (uint32_t t = 0; t < n; ++t) {
-        res.ids.insert(res.ids.end(), ids.begin() + (u64)t * lmax,
-                       ids.begin() + (u64)t * lmax + ln[t]);
-        res.offset.push_back(res.ids.size());
-      }
-      const QCtr &c = h_ctr[i];
-      nuri_stats &st = res.stats;
-      memset(&st, 0, sizeof(st));
-      st.steps = steps;
-      st.popped = c.popped;
-      st.expanded = c.expanded;
-      st.children = c.children;
-      st.pruned_at_pop = c.pruned_pop;
-      st.pruned_at_creation = c.pruned_new;
-      st.leaves = c.leaves;
-      st.offered = c.offered;
-      st.frontier_peak_bytes = peak_bytes;
-      st.logical_bytes = c.logical_bytes;
-      st.expand_launches = launches;
-      st.expand_ns = expand_ns;
-      st.wall_ns = wall;
+    const QRes &R = h_res.p[i];
+    const uint32_t n = Q.error ? 0 : R.tk_n;
+    std::vector<long long> sc(n);
+    std::vector<unsigned int> ln(n), ids((u64)n * lmax);
+    if (n) {
+      NURI_HIP(hipMemcpyAsync(sc.data(), R.tk_score[R.cur], n * 8, hipMemcpyDeviceToHost, s));
+      NURI_HIP(hipMemcpyAsync(ln.data(), R.tk_len[R.cur], n * 4, hipMemcpyDeviceToHost, s));
+      NURI_HIP(hipMemcpyAsync(ids.data(), R.tk_ids[R.cur], (u64)n * lmax * 4,
+                              hipMemcpyDeviceToHost, s));
+      NURI_HIP(hipStreamSynchronize(s));
     }
+    res.error = Q.error;
+    res.errmsg = Q.errmsg;
+    res.score.assign(sc.begin(), sc.end());
+    res.offset.assign(1, 0);
+    res.ids.clear();
+    for (uint32_t t = 0; t < n; ++t) {
+      res.ids.insert(res.ids.end(), ids.begin() + (u64)t * lmax,
+                     ids.begin() + (u64)t * lmax + ln[t]);
+      res.offset.push_back(res.ids.size());
+    }
+    const QCtr &c = h_ctr.p[i];
+    nuri_stats &st = res.stats;
+    memset(&st, 0, sizeof(st));
+    st.steps = Q.steps;
+    st.popped = c.popped;
+    st.expanded = c.expanded;
+    st.children = c.children;
+    st.pruned_at_pop = c.pruned_pop;
+    st.pruned_at_creation = c.pruned_new;
+    st.leaves = c.leaves;
+    st.offered = c.offered;
+    st.frontier_peak_bytes = Q.peak_bytes;
+    st.logical_bytes = c.logical_bytes;
+    st.expand_launches = Q.launches;
+    st.expand_ns = Q.expand_ns;
+    st.wall_ns = now_ns() - Q.t_admit;
+    Q.active = false;
+    Q.stack.clear();
+    tk[i]->score.release();
+    tk[i]->len.release();
+    tk[i]->ids.release();
   }
 };
 
 }  // namespace
 
+void check_clique_query(const Graph &g, uint32_t k, int kind) {
+  if (k == 0) throw Error{NURI_EINVAL, "k must be >= 1"};
+  if (kind != 0 && kind != 1) throw Error{NURI_EINVAL, "unknown weight_fn"};
+  if (kind == 1 && !g.has_vw)
+    throw Error{NURI_EINVAL, "NURI_SCORE_VERTEX_WEIGHT needs vertex weights"};
+}
+
 void run_cliques(Graph &g, const std::vector<uint32_t> &ks, const std::vector<int> &kinds,
                  const QueryOpts &o, std::vector<Result> &out) {
-  const uint64_t t0 = now_ns();
   if (ks.empty()) return;
   if (ks.size() > 65535) throw Error{NURI_EINVAL, "at most 65535 queries per batch"};
-  for (size_t i = 0; i < ks.size(); ++i) {
-    if (ks[i] == 0) throw Error{NURI_EINVAL, "k must be >= 1"};
-    if (kinds[i] != 0 && kinds[i] != 1) throw Error{NURI_EINVAL, "unknown weight_fn"};
-    if (kinds[i] == 1 && !g.has_vw)
-      throw Error{NURI_EINVAL, "NURI_SCORE_VERTEX_WEIGHT needs vertex weights"};
-  }
+  for (size_t i = 0; i < ks.size(); ++i) check_clique_query(g, ks[i], kinds[i]);
   Engine e(g, o);
-  e.setup(ks, kinds);
-  e.run();
-  e.collect(out, now_ns() - t0);
+  e.setup((uint32_t)ks.size());
+  for (uint32_t i = 0; i < ks.size(); ++i) e.admit(i, ks[i], kinds[i]);
+  while (e.step_all()) {
+  }
+  out.resize(ks.size());
+  for (uint32_t i = 0; i < ks.size(); ++i) e.harvest(i, out[i]);
 }
+
+// ------------------------------------------------------------------
+// slot interface for the server
+// ------------------------------------------------------------------
+struct CliqueSlots::Impl {
+  Engine e;
+  Impl(Graph &g, const QueryOpts &o) : e(g, o) {}
+};
+
+CliqueSlots::CliqueSlots(Graph &g, const QueryOpts &o, uint32_t slots) : impl(new Impl(g, o)) {
+  impl->e.server_mode = true;
+  impl->e.setup(slots);
+}
+CliqueSlots::~CliqueSlots() = default;
+uint32_t CliqueSlots::slots() const { return impl->e.nq; }
+bool CliqueSlots::free(uint32_t i) const { return impl->e.slot_free(i); }
+bool CliqueSlots::finished(uint32_t i) const { return impl->e.finished(i); }
+bool CliqueSlots::live() const { return impl->e.any_live(); }
+void CliqueSlots::admit(uint32_t i, uint32_t k, int kind) {
+  check_clique_query(impl->e.g, k, kind);
+  impl->e.admit(i, k, kind);
+}
+bool CliqueSlots::step() { return impl->e.step_all(); }
+void CliqueSlots::harvest(uint32_t i, Result &r) { impl->e.harvest(i, r); }
 
 }  // namespace nuri

@@ -70,10 +70,17 @@ struct MCfg {  // per query, per step
 };
 
 struct MStep {  // per query, this step's counters
-  unsigned int n_out, n_kept, overflow, pad;
+  unsigned int n_out, n_kept, overflow, cand_n;
   u64 out_cost;        // sum of nchild over appended records
   long long out_max_bound;
   u64 out_max_cost;
+  long long cand_max;  // best score among this step's complete matches
+};
+
+struct CPre {  // per query: score histogram window for the candidate prefilter
+  long long top;
+  uint32_t shift;
+  int tbin;  // candidates in bins >= tbin are kept
 };
 
 struct MCtr {
@@ -120,11 +127,11 @@ __device__ inline uint32_t child_bound(const MView &m, const MPlan &P, const MRe
 
 // ------------------------------------------------------------------
 // unit subgraphs: every vertex with the label of order[0] (lines 1-3)
-// grid: (x, query)
+// grid: (x, index into the list of slots being started)
 // ------------------------------------------------------------------
 __global__ void k_match_roots(MView m, const MPlan *plans, const uint64_t *lab_off, MCfg *cfg,
-                              MStep *ms) {
-  const uint32_t q = blockIdx.y;
+                              MStep *ms, const uint32_t *slots) {
+  const uint32_t q = slots[blockIdx.y];
   const MPlan &P = plans[q];
   const uint32_t a0 = P.order[0];
   const uint32_t l0 = P.label[a0];
@@ -417,6 +424,12 @@ __global__ void __launch_bounds__(64 * kMatchWaves)
       }
       const u64 fm = __ballot(offer);
       if (fm) {
+        long long cm = offer ? score2 : LLONG_MIN;
+        cm = wave_max(cm);
+        if (lane == 0) {
+          atomicAdd(&ms[q].cand_n, (unsigned int)__popcll(fm));
+          atomicMax(&ms[q].cand_max, cm);
+        }
         unsigned int c0 = 0;
         if (lane == 0) c0 = atomicAdd(&hdr->leaf_count, (unsigned int)__popcll(fm));
         c0 = __shfl(c0, 0, 64);
@@ -461,6 +474,66 @@ __global__ void __launch_bounds__(64 * kMatchWaves)
     }
     if (st_maxb != LLONG_MIN) atomicMax(&ms[q].out_max_bound, st_maxb);
   }
+}
+
+// ------------------------------------------------------------------
+// candidate prefilter: complete matches are results, so at most k of
+// them can matter per query; a histogram of scores over the new
+// candidates and the current top-k gives a score below which none can
+// enter, and only the rest go to the exact merge
+// ------------------------------------------------------------------
+__device__ inline int cbin(long long score, const CPre &c) {
+  long long gap = (c.top - score) >> c.shift;
+  long long b = kBins - 1 - gap;
+  return b < 0 ? 0 : (b > kBins - 1 ? kBins - 1 : (int)b);
+}
+
+__global__ void k_cand_hist(const Cand *cands, uint32_t ncand, const QRes *res, const CPre *pre,
+                            unsigned int *hist) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncand) {
+    const Cand c = cands[i];
+    atomicAdd(&hist[(size_t)c.qid * kBins + cbin(c.score, pre[c.qid])], 1u);
+  }
+}
+
+// the current top-k entries count too: one block per query
+
+__global__ void k_cand_hist_topk(const QRes *res, const CPre *pre, unsigned int *hist) {
+  const uint32_t q = blockIdx.x;
+  const QRes R = res[q];
+  for (uint32_t i = threadIdx.x; i < R.tk_n; i += blockDim.x)
+    atomicAdd(&hist[(size_t)q * kBins + cbin(R.tk_score[R.cur][i], pre[q])], 1u);
+}
+
+__global__ void k_cand_thresh(const uint32_t *ks, CPre *pre, unsigned int *hist) {
+  const uint32_t q = blockIdx.x;
+  if (threadIdx.x == 0) {
+    u64 n = 0;
+    int t = 0;
+    for (int b = kBins - 1; b >= 0; --b) {
+      n += hist[(size_t)q * kBins + b];
+      if (n >= ks[q]) {
+        t = b;
+        break;
+      }
+    }
+    pre[q].tbin = t;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) hist[(size_t)q * kBins + b] = 0;
+}
+
+__global__ void k_cand_compact(const Cand *cands, const uint32_t *ids, uint32_t ncand,
+                               const CPre *pre, Cand *out, uint32_t *out_ids,
+                               unsigned int *count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncand) return;
+  const Cand c = cands[i];
+  if (cbin(c.score, pre[c.qid]) < pre[c.qid].tbin) return;
+  const unsigned int slot = atomicAdd(count, 1u);
+  out[slot] = c;
+  for (int t = 0; t < QM; ++t) out_ids[(u64)slot * QM + t] = ids[(u64)i * QM + t];
 }
 
 // ------------------------------------------------------------------
@@ -567,14 +640,25 @@ struct MLevel {
 };
 
 struct MQHost {
+  bool active = false;  // the slot holds a query
+  bool done = true;     // the query needs no more steps
+  bool rooted = false;  // its unit subgraphs are in place
+  int error = 0;
+  std::string errmsg;
   uint32_t k = 1;
   std::vector<MLevel> stack;
-  bool rooted = false, done = false, impossible = false;
   long long theta = LLONG_MIN;
+  long long top_seen = LLONG_MIN;  // best score ever offered (bounds the top-k)
   uint32_t hdr_cap = 0;
+  uint64_t t_admit = 0, steps = 0, launches = 0, expand_ns = 0, peak_bytes = 0;
   int plan = 0;
   uint32_t new_begin = 0;
   int seg = -1;
+};
+
+struct MSlotTopk {
+  PoolBuf<long long> score;
+  PoolBuf<unsigned int> len, ids;
 };
 
 struct MStepLayout {
@@ -602,32 +686,37 @@ struct MStepLayout {
 
 struct MatchEngine {
   Graph &g;
-  const QueryOpts &o;
+  QueryOpts o;
   hipStream_t s;
-  uint32_t nq = 0;
+  bool server_mode = false;
+  uint32_t nq = 0;  // slots
   std::vector<MQHost> qh;
   std::vector<MPlan> plans;
   std::vector<MCfg> cfg;
-  DevBuf<MPlan> d_plans;
-  DevBuf<uint64_t> d_lab_off;
-  DevBuf<MRec> hdr, batch, temp;
-  DevBuf<MCtr> d_ctr;
-  DevBuf<QRes> d_res;
-  DevBuf<uint32_t> d_k;
-  DevBuf<long long> tk_score;
-  DevBuf<unsigned int> tk_len, tk_ids;
-  DevBuf<Cand> cands;
-  DevBuf<uint32_t> cand_ids;
-  DevBuf<unsigned int> d_hist;
-  DevBuf<u64> d_hcost;
-  DevBuf<unsigned char> d_step;
+  std::vector<std::unique_ptr<MSlotTopk>> tk;
+  PoolBuf<MPlan> d_plans;
+  PoolBuf<uint64_t> d_lab_off;
+  PoolBuf<MRec> hdr, batch, temp;
+  PoolBuf<MCtr> d_ctr;
+  PoolBuf<QRes> d_res;
+  PoolBuf<uint32_t> d_k, d_rootq;
+  PoolBuf<Cand> cands, cands2;
+  PoolBuf<uint32_t> cand_ids, cand_ids2;
+  PoolBuf<CPre> d_pre;
+  PinBuf<CPre> h_pre;
+  PoolBuf<unsigned int> d_chist, d_ccount;
+  PinBuf<unsigned int> h_ccount;
+  PoolBuf<unsigned int> d_hist;
+  PoolBuf<u64> d_hcost;
+  PoolBuf<unsigned char> d_step;
   PinBuf<unsigned char> h_step;
   PinBuf<QRes> h_res;
-  std::vector<MCtr> h_ctr;
+  PinBuf<MCtr> h_ctr;
+  PinBuf<uint32_t> h_k, h_rootq;
+  PinBuf<MPlan> h_plan;
   std::unique_ptr<MStepLayout> L;
   uint32_t batch_cap = 0, cand_cap = 0, B = 0;
   u64 step_children = 0;
-  uint64_t steps = 0, launches = 0, expand_ns = 0, peak_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   MatchEngine(Graph &g_, const QueryOpts &o_) : g(g_), o(o_), s(o_.stream ? o_.stream : g_.stream) {}
@@ -654,72 +743,74 @@ struct MatchEngine {
     return (T *)(d_step.p + off);
   }
 
-  void setup(const std::vector<const nuri_pattern *> &ps, const std::vector<uint32_t> &ks) {
-    nq = (uint32_t)ps.size();
-    qh.resize(nq);
-    plans.resize(nq);
-    cfg.resize(nq);
+  void fail(uint32_t i, int code, const std::string &msg) {
+    if (!server_mode) throw Error{code, msg};
+    qh[i].error = code;
+    qh[i].errmsg = msg;
+    qh[i].done = true;
+  }
+
+  void setup(uint32_t slots) {
+    nq = slots;
+    qh.assign(nq, MQHost{});
+    plans.assign(nq, MPlan{});
+    cfg.assign(nq, MCfg{});
+    tk.clear();
+    for (uint32_t i = 0; i < nq; ++i) tk.emplace_back(new MSlotTopk);
     L.reset(new MStepLayout(nq));
-    for (uint32_t i = 0; i < nq; ++i) {
-      plan_pattern(g, *ps[i], ks[i], plans[i]);
-      qh[i].k = ks[i];
-      qh[i].impossible = plans[i].rest0 == LLONG_MIN / 4;
-      qh[i].done = qh[i].impossible;
-    }
-    u64 per_q = o.frontier_budget / nq;
+    const u64 per_q = o.frontier_budget / nq;
     u64 hdr_per_q = std::max<u64>(4096, per_q / sizeof(MRec));
     hdr_per_q = std::min<u64>(hdr_per_q, 0x7FFFFFFFull);
-    hdr.alloc(hdr_per_q * nq);
+    hdr.alloc(g.pool, hdr_per_q * nq);
     for (uint32_t i = 0; i < nq; ++i) {
       qh[i].hdr_cap = (uint32_t)hdr_per_q;
       cfg[i].hdr = hdr.p + (u64)i * hdr_per_q;
       cfg[i].hdr_cap = (uint32_t)hdr_per_q;
       cfg[i].out_hdr = 0;
     }
-    d_plans.alloc(nq);
-    NURI_HIP(hipMemcpyAsync(d_plans.p, plans.data(), nq * sizeof(MPlan), hipMemcpyHostToDevice, s));
-    d_lab_off.alloc(NURI_MAX_LABELS + 1);
+    d_plans.alloc(g.pool, nq);
+    h_plan.alloc(1);
+    d_lab_off.alloc(g.pool, NURI_MAX_LABELS + 1);
     NURI_HIP(hipMemcpyAsync(d_lab_off.p, g.h_lab_off.data(), (NURI_MAX_LABELS + 1) * 8,
                             hipMemcpyHostToDevice, s));
-    u64 tk_total = 0;
-    for (uint32_t i = 0; i < nq; ++i) tk_total += ks[i];
-    tk_score.alloc(2 * tk_total);
-    tk_len.alloc(2 * tk_total);
-    tk_ids.alloc(2 * tk_total * QM);
+    NURI_HIP(hipStreamSynchronize(s));  // the host vector is not pinned
     h_res.alloc(nq);
-    u64 tko = 0;
+    h_ctr.alloc(nq);
+    h_k.alloc(nq);
+    h_rootq.alloc(nq);
     for (uint32_t i = 0; i < nq; ++i) {
-      QRes &R = h_res.p[i];
-      R.theta = LLONG_MIN;
-      R.tk_n = 0;
-      R.cur = 0;
-      for (int b = 0; b < 2; ++b) {
-        R.tk_score[b] = tk_score.p + 2 * tko + (u64)b * ks[i];
-        R.tk_len[b] = tk_len.p + 2 * tko + (u64)b * ks[i];
-        R.tk_ids[b] = tk_ids.p + (2 * tko + (u64)b * ks[i]) * QM;
-      }
-      tko += ks[i];
+      memset(&h_res.p[i], 0, sizeof(QRes));
+      h_res.p[i].theta = LLONG_MIN;
+      h_k.p[i] = 1;
     }
-    d_ctr.alloc(nq);
-    d_res.alloc(nq);
-    d_k.alloc(nq);
+    d_ctr.alloc(g.pool, nq);
+    d_res.alloc(g.pool, nq);
+    d_k.alloc(g.pool, nq);
+    d_rootq.alloc(g.pool, nq);
     NURI_HIP(hipMemcpyAsync(d_res.p, h_res.p, nq * sizeof(QRes), hipMemcpyHostToDevice, s));
-    NURI_HIP(hipMemcpyAsync(d_k.p, ks.data(), nq * 4, hipMemcpyHostToDevice, s));
+    NURI_HIP(hipMemcpyAsync(d_k.p, h_k.p, nq * 4, hipMemcpyHostToDevice, s));
     NURI_HIP(hipMemsetAsync(d_ctr.p, 0, nq * sizeof(MCtr), s));
-    h_ctr.assign(nq, MCtr{});
     B = o.batch_B ? o.batch_B : 16384;
     step_children = std::max<u64>(1ull << 16, std::min<u64>(o.frontier_budget / 8 / sizeof(MRec),
                                                             8ull << 20));
     cand_cap = (uint32_t)std::min<u64>(step_children, 1ull << 22);
     batch_cap = (uint32_t)std::min<u64>((u64)nq * B, 1u << 24);
-    batch.alloc(batch_cap);
-    cands.alloc(cand_cap);
-    cand_ids.alloc((u64)cand_cap * QM);
-    d_hist.alloc((u64)nq * kBins);
-    d_hcost.alloc((u64)nq * kBins);
+    batch.alloc(g.pool, batch_cap);
+    cands.alloc(g.pool, cand_cap);
+    cand_ids.alloc(g.pool, (u64)cand_cap * QM);
+    cands2.alloc(g.pool, cand_cap);
+    cand_ids2.alloc(g.pool, (u64)cand_cap * QM);
+    d_pre.alloc(g.pool, nq);
+    h_pre.alloc(nq);
+    d_chist.alloc(g.pool, (u64)nq * kBins);
+    NURI_HIP(hipMemsetAsync(d_chist.p, 0, d_chist.bytes(), s));
+    d_ccount.alloc(g.pool, 1);
+    h_ccount.alloc(1);
+    d_hist.alloc(g.pool, (u64)nq * kBins);
+    d_hcost.alloc(g.pool, (u64)nq * kBins);
     NURI_HIP(hipMemsetAsync(d_hist.p, 0, d_hist.bytes(), s));
     NURI_HIP(hipMemsetAsync(d_hcost.p, 0, d_hcost.bytes(), s));
-    d_step.alloc(L->total);
+    d_step.alloc(g.pool, L->total);
     h_step.alloc(L->total);
     if (o.profile) {
       NURI_HIP(hipEventCreate(&ev0));
@@ -727,10 +818,54 @@ struct MatchEngine {
     }
   }
 
+  // start a query in a free slot (its unit subgraphs are made on the next step)
+  void admit(uint32_t i, const nuri_pattern &pt, uint32_t k) {
+    MPlan P;
+    plan_pattern(g, pt, k, P);  // throws on an invalid pattern
+    MQHost &Q = qh[i];
+    Q = MQHost{};
+    Q.active = true;
+    Q.k = k;
+    Q.hdr_cap = cfg[i].hdr_cap;
+    Q.t_admit = now_ns();
+    Q.done = P.rest0 == LLONG_MIN / 4;  // some pattern edge has no data edge
+    Q.rooted = Q.done;
+    plans[i] = P;
+    *h_plan.p = P;
+    NURI_HIP(hipMemcpyAsync(&d_plans.p[i], h_plan.p, sizeof(MPlan), hipMemcpyHostToDevice, s));
+    MSlotTopk &T = *tk[i];
+    T.score.alloc(g.pool, 2ull * k);
+    T.len.alloc(g.pool, 2ull * k);
+    T.ids.alloc(g.pool, 2ull * k * QM);
+    QRes &R = h_res.p[i];
+    R.theta = LLONG_MIN;
+    R.tk_n = 0;
+    R.cur = 0;
+    for (int b = 0; b < 2; ++b) {
+      R.tk_score[b] = T.score.p + (u64)b * k;
+      R.tk_len[b] = T.len.p + (u64)b * k;
+      R.tk_ids[b] = T.ids.p + (u64)b * k * QM;
+    }
+    h_k.p[i] = k;
+    NURI_HIP(hipMemcpyAsync(&d_res.p[i], &h_res.p[i], sizeof(QRes), hipMemcpyHostToDevice, s));
+    NURI_HIP(hipMemcpyAsync(&d_k.p[i], &h_k.p[i], 4, hipMemcpyHostToDevice, s));
+    NURI_HIP(hipMemsetAsync(&d_ctr.p[i], 0, sizeof(MCtr), s));
+    NURI_HIP(hipStreamSynchronize(s));  // h_plan is reused by the next admission
+  }
+
+  bool slot_free(uint32_t i) const { return !qh[i].active; }
+  bool finished(uint32_t i) const { return qh[i].active && qh[i].done; }
+  bool any_live() const {
+    for (auto &Q : qh)
+      if (Q.active && !Q.done) return true;
+    return false;
+  }
+
   void upload_step() {
     for (uint32_t i = 0; i < nq; ++i) {
       cfg[i].out_hdr = qh[i].new_begin;
       sms()[i].out_max_bound = LLONG_MIN;
+      sms()[i].cand_max = LLONG_MIN;
     }
     memcpy(h_step.p + L->cfg, cfg.data(), nq * sizeof(MCfg));
     memset(h_step.p + L->taken, 0, 8ull * nq);
@@ -742,26 +877,34 @@ struct MatchEngine {
     NURI_HIP(hipStreamSynchronize(s));
   }
 
-  // every query's unit subgraphs become its first level, sorted by nothing:
-  // the select step orders them by bound
+  // unit subgraphs of newly admitted queries become their first level,
+  // unsorted: the select step orders them by bound
   void make_roots() {
+    uint32_t n = 0;
+    for (uint32_t i = 0; i < nq; ++i)
+      if (qh[i].active && !qh[i].rooted) h_rootq.p[n++] = i;
+    if (!n) return;
     memset(h_step.p, 0, L->cfg);
-    for (uint32_t i = 0; i < nq; ++i) qh[i].new_begin = 0;
+    for (uint32_t t = 0; t < n; ++t) qh[h_rootq.p[t]].new_begin = 0;
     upload_step();
+    NURI_HIP(hipMemcpyAsync(d_rootq.p, h_rootq.p, n * 4, hipMemcpyHostToDevice, s));
     uint32_t maxn = 1;
     for (int l = 0; l < NURI_MAX_LABELS; ++l)
       maxn = std::max<uint32_t>(maxn, (uint32_t)(g.h_lab_off[l + 1] - g.h_lab_off[l]));
     const uint32_t bx = std::min<uint32_t>((maxn + 255) / 256, 2048);
-    hipLaunchKernelGGL(k_match_roots, dim3(bx, nq), dim3(256), 0, s, view(), d_plans.p,
-                       d_lab_off.p, dev<MCfg>(L->cfg), dev<MStep>(L->ms));
+    hipLaunchKernelGGL(k_match_roots, dim3(bx, n), dim3(256), 0, s, view(), d_plans.p,
+                       d_lab_off.p, dev<MCfg>(L->cfg), dev<MStep>(L->ms), d_rootq.p);
     NURI_HIP(hipGetLastError());
     read_step();
-    for (uint32_t i = 0; i < nq; ++i) {
+    for (uint32_t t = 0; t < n; ++t) {
+      const uint32_t i = h_rootq.p[t];
       MQHost &Q = qh[i];
       const MStep &c = sms()[i];
-      if (c.overflow) throw Error{NURI_EBUDGET, "frontier budget too small for the unit subgraphs"};
       Q.rooted = true;
-      if (Q.done) continue;
+      if (c.overflow) {
+        fail(i, NURI_EBUDGET, "frontier budget too small for the unit subgraphs");
+        continue;
+      }
       if (c.n_out) {
         MLevel Lv;
         Lv.begin = 0;
@@ -784,8 +927,9 @@ struct MatchEngine {
     max_count = 0;
     any_sel = false;
     uint32_t live = 0;
-    for (auto &Q : qh) live += !Q.done;
+    for (auto &Q : qh) live += Q.active && !Q.done;
     if (!live) return false;
+    const uint64_t now = o.deadline_ns ? now_ns() : 0;
     const u64 share = std::max<u64>(step_children / live, 1);
     u64 left = step_children, left_cand = cand_cap;
     bool any = false;
@@ -793,7 +937,11 @@ struct MatchEngine {
       MQHost &Q = qh[i];
       Q.plan = 0;
       Q.seg = -1;
-      if (Q.done) continue;
+      if (!Q.active || Q.done) continue;
+      if (o.deadline_ns && now - Q.t_admit > o.deadline_ns) {
+        fail(i, NURI_ETIMEOUT, "query deadline passed");
+        continue;
+      }
       while (!Q.stack.empty() && Q.stack.back().count == 0) Q.stack.pop_back();
       if (Q.stack.empty()) {
         Q.done = true;
@@ -803,10 +951,12 @@ struct MatchEngine {
       const u64 free_h = Q.hdr_cap - (u64)(Lv.begin + Lv.count);
       const uint32_t depth = (uint32_t)Q.stack.size();  // records at this level match `depth` vertices
       const bool to_leaves = depth + 1 == plans[i].q;   // children are complete matches
-      u64 lim = std::min<u64>(std::min(left, share), to_leaves ? left_cand : free_h);
+      const u64 lim = std::min<u64>(std::min(left, share), to_leaves ? left_cand : free_h);
       const u64 rec = std::max<u64>(1, Lv.maxcost);
-      if ((to_leaves ? cand_cap : free_h) < rec)
-        throw Error{NURI_EBUDGET, "frontier budget exhausted"};
+      if ((to_leaves ? cand_cap : free_h) < rec) {
+        fail(i, NURI_EBUDGET, "frontier budget exhausted");
+        continue;
+      }
       if (lim < rec) continue;
       const uint32_t room = batch_cap - batch_ub;
       if (room == 0) continue;
@@ -841,8 +991,9 @@ struct MatchEngine {
       any = true;
     }
     if (!any)
-      for (auto &Q : qh)
-        if (!Q.done) throw Error{NURI_EBUDGET, "frontier budget too small to make progress"};
+      for (uint32_t i = 0; i < nq; ++i)
+        if (qh[i].active && !qh[i].done)
+          fail(i, NURI_EBUDGET, "frontier budget too small to make progress");
     return any;
   }
 
@@ -853,7 +1004,7 @@ struct MatchEngine {
     MStep *dms = dev<MStep>(L->ms);
     MCfg *dcfg = dev<MCfg>(L->cfg);
     MSeg *dseg = dev<MSeg>(L->seg);
-    if (temp_need && temp.n < temp_need) temp.alloc(temp_need * 2);
+    if (temp_need && temp.n < temp_need) temp.alloc(g.pool, temp_need * 2);
     const uint32_t bx = std::max(1u, std::min<uint32_t>((max_count + 255) / 256, 2048));
     if (any_sel) {
       hipLaunchKernelGGL(k_msel_hist, dim3(std::min(bx, 512u), nseg), dim3(256), 0, s, dseg, dcfg,
@@ -878,20 +1029,24 @@ struct MatchEngine {
                        d_ctr.p, d_res.p, cands.p, cand_ids.p, cand_cap);
     NURI_HIP(hipGetLastError());
     if (o.profile) NURI_HIP(hipEventRecord(ev1, s));
-    launches++;
     read_step();
+    uint64_t ens = 0;
     if (o.profile) {
       float ms = 0;
       NURI_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-      expand_ns += (uint64_t)(ms * 1e6);
+      ens = (uint64_t)(ms * 1e6);
     }
-    steps++;
-    u64 live = 0;
     for (uint32_t i = 0; i < nq; ++i) {
       MQHost &Q = qh[i];
-      const MStep &c = sms()[i];
-      if (c.overflow) throw Error{NURI_EBUDGET, "frontier overflow (internal accounting error)"};
       if (!Q.plan) continue;
+      const MStep &c = sms()[i];
+      Q.steps++;
+      Q.launches++;
+      Q.expand_ns += ens;
+      if (c.overflow) {
+        fail(i, NURI_EBUDGET, "frontier overflow (internal accounting error)");
+        continue;
+      }
       MLevel &Lv = Q.stack.back();
       Lv.count = sseg()[Q.seg].take_all ? 0 : c.n_kept;
       if (c.n_out) {
@@ -904,88 +1059,133 @@ struct MatchEngine {
         Q.stack.push_back(N);
       }
       const MLevel &T = Q.stack.back();
-      live += (u64)(T.begin + T.count) * sizeof(MRec);
+      Q.peak_bytes = std::max<u64>(Q.peak_bytes, (u64)(T.begin + T.count) * sizeof(MRec));
     }
-    peak_bytes = std::max<uint64_t>(peak_bytes, live);
-    // complete matches -> top-k merge in chunks (the threshold rises between chunks)
-    const uint32_t ncand = sh()->leaf_count;
-    if (ncand > cand_cap) throw Error{NURI_EBUDGET, "candidate buffer overflow (internal)"};
-    if (ncand) {
-      uint32_t kmax = 0;
-      for (auto &Q : qh) kmax = std::max(kmax, Q.k);
-      const uint32_t mx = (kmax + kCandChunk + 255) / 256;
-      for (uint32_t f = 0; f < ncand; f += kCandChunk) {
-        const uint32_t cnt = std::min<uint32_t>(kCandChunk, ncand - f);
-        // the merge kernels read a chunk through StepHdr::cand_count
-        NURI_HIP(hipMemcpyAsync(&dh->cand_count, &cnt, sizeof(cnt), hipMemcpyHostToDevice, s));
-        hipLaunchKernelGGL(k_merge_rank, dim3(mx, nq), dim3(256), 0, s, cands.p + f, dh,
-                           cand_ids.p + (u64)f * QM, (uint32_t)QM, d_res.p, d_k.p);
-        NURI_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_merge_finish, dim3(nq), dim3(256), 0, s, cands.p + f, dh, d_res.p,
-                           d_k.p);
-        NURI_HIP(hipGetLastError());
-        NURI_HIP(hipStreamSynchronize(s));  // `cnt` lives on this stack frame
-      }
-      NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
-      NURI_HIP(hipStreamSynchronize(s));
-      for (uint32_t i = 0; i < nq; ++i) qh[i].theta = h_res.p[i].theta;
-    }
+    merge_candidates(dh);
   }
 
-  void run() {
+  // complete matches -> top-k merge in chunks (the threshold rises between chunks)
+  void merge_candidates(StepHdr *dh) {
+    uint32_t ncand = sh()->leaf_count;
+    if (ncand > cand_cap) throw Error{NURI_EBUDGET, "candidate buffer overflow (internal)"};
+    if (!ncand) return;
+    uint32_t kmax = 0;
+    for (auto &Q : qh)
+      if (Q.active) kmax = std::max(kmax, Q.k);
+    const Cand *mc = cands.p;
+    const uint32_t *mids = cand_ids.p;
+    if (ncand > kCandChunk) {
+      // prefilter by score: keep, per query, the candidates in score bins
+      // at or above the bin of the k-th best among candidates and top-k
+      for (uint32_t i = 0; i < nq; ++i) {
+        const MStep &c = sms()[i];
+        CPre &P = h_pre.p[i];
+        P.top = c.cand_n ? c.cand_max : 0;
+        // the current top-k can hold higher scores than this step's best
+        if (qh[i].active && h_res.p[i].tk_n) P.top = std::max<long long>(P.top, qh[i].top_seen);
+        const long long floor_s = qh[i].theta == LLONG_MIN ? 0 : qh[i].theta;
+        const long long span = std::max<long long>(0, P.top - floor_s);
+        uint32_t shift = 0;
+        while ((span >> shift) >= kBins - 1) ++shift;
+        P.shift = shift;
+        P.tbin = 0;
+        if (c.cand_n) qh[i].top_seen = std::max(qh[i].top_seen, c.cand_max);
+      }
+      NURI_HIP(hipMemcpyAsync(d_pre.p, h_pre.p, nq * sizeof(CPre), hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_cand_hist, dim3((ncand + 255) / 256), dim3(256), 0, s, cands.p, ncand,
+                         d_res.p, d_pre.p, d_chist.p);
+      NURI_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_cand_hist_topk, dim3(nq), dim3(256), 0, s, d_res.p, d_pre.p,
+                         d_chist.p);
+      NURI_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_cand_thresh, dim3(nq), dim3(256), 0, s, d_k.p, d_pre.p, d_chist.p);
+      NURI_HIP(hipGetLastError());
+      NURI_HIP(hipMemsetAsync(d_ccount.p, 0, 4, s));
+      hipLaunchKernelGGL(k_cand_compact, dim3((ncand + 255) / 256), dim3(256), 0, s, cands.p,
+                         cand_ids.p, ncand, d_pre.p, cands2.p, cand_ids2.p, d_ccount.p);
+      NURI_HIP(hipGetLastError());
+      NURI_HIP(hipMemcpyAsync(h_ccount.p, d_ccount.p, 4, hipMemcpyDeviceToHost, s));
+      NURI_HIP(hipStreamSynchronize(s));
+      ncand = h_ccount.p[0];
+      mc = cands2.p;
+      mids = cand_ids2.p;
+    } else {
+      for (uint32_t i = 0; i < nq; ++i)
+        if (sms()[i].cand_n) qh[i].top_seen = std::max(qh[i].top_seen, sms()[i].cand_max);
+    }
+    const uint32_t mx = (kmax + kCandChunk + 255) / 256;
+    for (uint32_t f = 0; f < ncand; f += kCandChunk) {
+      h_ccount.p[0] = std::min<uint32_t>(kCandChunk, ncand - f);
+      // the merge kernels read the chunk size through StepHdr::cand_count
+      NURI_HIP(hipMemcpyAsync(&dh->cand_count, h_ccount.p, 4, hipMemcpyHostToDevice, s));
+      hipLaunchKernelGGL(k_merge_rank, dim3(mx, nq), dim3(256), 0, s, mc + f, dh,
+                         mids + (u64)f * QM, (uint32_t)QM, d_res.p, d_k.p);
+      NURI_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_merge_finish, dim3(nq), dim3(256), 0, s, mc + f, dh, d_res.p, d_k.p);
+      NURI_HIP(hipGetLastError());
+      NURI_HIP(hipStreamSynchronize(s));  // the pinned chunk size is rewritten next round
+    }
+    NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
+    NURI_HIP(hipStreamSynchronize(s));
+    for (uint32_t i = 0; i < nq; ++i)
+      if (qh[i].active) qh[i].theta = h_res.p[i].theta;
+  }
+
+  bool step_all() {
     make_roots();
     uint32_t nseg, batch_ub, maxc;
     u64 temp_need;
     bool any_sel;
-    const uint64_t t0 = now_ns();
-    while (plan(nseg, batch_ub, temp_need, maxc, any_sel)) {
-      if (o.deadline_ns && now_ns() - t0 > o.deadline_ns)
-        throw Error{NURI_ETIMEOUT, "query deadline passed"};
-      step(nseg, batch_ub, temp_need, maxc, any_sel);
-    }
+    if (!plan(nseg, batch_ub, temp_need, maxc, any_sel)) return false;
+    step(nseg, batch_ub, temp_need, maxc, any_sel);
+    return true;
   }
 
-  void collect(std::vector<Result> &out, uint64_t wall) {
-    NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
-    NURI_HIP(hipMemcpyAsync(h_ctr.data(), d_ctr.p, nq * sizeof(MCtr), hipMemcpyDeviceToHost, s));
+  void harvest(uint32_t i, Result &res) {
+    MQHost &Q = qh[i];
+    NURI_HIP(hipMemcpyAsync(&h_res.p[i], &d_res.p[i], sizeof(QRes), hipMemcpyDeviceToHost, s));
+    NURI_HIP(hipMemcpyAsync(&h_ctr.p[i], &d_ctr.p[i], sizeof(MCtr), hipMemcpyDeviceToHost, s));
     NURI_HIP(hipStreamSynchronize(s));
-    out.resize(nq);
-    for (uint32_t i = 0; i < nq; ++i) {
-      const QRes &R = h_res.p[i];
-      Result &res = out[i];
-      const uint32_t n = R.tk_n, q = plans[i].q;
-      std::vector<long long> sc(n);
-      std::vector<unsigned int> ids((u64)n * QM);
-      if (n) {
-        NURI_HIP(hipMemcpyAsync(sc.data(), R.tk_score[R.cur], n * 8, hipMemcpyDeviceToHost, s));
-        NURI_HIP(hipMemcpyAsync(ids.data(), R.tk_ids[R.cur], (u64)n * QM * 4,
-                                hipMemcpyDeviceToHost, s));
-        NURI_HIP(hipStreamSynchronize(s));
-      }
-      res.score.assign(sc.begin(), sc.end());
-      res.offset.assign(1, 0);
-      res.ids.clear();
-      for (uint32_t t = 0; t < n; ++t) {
-        res.ids.insert(res.ids.end(), ids.begin() + (u64)t * QM, ids.begin() + (u64)t * QM + q);
-        res.offset.push_back(res.ids.size());
-      }
-      const MCtr &c = h_ctr[i];
-      nuri_stats &st = res.stats;
-      memset(&st, 0, sizeof(st));
-      st.steps = steps;
-      st.popped = c.popped;
-      st.expanded = c.expanded;
-      st.children = c.children;
-      st.pruned_at_pop = c.pruned_pop;
-      st.pruned_at_creation = c.pruned_new;
-      st.leaves = c.leaves;
-      st.offered = c.offered;
-      st.frontier_peak_bytes = peak_bytes;
-      st.logical_bytes = c.logical_bytes;
-      st.expand_launches = launches;
-      st.expand_ns = expand_ns;
-      st.wall_ns = wall;
+    const QRes &R = h_res.p[i];
+    const uint32_t n = Q.error ? 0 : R.tk_n, q = plans[i].q;
+    std::vector<long long> sc(n);
+    std::vector<unsigned int> ids((u64)n * QM);
+    if (n) {
+      NURI_HIP(hipMemcpyAsync(sc.data(), R.tk_score[R.cur], n * 8, hipMemcpyDeviceToHost, s));
+      NURI_HIP(hipMemcpyAsync(ids.data(), R.tk_ids[R.cur], (u64)n * QM * 4,
+                              hipMemcpyDeviceToHost, s));
+      NURI_HIP(hipStreamSynchronize(s));
     }
+    res.error = Q.error;
+    res.errmsg = Q.errmsg;
+    res.score.assign(sc.begin(), sc.end());
+    res.offset.assign(1, 0);
+    res.ids.clear();
+    for (uint32_t t = 0; t < n; ++t) {
+      res.ids.insert(res.ids.end(), ids.begin() + (u64)t * QM, ids.begin() + (u64)t * QM + q);
+      res.offset.push_back(res.ids.size());
+    }
+    const MCtr &c = h_ctr.p[i];
+    nuri_stats &st = res.stats;
+    memset(&st, 0, sizeof(st));
+    st.steps = Q.steps;
+    st.popped = c.popped;
+    st.expanded = c.expanded;
+    st.children = c.children;
+    st.pruned_at_pop = c.pruned_pop;
+    st.pruned_at_creation = c.pruned_new;
+    st.leaves = c.leaves;
+    st.offered = c.offered;
+    st.frontier_peak_bytes = Q.peak_bytes;
+    st.logical_bytes = c.logical_bytes;
+    st.expand_launches = Q.launches;
+    st.expand_ns = Q.expand_ns;
+    st.wall_ns = now_ns() - Q.t_admit;
+    Q.active = false;
+    Q.stack.clear();
+    tk[i]->score.release();
+    tk[i]->len.release();
+    tk[i]->ids.release();
   }
 };
 
@@ -993,14 +1193,38 @@ struct MatchEngine {
 
 void run_matches(Graph &g, const std::vector<const nuri_pattern *> &ps,
                  const std::vector<uint32_t> &ks, const QueryOpts &o, std::vector<Result> &out) {
-  const uint64_t t0 = now_ns();
   if (ps.empty()) return;
   if (!g.has_lab) throw Error{NURI_EINVAL, "labelled matching needs vertex labels"};
   if (ps.size() > 65535) throw Error{NURI_EINVAL, "at most 65535 queries per batch"};
   MatchEngine e(g, o);
-  e.setup(ps, ks);
-  e.run();
-  e.collect(out, now_ns() - t0);
+  e.setup((uint32_t)ps.size());
+  for (uint32_t i = 0; i < ps.size(); ++i) e.admit(i, *ps[i], ks[i]);
+  while (e.step_all()) {
+  }
+  out.resize(ps.size());
+  for (uint32_t i = 0; i < ps.size(); ++i) e.harvest(i, out[i]);
 }
+
+// ------------------------------------------------------------------
+// slot interface for the server
+// ------------------------------------------------------------------
+struct MatchSlots::Impl {
+  MatchEngine e;
+  Impl(Graph &g, const QueryOpts &o) : e(g, o) {}
+};
+
+MatchSlots::MatchSlots(Graph &g, const QueryOpts &o, uint32_t slots) : impl(new Impl(g, o)) {
+  if (!g.has_lab) throw Error{NURI_EINVAL, "labelled matching needs vertex labels"};
+  impl->e.server_mode = true;
+  impl->e.setup(slots);
+}
+MatchSlots::~MatchSlots() = default;
+uint32_t MatchSlots::slots() const { return impl->e.nq; }
+bool MatchSlots::free(uint32_t i) const { return impl->e.slot_free(i); }
+bool MatchSlots::finished(uint32_t i) const { return impl->e.finished(i); }
+bool MatchSlots::live() const { return impl->e.any_live(); }
+void MatchSlots::admit(uint32_t i, const nuri_pattern &p, uint32_t k) { impl->e.admit(i, p, k); }
+bool MatchSlots::step() { return impl->e.step_all(); }
+void MatchSlots::harvest(uint32_t i, Result &r) { impl->e.harvest(i, r); }
 
 }  // namespace nuri

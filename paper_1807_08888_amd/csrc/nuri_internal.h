@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -53,6 +55,75 @@ struct DevBuf {
     release();
     if (count == 0) count = 1;
     NURI_HIP(hipMalloc(&p, count * sizeof(T)));
+    n = count;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+};
+
+// Device memory kept for reuse by later queries on the same graph: query
+// workspaces (frontier arenas, buffers) are taken from here and returned,
+// so repeated queries do not pay for hipMalloc/hipFree of large blocks.
+struct MemPool {
+  std::mutex mu;
+  std::multimap<size_t, void *> free_blocks;  // size -> block
+  ~MemPool() { trim(); }
+  void *get(size_t bytes) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      auto it = free_blocks.lower_bound(bytes);
+      if (it != free_blocks.end() && it->first <= 2 * bytes + (64ull << 20)) {
+        void *p = it->second;
+        free_blocks.erase(it);
+        return p;
+      }
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      trim();
+      e = hipMalloc(&p, bytes);
+    }
+    if (e != hipSuccess)
+      throw Error{e == hipErrorOutOfMemory ? NURI_ENOMEM : NURI_EDEVICE,
+                  std::string("hipMalloc: ") + hipGetErrorString(e)};
+    return p;
+  }
+  void put(void *p, size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu);
+    free_blocks.emplace(bytes, p);
+  }
+  void trim() {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto &kv : free_blocks) (void)hipFree(kv.second);
+    free_blocks.clear();
+  }
+};
+
+// Device buffer borrowed from a graph's MemPool.  The block returns to the
+// pool when the buffer is released; block sizes are remembered exactly so
+// a later query asking for the same size reuses it.
+template <class T>
+struct PoolBuf {
+  MemPool *pool = nullptr;
+  T *p = nullptr;
+  size_t n = 0, cap_bytes = 0;
+  PoolBuf() = default;
+  PoolBuf(const PoolBuf &) = delete;
+  PoolBuf &operator=(const PoolBuf &) = delete;
+  ~PoolBuf() { release(); }
+  void release() {
+    if (p && pool) pool->put(p, cap_bytes);
+    p = nullptr;
+    n = 0;
+    cap_bytes = 0;
+  }
+  void alloc(MemPool &mp, size_t count) {
+    release();
+    if (count == 0) count = 1;
+    pool = &mp;
+    cap_bytes = count * sizeof(T);
+    p = (T *)mp.get(cap_bytes);
     n = count;
   }
   size_t bytes() const { return n * sizeof(T); }
@@ -118,6 +189,8 @@ struct Graph {
   DevBuf<uint32_t> oplus;
   DevBuf<int32_t> wloc;
 
+  MemPool pool;  // query workspaces kept between queries
+
   uint64_t device_bytes() const;
   Graph() = default;
   Graph(const Graph &) = delete;
@@ -133,6 +206,8 @@ Graph *load_graph(const nuri_csr *csr, hipStream_t stream);
 // results
 // ------------------------------------------------------------------
 struct Result {
+  int error = 0;  // nuri_status of a failed query (served queries only)
+  std::string errmsg;
   std::vector<int64_t> score;
   std::vector<uint64_t> offset;
   std::vector<uint32_t> ids;
@@ -143,6 +218,7 @@ struct QueryOpts {
   uint64_t frontier_budget = 8ull << 30;
   uint32_t batch_B = 0;
   uint32_t root_batch = 0;
+  uint32_t bound = 0;  // 0 auto, 1 Carraghan-Pardalos only, 2 colour classes always
   uint64_t deadline_ns = 0;
   bool profile = false;
   hipStream_t stream = nullptr;
@@ -156,9 +232,47 @@ uint64_t now_ns();
 void run_cliques(Graph &g, const std::vector<uint32_t> &ks, const std::vector<int> &wfs,
                  const QueryOpts &o, std::vector<Result> &out);
 
+// Query slots for continuous batching: queries are admitted into free
+// slots between steps, every step serves all live slots, and finished
+// slots are harvested.
+struct CliqueSlots {
+  struct Impl;
+  std::unique_ptr<Impl> impl;
+  CliqueSlots(Graph &g, const QueryOpts &o, uint32_t slots);
+  ~CliqueSlots();
+  uint32_t slots() const;
+  bool free(uint32_t i) const;
+  bool finished(uint32_t i) const;
+  bool live() const;
+  void admit(uint32_t i, uint32_t k, int kind);  // throws on invalid arguments
+  bool step();                                    // false when no slot has work
+  void harvest(uint32_t i, Result &r);
+};
+
+struct MatchSlots {
+  struct Impl;
+  std::unique_ptr<Impl> impl;
+  MatchSlots(Graph &g, const QueryOpts &o, uint32_t slots);
+  ~MatchSlots();
+  uint32_t slots() const;
+  bool free(uint32_t i) const;
+  bool finished(uint32_t i) const;
+  bool live() const;
+  void admit(uint32_t i, const nuri_pattern &p, uint32_t k);  // throws on invalid arguments
+  bool step();
+  void harvest(uint32_t i, Result &r);
+};
+
 // matching engine
-struct PatternPlan;
 void run_matches(Graph &g, const std::vector<const nuri_pattern *> &ps,
                  const std::vector<uint32_t> &ks, const QueryOpts &o, std::vector<Result> &out);
 
 }  // namespace nuri
+
+// the opaque handles of the C ABI
+struct nuri_graph {
+  nuri::Graph *g;
+};
+struct nuri_result {
+  nuri::Result r;
+};

@@ -1,18 +1,306 @@
-// Continuous-batching server (placeholder until the serving loop lands).
+// Continuous-batching server over one resident graph.
+//
+// The paper's communication component takes a computation from the user
+// and returns its result set (Section 5); here many computations are live
+// at once.  A worker thread owns two slot engines (cliques, matching), each
+// holding up to max_slots queries with an equal share of the frontier
+// memory.  Between steps it admits queued queries into free slots (a slot
+// is a unit of frontier memory), runs one step for every live query of
+// each engine -- so the work of all of them shares every launch -- and
+// harvests finished slots.  A query's result does not depend on what else
+// is in flight: every search is exact.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <thread>
+#include <unordered_map>
+
 #include "nuri_internal.h"
 
+
+namespace nuri {
+
+struct Served {
+  uint64_t ticket = 0;
+  uint32_t kind = 0, k = 0;
+  int wf = 0;
+  std::vector<uint8_t> labels;
+  std::vector<uint32_t> edges;
+  uint64_t t_submit = 0;
+};
+
+struct Server {
+  Graph *g = nullptr;
+  QueryOpts opts;
+  uint32_t max_slots = 0;
+  std::unique_ptr<CliqueSlots> cs;
+  std::unique_ptr<MatchSlots> ms;
+  std::vector<uint64_t> c_ticket, m_ticket;      // ticket per slot (0 = free)
+  std::unordered_map<uint64_t, uint64_t> submit_t;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Served> queue;
+  std::unordered_map<uint64_t, Result> done;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  int fatal = 0;
+  std::string fatal_msg;
+  std::thread worker;
+
+  void finish(uint64_t ticket, Result &&r) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = submit_t.find(ticket);
+    if (it != submit_t.end()) {
+      r.stats.wall_ns = now_ns() - it->second;  // completion - arrival
+      submit_t.erase(it);
+    }
+    done.emplace(ticket, std::move(r));
+  }
+
+  void fail_ticket(uint64_t ticket, int code, const std::string &msg) {
+    Result r;
+    r.error = code;
+    r.errmsg = msg;
+    r.offset.assign(1, 0);
+    finish(ticket, std::move(r));
+  }
+
+  // move queued queries into free slots, in arrival order per engine
+  void admit() {
+    std::deque<Served> take;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      uint32_t cfree = 0, mfree = 0;
+      for (auto t : c_ticket) cfree += t == 0;
+      for (auto t : m_ticket) mfree += t == 0;
+      std::deque<Served> keep;
+      while (!queue.empty()) {
+        Served q = std::move(queue.front());
+        queue.pop_front();
+        if (q.kind == 0 && cfree) {
+          --cfree;
+          take.push_back(std::move(q));
+        } else if (q.kind == 1 && mfree) {
+          --mfree;
+          take.push_back(std::move(q));
+        } else {
+          keep.push_back(std::move(q));
+        }
+      }
+      queue.swap(keep);
+    }
+    for (auto &q : take) {
+      try {
+        if (q.kind == 0) {
+          uint32_t i = 0;
+          while (c_ticket[i]) ++i;
+          cs->admit(i, q.k, q.wf);
+          c_ticket[i] = q.ticket;
+        } else {
+          if (!ms) throw Error{NURI_EINVAL, "labelled matching needs vertex labels"};
+          uint32_t i = 0;
+          while (m_ticket[i]) ++i;
+          nuri_pattern p{(uint32_t)q.labels.size(), (uint32_t)(q.edges.size() / 2),
+                         q.labels.data(), q.edges.data()};
+          ms->admit(i, p, q.k);
+          m_ticket[i] = q.ticket;
+        }
+      } catch (const Error &e) {
+        if (e.code == NURI_EINVAL) {
+          fail_ticket(q.ticket, e.code, e.msg);
+        } else {
+          throw;
+        }
+      }
+    }
+  }
+
+  void harvest() {
+    for (uint32_t i = 0; i < c_ticket.size(); ++i)
+      if (c_ticket[i] && cs->finished(i)) {
+        Result r;
+        cs->harvest(i, r);
+        finish(c_ticket[i], std::move(r));
+        c_ticket[i] = 0;
+      }
+    for (uint32_t i = 0; i < m_ticket.size(); ++i)
+      if (m_ticket[i] && ms->finished(i)) {
+        Result r;
+        ms->harvest(i, r);
+        finish(m_ticket[i], std::move(r));
+        m_ticket[i] = 0;
+      }
+  }
+
+  bool busy() const {
+    for (auto t : c_ticket)
+      if (t) return true;
+    for (auto t : m_ticket)
+      if (t) return true;
+    return false;
+  }
+
+  void loop() {
+    try {
+      for (;;) {
+        {
+          std::unique_lock<std::mutex> lk(mu);
+          cv.wait(lk, [&] { return stop || !queue.empty() || busy(); });
+          if (stop) return;
+        }
+        admit();
+        if (cs && cs->live()) cs->step();
+        if (ms && ms->live()) ms->step();
+        harvest();
+      }
+    } catch (const Error &e) {
+      fail_all(e.code, e.msg);
+    } catch (const std::exception &e) {
+      fail_all(NURI_EDEVICE, e.what());
+    }
+  }
+
+  // a device error ends the server: every pending and live query fails
+  void fail_all(int code, const std::string &msg) {
+    std::vector<uint64_t> tickets;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      fatal = code;
+      fatal_msg = msg;
+      for (auto &q : queue) tickets.push_back(q.ticket);
+      queue.clear();
+    }
+    for (auto t : c_ticket)
+      if (t) tickets.push_back(t);
+    for (auto t : m_ticket)
+      if (t) tickets.push_back(t);
+    for (auto t : tickets) fail_ticket(t, code, msg);
+  }
+};
+
+}  // namespace nuri
+
+using namespace nuri;
+
+struct nuri_server {
+  nuri::Server s;
+};
+
 extern "C" {
-int nuri_server_create(nuri_graph *, uint64_t, uint32_t, nuri_server **) {
-  nuri::set_error("the server is not available in this build");
-  return NURI_EINVAL;
+
+int nuri_server_create(nuri_graph *g, uint64_t frontier_budget_bytes, uint32_t max_slots,
+                       nuri_server **out) {
+  if (!g || !out || max_slots == 0 || max_slots > 4096) {
+    set_error("server needs a graph, an out pointer and 1..4096 slots");
+    return NURI_EINVAL;
+  }
+  try {
+    nuri_opts o{};
+    o.frontier_budget_bytes = frontier_budget_bytes;
+    QueryOpts qo = resolve_opts(*g->g, &o);
+    auto *srv = new nuri_server;
+    Server &S = srv->s;
+    S.g = g->g;
+    S.opts = qo;
+    S.max_slots = max_slots;
+    // the frontier memory is split between the two engines
+    QueryOpts half = qo;
+    half.frontier_budget = g->g->has_lab ? qo.frontier_budget / 2 : qo.frontier_budget;
+    try {
+      S.cs.reset(new CliqueSlots(*g->g, half, max_slots));
+      if (g->g->has_lab) S.ms.reset(new MatchSlots(*g->g, half, max_slots));
+    } catch (...) {
+      delete srv;
+      throw;
+    }
+    S.c_ticket.assign(max_slots, 0);
+    S.m_ticket.assign(S.ms ? max_slots : 0, 0);
+    S.worker = std::thread([&S] { S.loop(); });
+    *out = srv;
+    return NURI_OK;
+  } catch (const Error &e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::exception &e) {
+    set_error(e.what());
+    return NURI_EDEVICE;
+  }
 }
-int nuri_server_submit(nuri_server *, const nuri_query *, uint64_t *) {
-  nuri::set_error("the server is not available in this build");
-  return NURI_EINVAL;
+
+int nuri_server_submit(nuri_server *srv, const nuri_query *q, uint64_t *ticket) {
+  if (!srv || !q || !ticket) {
+    set_error("NULL argument");
+    return NURI_EINVAL;
+  }
+  Server &S = srv->s;
+  Served item;
+  item.kind = q->kind;
+  item.k = q->k;
+  item.wf = (int)q->wf;
+  if (q->kind == 1) {
+    if (!q->p || !q->p->label || (!q->p->edges && q->p->n_edges) || q->p->q > NURI_MAX_PATTERN) {
+      set_error("bad pattern");
+      return NURI_EINVAL;
+    }
+    item.labels.assign(q->p->label, q->p->label + q->p->q);
+    item.edges.assign(q->p->edges, q->p->edges + 2 * q->p->n_edges);
+  } else if (q->kind != 0) {
+    set_error("query kind must be 0 (clique) or 1 (match)");
+    return NURI_EINVAL;
+  }
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    if (S.fatal) {
+      set_error("server stopped after an error: " + S.fatal_msg);
+      return S.fatal;
+    }
+    item.ticket = S.next_ticket++;
+    item.t_submit = now_ns();
+    S.submit_t[item.ticket] = item.t_submit;
+    *ticket = item.ticket;
+    S.queue.push_back(std::move(item));
+  }
+  S.cv.notify_one();
+  return NURI_OK;
 }
-int nuri_server_poll(nuri_server *, uint64_t, nuri_result **) {
-  nuri::set_error("the server is not available in this build");
-  return NURI_EINVAL;
+
+int nuri_server_poll(nuri_server *srv, uint64_t ticket, nuri_result **out) {
+  if (!srv || !out) {
+    set_error("NULL argument");
+    return NURI_EINVAL;
+  }
+  Server &S = srv->s;
+  std::lock_guard<std::mutex> lk(S.mu);
+  auto it = S.done.find(ticket);
+  if (it == S.done.end()) {
+    if (ticket == 0 || ticket >= S.next_ticket) {
+      set_error("unknown ticket");
+      return NURI_EINVAL;
+    }
+    return 0;
+  }
+  Result r = std::move(it->second);
+  S.done.erase(it);
+  if (r.error) {
+    set_error(r.errmsg);
+    return r.error;
+  }
+  auto *res = new nuri_result;
+  res->r = std::move(r);
+  *out = res;
+  return 1;
 }
-void nuri_server_destroy(nuri_server *) {}
+
+void nuri_server_destroy(nuri_server *srv) {
+  if (!srv) return;
+  Server &S = srv->s;
+  {
+    std::lock_guard<std::mutex> lk(S.mu);
+    S.stop = true;
+  }
+  S.cv.notify_all();
+  if (S.worker.joinable()) S.worker.join();
+  delete srv;
 }
+
+}  // extern "C"

@@ -47,8 +47,9 @@ class _Pattern(ctypes.Structure):
 
 class _Opts(ctypes.Structure):
     _fields_ = [("frontier_budget_bytes", ctypes.c_uint64), ("batch_B", ctypes.c_uint32),
-                ("root_batch", ctypes.c_uint32), ("deadline_ns", ctypes.c_uint64),
-                ("profile", ctypes.c_uint32), ("hip_stream", ctypes.c_void_p)]
+                ("root_batch", ctypes.c_uint32), ("bound", ctypes.c_uint32),
+                ("deadline_ns", ctypes.c_uint64), ("profile", ctypes.c_uint32),
+                ("hip_stream", ctypes.c_void_p)]
 
 
 class _Query(ctypes.Structure):
@@ -129,10 +130,10 @@ def _stream_handle(stream) -> Optional[int]:
     return int(stream.cuda_stream)
 
 
-def _opts(frontier_budget_bytes=0, batch_B=0, root_batch=0, deadline_ns=0, profile=False,
-          stream=None) -> _Opts:
-    return _Opts(frontier_budget_bytes, batch_B, root_batch, deadline_ns, int(bool(profile)),
-                 _stream_handle(stream))
+def _opts(frontier_budget_bytes=0, batch_B=0, root_batch=0, bound=0, deadline_ns=0,
+          profile=False, stream=None) -> _Opts:
+    return _Opts(frontier_budget_bytes, batch_B, root_batch, bound, deadline_ns,
+                 int(bool(profile)), _stream_handle(stream))
 
 
 class Result:

@@ -220,3 +220,68 @@ def test_batch_equals_single_queries(nuri):
             assert outs[i].items == want, i
     finally:
         G.close()
+
+
+def _check_maximal_cliques(g, items):
+    """Every item is a clique, maximal in g, with an exact size score; strict order."""
+    rp, col = g.row_ptr.astype(np.int64), g.col
+    keys = [(-s, ids) for s, ids in items]
+    assert keys == sorted(keys) and len(set(keys)) == len(keys)
+    for s, ids in items:
+        C = np.array(ids, dtype=np.int64)
+        assert s == len(C)
+        assert np.all(C[1:] > C[:-1])
+        for u in C:
+            row = col[rp[u]:rp[u + 1]]
+            others = C[C != u]
+            assert np.isin(others, row).all(), "not a clique"
+        # maximal: no vertex outside C is adjacent to all of C
+        u0 = C[np.argmin(rp[C + 1] - rp[C])]
+        cand = np.setdiff1d(col[rp[u0]:rp[u0 + 1]].astype(np.int64), C)
+        for x in cand:
+            if np.isin(C, col[rp[x]:rp[x + 1]]).all():
+                raise AssertionError(f"clique extendable by {x}")
+
+
+def test_power_law_generator_small_vs_oracle(nuri):
+    """The power-law workload's generator at n=20,000 (cap 2,000, 20 planted cliques)."""
+    g = synth.chung_lu(n=20000, m_target=4e5, cap=2000.0, n_cliques=20, lo=20, hi=40)
+    _case("chung-lu n=20000 k=100")
+    want, _ = oracle.topk_cliques(g, 100)
+    got = _gpu(nuri, g, 100)
+    assert got.items == want
+
+
+def test_power_law_full_size_properties(nuri):
+    """Power-law workload at full size (n=1M, ~20M edges), k=100, as the benchmark runs it.
+
+    The oracle cannot finish this instance, so the check is: every result is
+    a maximal clique with its exact size, the list is strictly ordered, and
+    the result is identical under different batch sizes.
+    """
+    g = synth.chung_lu()
+    _case("chung-lu full size k=100")
+    G = nuri.Graph.from_synth(g)
+    try:
+        a = nuri.topk_cliques(G, 100)
+        b = nuri.topk_cliques(G, 100, batch_B=4096, root_batch=1024)
+    finally:
+        G.close()
+    assert a.items == b.items
+    assert len(a.items) == 100
+    _check_maximal_cliques(g, a.items)
+
+
+@pytest.mark.parametrize("bound", [0, 1, 2])
+def test_result_independent_of_bound(nuri, bound):
+    """Carraghan-Pardalos only, colour classes always, or automatic: same results."""
+    _case(f"bound={bound}")
+    cases = [synth.gnp(70, 0.7, 3), synth.gnp(300, 0.06, 4),
+             synth.er_planted(n=3000, avg_degree=6.0, n_cliques=1, lo=130, hi=130, master=130)]
+    for i, g in enumerate(cases):
+        synth.add_vertex_weights(g, 1, 9, master=i)
+        for wf in (0, 1):
+            for k in (1, 25):
+                want, _ = oracle.topk_cliques(g, k, weighted=bool(wf))
+                got = _gpu(nuri, g, k, wf, bound=bound)
+                assert got.items == want, (i, wf, k)

@@ -1,0 +1,133 @@
+"""Serving: continuous batching must not change any result.
+
+Queries are submitted to a server with fewer slots than queries (so most
+wait and are admitted while others run) and in staggered waves; every
+served result must equal the same query run alone, and the oracle.
+"""
+import time
+
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nuri():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1807_08888_amd import nuri as N
+    N.lib()
+    return N
+
+
+def _case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def workload(nuri):
+    g = synth.rmat(13)
+    synth.add_vertex_weights(g)
+    synth.add_edge_weights(g)
+    synth.add_zipf_labels(g)
+    queries = []
+    for i in range(18):
+        queries.append({"kind": "clique", "k": synth.log_uniform_k(i, 200), "weight_fn": i % 2})
+    for i in range(12):
+        p = synth.random_pattern(i, q_lo=3, q_hi=6)
+        queries.append({"kind": "match", "k": 10 + (i * 7) % 50, "labels": p.labels,
+                        "edges": p.edges})
+    G = nuri.Graph.from_synth(g)
+    yield g, G, queries
+    G.close()
+
+
+def _alone(nuri, G, q):
+    if q["kind"] == "clique":
+        return nuri.topk_cliques(G, q["k"], q["weight_fn"]).items
+    return nuri.topk_match(G, q["labels"], q["edges"], q["k"]).items
+
+
+def _wait(nuri, S, tickets, timeout=90.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t in out:
+                continue
+            r = S.poll(t)
+            if r is not None:
+                out[t] = r
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"{len(tickets) - len(out)} queries still pending")
+        time.sleep(0.002)
+    return out
+
+
+def test_served_equals_alone_and_oracle(nuri, workload):
+    g, G, queries = workload
+    _case("server: 30 mixed queries, 4 slots per engine")
+    alone = [_alone(nuri, G, q) for q in queries]
+    S = nuri.Server(G, frontier_budget_bytes=4 << 30, max_slots=4)
+    try:
+        tickets = [S.submit(q) for q in queries]
+        res = _wait(nuri, S, tickets)
+    finally:
+        S.close()
+    for i, t in enumerate(tickets):
+        assert res[t].items == alone[i], i
+        assert res[t].stats["wall_ns"] > 0
+    for i in (0, 1, 18, 19):
+        q = queries[i]
+        if q["kind"] == "clique":
+            want, _ = oracle.topk_cliques(g, q["k"], weighted=bool(q["weight_fn"]))
+        else:
+            want, _ = oracle.topk_match(g, q["labels"], q["edges"], q["k"])
+        assert alone[i] == want, i
+
+
+def test_staggered_arrivals(nuri, workload):
+    g, G, queries = workload
+    _case("server: staggered arrivals")
+    alone = {i: _alone(nuri, G, queries[i]) for i in range(0, len(queries), 3)}
+    S = nuri.Server(G, frontier_budget_bytes=4 << 30, max_slots=2)
+    try:
+        tickets = {}
+        for i in sorted(alone):
+            tickets[i] = S.submit(queries[i])
+            time.sleep(0.003)  # later queries arrive while earlier ones run
+        res = _wait(nuri, S, list(tickets.values()))
+    finally:
+        S.close()
+    for i, t in tickets.items():
+        assert res[t].items == alone[i], i
+
+
+def test_invalid_query_fails_alone(nuri, workload):
+    g, G, queries = workload
+    _case("server: invalid query among valid ones")
+    S = nuri.Server(G, frontier_budget_bytes=2 << 30, max_slots=2)
+    try:
+        good = S.submit(queries[0])
+        bad = S.submit({"kind": "clique", "k": 0, "weight_fn": 0})
+        bad2 = S.submit({"kind": "match", "k": 5, "labels": [0, 0, 0], "edges": [(0, 1)]})
+        t0 = time.time()
+        errors = {}
+        while len(errors) < 2 and time.time() - t0 < 30:
+            for t in (bad, bad2):
+                if t in errors:
+                    continue
+                try:
+                    S.poll(t)
+                except nuri.NuriError as e:
+                    errors[t] = e.name
+            time.sleep(0.002)
+        assert errors == {bad: "EINVAL", bad2: "EINVAL"}
+        res = _wait(nuri, S, [good])
+        assert res[good].items == _alone(nuri, G, queries[0])
+    finally:
+        S.close()
