@@ -1,14 +1,21 @@
-"""Benchmark: top-k maximal clique discovery on the power-law workload.
+"""Benchmark: top-k subgraph discovery on one MI355X.
 
-Workload (one "step" = one full top-k query through the HIP engine, inputs
-resident in HBM): Chung-Lu graph, 1,000,000 vertices, ~20M undirected
-edges, degree exponent 2.1, expected degree capped at 20,000, 200 planted
-cliques of 20..40 vertices; top-100 maximal cliques by size.
+Default workload (what the driver runs; one "step" = one full top-k query
+through the HIP engine, inputs resident in HBM): Chung-Lu graph, 1,000,000
+vertices, ~20M undirected edges, degree exponent 2.1, expected degree capped
+at 20,000, 200 planted cliques of 20..40 vertices; top-100 maximal cliques
+by size.  It prints one JSON line with the throughput in expanded subgraphs
+(children created, the paper's candidate-subgraph count) per second, the
+query time, the expansion kernel's roofline figures and the CPU oracle timed
+on a bounded sample of the same workload.
 
-Prints one JSON line with the throughput in expanded subgraphs (children
-created, the paper's candidate-subgraph count) per second, the query time,
-the expansion kernel's roofline figures and the CPU oracle timed on a
-bounded sample of the same workload.
+Other workloads (--workload), each printing one JSON line of its own:
+  rmat_cliques_batched  vertex-weighted top-k cliques, many queries with
+                        log-uniform k in one batch vs one at a time
+  rmat_match_batched    top-50 labelled matching, 128 patterns in one
+                        batch vs one at a time
+  served_mix            Poisson arrivals of a clique/pattern mix into the
+                        continuous-batching server: p50/p99 latency, queries/s
 """
 from __future__ import annotations
 
@@ -54,9 +61,154 @@ def cpu_baseline(g, k: int, seconds: float) -> dict:
                       f"(search capped, {dt:.1f} s, one host core)"}
 
 
+def _rmat(scale, weights=True, labels=True):
+    import synth
+    g = synth.rmat(scale)
+    if weights:
+        synth.add_vertex_weights(g)
+        synth.add_edge_weights(g)
+    if labels:
+        synth.add_zipf_labels(g)
+    return g
+
+
+def bench_rmat_cliques(args, nuri, stream) -> dict:
+    """Many vertex-weighted top-k clique queries (k log-uniform in 1..k_max)."""
+    import synth
+    g = _rmat(args.scale, labels=False)
+    G = nuri.Graph.from_synth(g, stream=stream)
+    ks = [synth.log_uniform_k(i, args.k_max) for i in range(args.queries)]
+    qs = [{"kind": "clique", "k": k, "weight_fn": nuri.SCORE_VERTEX_WEIGHT} for k in ks]
+    nuri.topk_batch(G, qs[:4], stream=stream)  # warm the workspace pool
+    _log(f"graph {G.info()}; {len(qs)} queries, k = {ks}")
+    t = time.perf_counter()
+    outs = nuri.topk_batch(G, qs, stream=stream)
+    tb = time.perf_counter() - t
+    _log(f"batched: {tb:.2f} s")
+    t = time.perf_counter()
+    singles = []
+    for i, k in enumerate(ks):
+        singles.append(nuri.topk_cliques(G, k, nuri.SCORE_VERTEX_WEIGHT, stream=stream).items)
+        _log(f"single {i} k={k}: {time.perf_counter() - t:.2f} s so far")
+    ts = time.perf_counter() - t
+    same = all(outs[i].items == singles[i] for i in range(len(ks)))
+    G.close()
+    return {"metric": "batched top-k queries/s", "value": len(ks) / tb, "unit": "queries/s",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "int64", "data": "synthetic",
+            "config": {"workload": f"rmat{args.scale}_weighted_cliques_{len(ks)}q_k1-{args.k_max}",
+                       "n": g.n, "m": g.m},
+            "one_at_a_time_queries_per_s": len(ks) / ts, "batch_equals_single": same,
+            "children_total": sum(o.stats["children"] for o in outs)}
+
+
+def bench_rmat_match(args, nuri, stream) -> dict:
+    """128 labelled patterns (3..7 vertices), top-50 each, batched vs one at a time."""
+    import synth
+    g = _rmat(args.scale)
+    G = nuri.Graph.from_synth(g, stream=stream)
+    pats = [synth.random_pattern(i) for i in range(args.queries)]
+    qs = [{"kind": "match", "k": 50, "labels": p.labels, "edges": p.edges} for p in pats]
+    nuri.topk_batch(G, qs[:4], stream=stream)
+    _log(f"graph {G.info()}; {len(qs)} patterns")
+    t = time.perf_counter()
+    outs = nuri.topk_batch(G, qs, stream=stream, profile=True)
+    tb = time.perf_counter() - t
+    _log(f"batched: {tb:.2f} s")
+    t = time.perf_counter()
+    singles = []
+    for i, p in enumerate(pats):
+        singles.append(nuri.topk_match(G, p.labels, p.edges, 50, stream=stream).items)
+        if i % 16 == 15:
+            _log(f"single {i}: {time.perf_counter() - t:.2f} s so far")
+    ts = time.perf_counter() - t
+    same = all(outs[i].items == singles[i] for i in range(len(pats)))
+    G.close()
+    return {"metric": "batched top-k queries/s", "value": len(pats) / tb, "unit": "queries/s",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "int64", "data": "synthetic",
+            "config": {"workload": f"rmat{args.scale}_labelled_match_{len(pats)}patterns_top50",
+                       "n": g.n, "m": g.m},
+            "one_at_a_time_queries_per_s": len(pats) / ts, "batch_equals_single": same,
+            "children_total": sum(o.stats["children"] for o in outs)}
+
+
+def bench_served(args, nuri, stream) -> dict:
+    """Poisson arrivals of a 60% weighted-clique / 40% pattern mix into the server."""
+    import random
+    import synth
+    g = _rmat(args.scale)
+    G = nuri.Graph.from_synth(g, stream=stream)
+
+    def query(i):
+        u = synth.unif(synth.stream_seed(synth.MASTER_SEED, 107), i)
+        if u < 0.6:
+            return {"kind": "clique", "k": synth.log_uniform_k(i, args.k_max),
+                    "weight_fn": nuri.SCORE_VERTEX_WEIGHT}
+        p = synth.random_pattern(10_000 + i, q_lo=3, q_hi=8)
+        k = 10 + synth.below(synth.stream_seed(synth.MASTER_SEED, 108), i, 91)
+        return {"kind": "match", "k": k, "labels": p.labels, "edges": p.edges}
+
+    def run(qs, rate):
+        S = nuri.Server(G, max_slots=args.slots)
+        rng = random.Random(1807088880)
+        t0 = time.perf_counter()
+        arrive, tickets, lat, kind_of, st = [], [], {}, {}, {}
+        next_t = t0
+        pending = {}
+        i = 0
+        while i < len(qs) or pending:
+            now = time.perf_counter()
+            while i < len(qs) and (rate is None or now >= next_t):
+                tk = S.submit(qs[i])
+                pending[tk] = now
+                kind_of[tk] = (i, qs[i]["kind"], qs[i]["k"])
+                i += 1
+                if rate is not None:
+                    next_t += rng.expovariate(rate)
+            for tk in list(pending):
+                r = S.poll(tk)
+                if r is not None:
+                    lat[tk] = time.perf_counter() - pending.pop(tk)
+                    st[tk] = r.stats
+                    if len(lat) % 16 == 0:
+                        _log(f"{len(lat)} done")
+            time.sleep(0.0005)
+        S.close()
+        slow = sorted(lat.items(), key=lambda kv: -kv[1])[:5]
+        for t, v in slow:
+            s_ = st[t]
+            _log(f"slow {kind_of[t]} {v:.2f}s steps={s_['steps']} expanded={s_['expanded']} "
+                 f"peak={s_['frontier_peak_bytes'] >> 20}MiB expand_ms={s_['expand_ns'] / 1e6:.0f}")
+        return time.perf_counter() - t0, sorted(lat.values())
+
+    # saturated throughput X: the same queries submitted all at once; the
+    # measured run then offers them as Poisson arrivals at 0.7 X
+    qs = [query(i) for i in range(args.queries)]
+    tc, _ = run(qs, None)
+    x = len(qs) / tc
+    _log(f"saturated: {len(qs)} queries in {tc:.2f} s -> {x:.2f} queries/s")
+    tt, lat = run(qs, 0.7 * x)
+    _log(f"served {len(qs)} queries at {0.7 * x:.2f}/s arrival in {tt:.2f} s")
+    G.close()
+    p = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]
+    return {"metric": "served queries/s (p50/p99 latency)", "value": len(qs) / tt,
+            "unit": "queries/s", "n_gpus": 1, "higher_is_better": True, "dtype": "int64",
+            "data": "synthetic",
+            "config": {"workload": f"rmat{args.scale}_served_mix_60clique_40pattern_{len(qs)}q",
+                       "n": g.n, "m": g.m, "slots": args.slots, "arrival_rate": 0.7 * x},
+            "p50_latency_ms": p(0.5) * 1e3, "p99_latency_ms": p(0.99) * 1e3,
+            "saturated_queries_per_s": x, "one_gpu": True}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="power_law",
+                    choices=["power_law", "rmat_cliques_batched", "rmat_match_batched",
+                             "served_mix"])
+    ap.add_argument("--scale", type=int, default=16)
+    ap.add_argument("--queries", type=int, default=64)
+    ap.add_argument("--k-max", type=int, default=1000)
+    ap.add_argument("--slots", type=int, default=32)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--k", type=int, default=100)
@@ -79,6 +231,11 @@ def main() -> int:
         return 2
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    other = {"rmat_cliques_batched": bench_rmat_cliques, "rmat_match_batched": bench_rmat_match,
+             "served_mix": bench_served}
+    if args.workload in other:
+        print(json.dumps(other[args.workload](args, nuri, stream)), flush=True)
+        return 0
 
     t = time.perf_counter()
     g = synth.chung_lu()

@@ -98,6 +98,9 @@ typedef struct {
   uint64_t bitmap_bytes;      /* bytes of all local adjacency bitmaps */
   uint64_t device_bytes;      /* device memory held by the graph */
   uint64_t preprocess_ns;     /* wall time of nuri_load_graph */
+  double core_density;        /* edge density inside the largest out-neighbourhoods;
+                                 near 1 means a near-clique, where the automatic
+                                 clique bound keeps to |V| + |P| */
 } nuri_graph_info;
 int nuri_graph_get_info(const nuri_graph *g, nuri_graph_info *info);
 
@@ -129,9 +132,11 @@ typedef struct {
  *   batch_B                records expanded per step (0 = automatic)
  *   root_batch             unit subgraphs expanded per step (0 = automatic)
  *   bound                  clique bound used to skip children before they
- *                          are built: 0 automatic, 1 Carraghan-Pardalos
- *                          (|V| + |P|, or the weight analogue) only,
- *                          2 also colour classes of P for every record
+ *                          are built: 0 automatic (colour classes of P
+ *                          unless the densest part of the graph is a
+ *                          near-clique, where they cannot beat |P|),
+ *                          1 Carraghan-Pardalos (|V| + |P|, or the weight
+ *                          analogue) only, 2 colour classes of P always
  *   deadline_ns            wall-clock limit per call (0 = none)
  *   profile                1: time every expansion launch with HIP events
  *                          (reported in nuri_stats)

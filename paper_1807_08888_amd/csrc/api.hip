@@ -101,6 +101,7 @@ int nuri_graph_get_info(const nuri_graph *g, nuri_graph_info *info) {
   info->bitmap_bytes = g->g->bitmap_words * 8;
   info->device_bytes = g->g->device_bytes();
   info->preprocess_ns = g->g->preprocess_ns;
+  info->core_density = g->g->core_density;
   return NURI_OK;
 }
 

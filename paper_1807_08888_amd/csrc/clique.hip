@@ -36,6 +36,8 @@
 #include <algorithm>
 #include <climits>
 #include <cstddef>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "device_common.h"
@@ -818,8 +820,13 @@ struct Engine {
   u64 step_children = 0, step_words = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::unique_ptr<StepLayout> L;
+  bool trace = false;  // NURI_TRACE=1: one line per step on stderr
+  uint32_t rr = 0;     // round-robin start of the per-step planning
 
-  Engine(Graph &g_, const QueryOpts &o_) : g(g_), o(o_), s(o_.stream ? o_.stream : g_.stream) {}
+  Engine(Graph &g_, const QueryOpts &o_) : g(g_), o(o_), s(o_.stream ? o_.stream : g_.stream) {
+    const char *t = getenv("NURI_TRACE");
+    trace = t && t[0] == '1';
+  }
   ~Engine() {
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
@@ -938,7 +945,9 @@ struct Engine {
     QCfg &c = cfg[i];
     c.weighted = kind;
     c.k = k;
-    c.colour_min = o.bound == 1 ? 0u : (o.bound == 2 ? 1u : 32u);
+    // automatic: colour classes unless the densest region is a near-clique
+    const bool colour = o.bound == 2 || (o.bound == 0 && g.core_density < 0.9);
+    c.colour_min = colour ? 1u : 0u;
     c.pad = 0;
     SlotTopk &T = *tk[i];
     T.score.alloc(g.pool, 2ull * k);
@@ -983,15 +992,24 @@ struct Engine {
     for (auto &Q : qh) live += Q.active && !Q.done;
     if (!live) return false;
     const uint64_t now = o.deadline_ns ? now_ns() : 0;
-    // each live query may use an equal share of this step's output limits
-    const u64 share_c = std::max<u64>(step_children / live, max_rec_children());
-    const u64 share_w = std::max<u64>(step_words / live, max_rec_words());
+    // each live query may use an equal share of this step's output limits,
+    // and at most an eighth of its own arena: a step that fills the arena
+    // leaves the deeper levels so little room that the search then crawls
+    // forward a few records per step
+    const u64 share_c = std::max<u64>(std::min<u64>(step_children / live, cfg[0].hdr_cap / 8),
+                                      max_rec_children());
+    const u64 share_w = std::max<u64>(std::min<u64>(step_words / live, cfg[0].word_cap / 8),
+                                      max_rec_words());
     u64 left_c = step_children, left_w = step_words;
     bool any = false;
     for (uint32_t i = 0; i < nq; ++i) {
+      qh[i].plan = 0;
+      qh[i].sel_seg = -1;
+    }
+    rr = (rr + 1) % nq;  // the query served first rotates between steps
+    for (uint32_t t = 0; t < nq; ++t) {
+      const uint32_t i = (rr + t) % nq;
       QHost &Q = qh[i];
-      Q.plan = 0;
-      Q.sel_seg = -1;
       if (!Q.active || Q.done) continue;
       if (o.deadline_ns && now - Q.t_admit > o.deadline_ns) {
         fail(i, NURI_ETIMEOUT, "query deadline passed");
@@ -1228,8 +1246,18 @@ struct Engine {
   bool step_all() {
     uint32_t nseg, nrseg, batch_ub, mseg, mrseg;
     u64 temp_need;
+    const uint64_t t0 = trace ? now_ns() : 0;
     if (!plan(nseg, nrseg, batch_ub, temp_need, mseg, mrseg)) return false;
+    const uint64_t t1 = trace ? now_ns() : 0;
     step(nseg, nrseg, batch_ub, temp_need, mseg, mrseg);
+    if (trace) {
+      uint32_t live = 0;
+      for (auto &Q : qh) live += Q.active && !Q.done;
+      fprintf(stderr, "[nuri] step live=%u segs=%u roots=%u batch<=%u maxlevel=%u temp=%llu "
+              "leaves=%u plan_us=%llu step_us=%llu\n", live, nseg, nrseg, batch_ub, mseg,
+              (unsigned long long)temp_need, sh()->leaf_count,
+              (unsigned long long)(t1 - t0) / 1000, (unsigned long long)(now_ns() - t1) / 1000);
+    }
     return true;
   }
 

@@ -378,6 +378,26 @@ Graph *load_graph(const nuri_csr *csr, hipStream_t stream) {
     NURI_HIP(hipStreamSynchronize(s));
   }
   NURI_HIP(hipStreamSynchronize(s));
+  // density of the largest local universes (up to 8 roots): a near-clique
+  // dense region is where colour classes cannot beat |P|
+  {
+    std::vector<uint32_t> top(n);
+    std::iota(top.begin(), top.end(), 0u);
+    const size_t nt = std::min<size_t>(8, n);
+    std::partial_sort(top.begin(), top.begin() + nt, top.end(),
+                      [&](uint32_t a, uint32_t b) { return dplus[a] > dplus[b]; });
+    double edges = 0, pairs = 0;
+    for (size_t t = 0; t < nt; ++t) {
+      const uint32_t r = top[t];
+      const uint64_t d = dplus[r];
+      if (d < 2) continue;
+      std::vector<uint64_t> rows(bm_off[r + 1] - bm_off[r]);
+      NURI_HIP(hipMemcpy(rows.data(), g.bm.p + bm_off[r], rows.size() * 8, hipMemcpyDeviceToHost));
+      for (uint64_t w : rows) edges += __builtin_popcountll(w);
+      pairs += (double)d * (double)(d - 1);
+    }
+    g.core_density = pairs > 0 ? edges / pairs : 0.0;
+  }
   g.preprocess_ns = now_ns() - t0;
   return G.release();
 }

@@ -718,6 +718,7 @@ struct MatchEngine {
   uint32_t batch_cap = 0, cand_cap = 0, B = 0;
   u64 step_children = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  uint32_t rr = 0;  // round-robin start of the per-step planning
 
   MatchEngine(Graph &g_, const QueryOpts &o_) : g(g_), o(o_), s(o_.stream ? o_.stream : g_.stream) {}
   ~MatchEngine() {
@@ -930,13 +931,20 @@ struct MatchEngine {
     for (auto &Q : qh) live += Q.active && !Q.done;
     if (!live) return false;
     const uint64_t now = o.deadline_ns ? now_ns() : 0;
-    const u64 share = std::max<u64>(step_children / live, 1);
-    u64 left = step_children, left_cand = cand_cap;
+    // a query's children go to its own arena, so only its free space and a
+    // per-step cap limit it; complete matches go to the shared candidate
+    // buffer, which is split between the queries that produce them
+    const u64 cand_share = std::max<u64>(cand_cap / live, 1);
+    u64 left_cand = cand_cap;
     bool any = false;
     for (uint32_t i = 0; i < nq; ++i) {
+      qh[i].plan = 0;
+      qh[i].seg = -1;
+    }
+    rr = (rr + 1) % nq;  // the query served first rotates between steps
+    for (uint32_t t = 0; t < nq; ++t) {
+      const uint32_t i = (rr + t) % nq;
       MQHost &Q = qh[i];
-      Q.plan = 0;
-      Q.seg = -1;
       if (!Q.active || Q.done) continue;
       if (o.deadline_ns && now - Q.t_admit > o.deadline_ns) {
         fail(i, NURI_ETIMEOUT, "query deadline passed");
@@ -951,12 +959,16 @@ struct MatchEngine {
       const u64 free_h = Q.hdr_cap - (u64)(Lv.begin + Lv.count);
       const uint32_t depth = (uint32_t)Q.stack.size();  // records at this level match `depth` vertices
       const bool to_leaves = depth + 1 == plans[i].q;   // children are complete matches
-      const u64 lim = std::min<u64>(std::min(left, share), to_leaves ? left_cand : free_h);
       const u64 rec = std::max<u64>(1, Lv.maxcost);
       if ((to_leaves ? cand_cap : free_h) < rec) {
         fail(i, NURI_EBUDGET, "frontier budget exhausted");
         continue;
       }
+      // one step's children take at most an eighth of the query's arena, so
+      // that deeper levels keep room for batches of useful size
+      const u64 lim = to_leaves ? std::min<u64>(left_cand, std::max(cand_share, rec))
+                                : std::min<u64>(free_h, std::min<u64>(step_children,
+                                                                      std::max<u64>(Q.hdr_cap / 8, rec)));
       if (lim < rec) continue;
       const uint32_t room = batch_cap - batch_ub;
       if (room == 0) continue;
@@ -986,7 +998,6 @@ struct MatchEngine {
       Q.new_begin = Lv.begin + Lv.count;
       batch_ub += (uint32_t)(sg.take_all ? Lv.count : sg.max_records);
       const u64 used = sg.take_all ? Lv.cost : lim;
-      left -= std::min(left, used);
       if (to_leaves) left_cand -= std::min(left_cand, used);
       any = true;
     }

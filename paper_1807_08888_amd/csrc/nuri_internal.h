@@ -182,6 +182,7 @@ struct Graph {
   std::vector<int64_t> h_root_bound[2];
   DevBuf<uint32_t> root_order[2];
   uint64_t bitmap_words = 0;
+  double core_density = 0;  // edge density inside the largest local universes
 
   // oriented adjacency in a compact layout: N+(r) at oplus[ooff[r] ..
   // ooff[r] + dplus[r]) and the weights of those vertices at wloc[...]

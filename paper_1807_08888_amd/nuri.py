@@ -37,7 +37,7 @@ class _CSR(ctypes.Structure):
 class _GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("nnz", ctypes.c_uint64), ("degeneracy", ctypes.c_uint32),
                 ("bitmap_bytes", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
-                ("preprocess_ns", ctypes.c_uint64)]
+                ("preprocess_ns", ctypes.c_uint64), ("core_density", ctypes.c_double)]
 
 
 class _Pattern(ctypes.Structure):
@@ -191,7 +191,7 @@ class Graph:
     def info(self) -> Dict[str, int]:
         i = _GraphInfo()
         _check(lib().nuri_graph_get_info(self._h, ctypes.byref(i)))
-        return {f: int(getattr(i, f)) for f, _ in _GraphInfo._fields_}
+        return {f: getattr(i, f) for f, _ in _GraphInfo._fields_}
 
     def close(self):
         if getattr(self, "_h", None):
