@@ -276,107 +276,170 @@ __global__ void k_copy_back(const SelSeg *segs, const QCfg *cfg, const CRec *tem
 // child vertex's local adjacency row.  Group reductions give |P'| (or
 // w(P')); survivors are compacted with a ballot and one atomic per wave
 // and written with coalesced stores.
+//
+// Chains: when a record keeps exactly one child, the wave expands that
+// child at once instead of writing it to the frontier and waiting for a
+// later step.  Dense regions make such chains hundreds of vertices long
+// (one per clique member), so this turns hundreds of steps into one.  The
+// order in which records are expanded does not change the result: every
+// expansion prunes against a valid lower bound of the k-th score.
+//
+// LDS per wave (dynamic, sized by the largest local row of the graph):
+// five bitmaps of wst words (parent P, parent V, parent X, carried child
+// V+P, carried child X) and a candidate list of lst u16 positions.
 constexpr int kExpandWaves = 4;
+
+__device__ inline void put_crec(CRec *hdr, u64 slot, long long score, long long bound, u64 woff,
+                                uint32_t root, int j, uint32_t q) {
+  CRec ch;
+  ch.score = score;
+  ch.bound = bound;
+  ch.woff = woff;
+  ch.root = root;
+  ch.last = (int16_t)j;
+  ch.qid = (uint16_t)q;
+  hdr[slot] = ch;
+}
 
 __global__ void __launch_bounds__(64 * kExpandWaves)
     k_expand(GView g, const CRec *__restrict__ batch, StepHdr *hdr, const QCfg *__restrict__ cfg,
              QStep *qs, QCtr *ctr, const QRes *__restrict__ res, LRec *leaves, u64 *leaf_words,
-             uint32_t leaf_cap, u64 leaf_word_cap) {
-  __shared__ uint16_t s_list[kExpandWaves][kMaxLocal];
-  __shared__ u64 s_pw[kExpandWaves][kMaxWords];
-  __shared__ u64 s_vw[kExpandWaves][kMaxWords];
-  __shared__ u64 s_xw[kExpandWaves][kMaxWords];
+             uint32_t leaf_cap, u64 leaf_word_cap, uint32_t wst, uint32_t lst, u64 chain_cap) {
+  extern __shared__ u64 s_dyn[];
+  __shared__ long long s_cscore[kExpandWaves], s_cbound[kExpandWaves];
+  __shared__ int s_cj[kExpandWaves];
+  __shared__ uint32_t s_ccnt[kExpandWaves];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  u64 *s_pw = s_dyn + (u64)wv * 5 * wst;
+  u64 *s_vw = s_pw + wst;
+  u64 *s_xw = s_vw + wst;
+  u64 *s_cv = s_xw + wst;  // carried child: V + P bitmap
+  u64 *s_cx = s_cv + wst;  // carried child: X bitmap
+  uint16_t *s_list = (uint16_t *)(s_dyn + (u64)kExpandWaves * 5 * wst) + (u64)wv * lst;
   const uint32_t rec = blockIdx.x * kExpandWaves + wv;
   if (rec >= hdr->batch_count) return;
-  const CRec p = batch[rec];
+  CRec p = batch[rec];
   const uint32_t q = p.qid;
   const QCfg cf = cfg[q];
   const long long theta = res[q].theta;
-  u64 st_pruned_pop = 0, st_expanded = 0, st_children = 0, st_pruned_new = 0, st_leaves = 0,
-      st_bytes = 0, st_cost_c = 0, st_cost_w = 0, st_max_cc = 0;
+  const bool weighted = cf.weighted != 0;
+  u64 st_popped = 0, st_pruned_pop = 0, st_expanded = 0, st_children = 0, st_pruned_new = 0,
+      st_leaves = 0, st_bytes = 0, st_cost_c = 0, st_cost_w = 0, st_max_cc = 0;
   long long st_maxb = LLONG_MIN;
 
   const uint32_t r = p.root;
   const uint32_t d = g.dplus[r];
   const uint32_t W = words_of(d);
-  if (p.bound < theta) {
-    st_pruned_pop = 1;
-  } else if (d == 0) {
-    // a unit subgraph with no later neighbour: itself a leaf
-    st_leaves = 1;
-    if (p.score >= theta && lane == 0) {
-      unsigned int slot = atomicAdd(&hdr->leaf_count, 1u);
-      if (slot < leaf_cap) {
-        LRec l;
-        l.score = p.score;
-        l.woff = 0;
-        l.root = r;
-        l.last = -1;
-        l.qid = (uint16_t)q;
-        leaves[slot] = l;
-      } else {
-        atomicAdd(&qs[q].overflow, 1u);
-      }
+  const int32_t *wl = g.wloc + g.ooff[r];
+  const u64 *rows = g.bm + g.bm_off[r];
+  uint32_t G = 1;
+  while (G < W) G <<= 1;
+  const uint32_t per = 64 / G;
+  const int wi = lane & (G - 1);
+  const int gl = lane & ~(int)(G - 1);  // lane of this group's leader
+  const u64 below = gl ? ((1ull << gl) - 1ull) : 0ull;
+  bool carried = false;  // p is a kept child carried over from the previous link
+  u64 credit = 0;        // leaf slots reserved for chained links, not yet used (lane 0)
+  // write the held child (s_cv, s_cx, s_c*) to header slot hs, word slot ws
+  auto write_held = [&](u64 hs, u64 ws) {
+    if (lane < (int)W) {
+      cf.words[ws + lane] = s_cv[lane];
+      cf.words[ws + W + lane] = s_cx[lane];
     }
-  } else {
+    if (lane == 0) {
+      const int jc = s_cj[wv];
+      put_crec(cf.hdr, hs, s_cscore[wv], s_cbound[wv], ws, r, jc, q);
+      const u64 cc = (u64)(d - jc - 1);
+      st_cost_c += cc;
+      st_cost_w += cc * 2 * W;
+      st_max_cc = cc > st_max_cc ? cc : st_max_cc;
+      st_maxb = s_cbound[wv] > st_maxb ? s_cbound[wv] : st_maxb;
+      st_bytes += 32 + 16ull * W;
+    }
+  };
+
+  for (;;) {
+    ++st_popped;
+    if (p.bound < theta) {
+      st_pruned_pop = 1;
+      break;
+    }
+    if (d == 0) {
+      // a unit subgraph with no later neighbour: itself a leaf
+      st_leaves = 1;
+      if (p.score >= theta && lane == 0) {
+        unsigned int slot = atomicAdd(&hdr->leaf_count, 1u);
+        if (slot < leaf_cap) {
+          LRec l;
+          l.score = p.score;
+          l.woff = 0;
+          l.root = r;
+          l.last = -1;
+          l.qid = (uint16_t)q;
+          leaves[slot] = l;
+        } else {
+          atomicAdd(&qs[q].overflow, 1u);
+        }
+      }
+      break;
+    }
     const int last = p.last;
-    const bool weighted = cf.weighted != 0;
-    const int32_t *wl = g.wloc + g.ooff[r];
     u64 word = 0, xword = 0;
     if (lane < (int)W) {
-      word = last < 0 ? lt_mask(lane, d) : cf.words[p.woff + lane];
-      xword = last < 0 ? 0ull : cf.words[p.woff + W + lane];
+      if (carried) {
+        word = s_cv[lane];
+        xword = s_cx[lane];
+      } else {
+        word = last < 0 ? lt_mask(lane, d) : cf.words[p.woff + lane];
+        xword = last < 0 ? 0ull : cf.words[p.woff + W + lane];
+      }
     }
     const u64 pw = word & gt_mask(lane, last);
     const u64 vwd = word & ~gt_mask(lane, last);
+    wave_sync();  // every lane has read the carried child before it is replaced
     if (lane < (int)W) {
-      s_pw[wv][lane] = pw;
-      s_vw[wv][lane] = vwd;
-      s_xw[wv][lane] = xword;
+      s_pw[lane] = pw;
+      s_vw[lane] = vwd;
+      s_xw[lane] = xword;
     }
-    // list the candidate positions in increasing order, and the weight of
-    // this lane's share of them
-    uint32_t c = __popcll(pw);
-    uint32_t off = wave_excl_scan(c, lane);
+    // candidates in increasing position: this lane holds positions
+    // [off, off + c) of the list
+    const uint32_t c = __popcll(pw);
+    const uint32_t off = wave_excl_scan(c, lane);
     const uint32_t nchild = __shfl(off + c, 63, 64);
-    long long lsum = 0;
-    {
-      u64 t = pw;
-      uint32_t o = off;
-      while (t) {
-        int b = __ffsll((long long)t) - 1;
-        s_list[wv][o++] = (uint16_t)(lane * 64 + b);
-        lsum += weighted ? (long long)wl[lane * 64 + b] : 1ll;
-        t &= t - 1;
-      }
-    }
-    // cutoff: first idx whose prefix weight exceeds total + score - theta
+    // cutoff: child idx reaches at most score + (weight of candidates
+    // idx, idx+1, ...); past the first idx where that is below theta every
+    // child is dominated
     uint32_t n_eff = nchild;
     if (theta != LLONG_MIN) {
-      const long long lexcl = wave_excl_scan64(lsum, lane);
-      const long long total = __shfl(lexcl + lsum, 63, 64);
-      const long long R = total + p.score - theta;
-      uint32_t cut = 0xFFFFFFFFu;
-      if (R < 0) {
-        cut = 0;
-      } else if (c && lexcl + lsum > R) {
-        long long run = lexcl;
-        uint32_t idx = off;
-        u64 t = pw;
-        while (t) {
-          if (run > R) {
-            cut = idx;
-            break;
+      if (!weighted) {
+        // each candidate weighs 1: child idx reaches score + nchild - idx
+        const long long R = p.score + (long long)nchild - theta;
+        n_eff = R < 0 ? 0u : (uint32_t)(R + 1 < (long long)nchild ? R + 1 : nchild);
+      } else {
+        long long lsum = 0;
+        for (u64 t = pw; t; t &= t - 1) lsum += wl[lane * 64 + __ffsll((long long)t) - 1];
+        const long long lexcl = wave_excl_scan64(lsum, lane);
+        const long long total = __shfl(lexcl + lsum, 63, 64);
+        const long long R = total + p.score - theta;
+        uint32_t cut = 0xFFFFFFFFu;
+        if (R < 0) {
+          cut = 0;
+        } else if (c && lexcl + lsum > R) {
+          long long run = lexcl;
+          uint32_t idx = off;
+          for (u64 t = pw; t; t &= t - 1) {
+            if (run > R) {
+              cut = idx;
+              break;
+            }
+            run += wl[lane * 64 + __ffsll((long long)t) - 1];
+            ++idx;
           }
-          int b = __ffsll((long long)t) - 1;
-          run += weighted ? (long long)wl[lane * 64 + b] : 1ll;
-          ++idx;
-          t &= t - 1;
         }
+        cut = wave_min_u32(cut);
+        if (cut < n_eff) n_eff = cut;
       }
-      cut = wave_min_u32(cut);
-      if (cut < n_eff) n_eff = cut;
       // colour-class cutoff (a tighter bound than Carraghan-Pardalos, the
       // direction the paper leaves to future work): split the candidates
       // into independent sets, each built greedily from the highest
@@ -389,7 +452,6 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       // above the top of the last class built are dominated.
       const long long need = theta - p.score;
       if (cf.colour_min && n_eff >= cf.colour_min && need > 0) {
-        const u64 *crow = g.bm + g.bm_off[r];
         u64 U = pw, Q = 0;
         long long run = 0;
         int cut_pos = -1;  // children at positions <= cut_pos survive
@@ -411,7 +473,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
               U &= ~bit;
               Q &= ~bit;
             }
-            if (lane < (int)W) Q &= ~crow[(u64)hb * W + lane];
+            if (lane < (int)W) Q &= ~rows[(u64)hb * W + lane];
           }
           run += cmax;
           if (run >= need) {
@@ -426,29 +488,32 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
           keep_n = (uint32_t)wave_sum((u64)__popcll(m));
         }
         if (keep_n < n_eff) n_eff = keep_n;
-              }
+      }
+    }
+    // list the positions of the children that get built
+    {
+      uint32_t o = off;
+      for (u64 t = pw; t && o < n_eff; t &= t - 1)
+        s_list[o++] = (uint16_t)(lane * 64 + __ffsll((long long)t) - 1);
     }
     wave_sync();
-    if (last >= 0 && lane == 0) st_bytes += 32 + 16ull * W;  // the parent record
-    if (nchild) st_expanded = 1;
-    st_children = nchild;
-    st_pruned_new = nchild - n_eff;
-    const u64 *rows = g.bm + g.bm_off[r];
-    uint32_t G = 1;
-    while (G < W) G <<= 1;
-    const uint32_t per = 64 / G;
-    const int wi = lane & (G - 1);
-    const int gl = lane & ~(int)(G - 1);  // lane of this group's leader
+    if (last >= 0 && !carried && lane == 0) st_bytes += 32 + 16ull * W;  // the parent record
+    if (nchild) st_expanded += 1;
+    st_children += nchild;
+    st_pruned_new += nchild - n_eff;
+    // kept children: the first is held back (in s_cv/s_cx) in case it
+    // stays the only one; `spilled` once it has been written out
+    bool held = false, spilled = false;
     for (uint32_t base = 0; base < n_eff; base += per) {
       const uint32_t ci = base + lane / G;
       const bool valid = ci < n_eff;
-      const uint32_t j = valid ? s_list[wv][ci] : 0;
+      const uint32_t j = valid ? s_list[ci] : 0;
       u64 a = 0, xc = 0;
       if (valid && wi < (int)W) {
         const u64 row = rows[(u64)j * W + wi];
-        const u64 pv = s_pw[wv][wi];
-        a = pv & row & gt_mask(wi, (int)j);                           // P'
-        xc = (s_xw[wv][wi] | (pv & ~gt_mask(wi, (int)j - 1))) & row;  // X'
+        const u64 pv = s_pw[wi];
+        a = pv & row & gt_mask(wi, (int)j);                        // P'
+        xc = (s_xw[wi] | (pv & ~gt_mask(wi, (int)j - 1))) & row;  // X'
       }
       // extension witness: the first vertex of X'; if it is adjacent to all
       // of P', no clique below this child is maximal
@@ -465,14 +530,8 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       }
       uint32_t cnt = __popcll(a);
       long long wsum = 0;
-      if (weighted) {
-        u64 t = a;
-        while (t) {
-          int b = __ffsll((long long)t) - 1;
-          wsum += wl[wi * 64 + b];
-          t &= t - 1;
-        }
-      }
+      if (weighted)
+        for (u64 t = a; t; t &= t - 1) wsum += wl[wi * 64 + __ffsll((long long)t) - 1];
       for (uint32_t o2 = 1; o2 < G; o2 <<= 1) {
         cnt += __shfl_xor(cnt, o2, 64);
         if (weighted) wsum += __shfl_xor(wsum, o2, 64);
@@ -491,48 +550,65 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       st_leaves += __popcll(__ballot(leader && leaf));
       if (lane == 0) st_bytes += 8ull * W * __popcll(lm);  // adjacency rows read
       if (wi == 0 && valid && x0 != 0x7FFFFFFF) st_bytes += 8ull * W;  // witness row
-      const u64 below = gl ? ((1ull << gl) - 1ull) : 0ull;
       const u64 jbit = (wi == (int)(j >> 6)) ? (1ull << (j & 63)) : 0ull;
       if (km) {
-        const uint32_t nk = __popcll(km);
-        unsigned int h0 = 0;
-        u64 w0 = 0;
-        if (lane == 0) {
-          h0 = atomicAdd(&qs[q].n_out, nk);
-          w0 = atomicAdd(&qs[q].out_words, (u64)nk * 2 * W);
-        }
-        h0 = __shfl(h0, 0, 64);
-        w0 = __shfl(w0, 0, 64);
-        if (keep) {
-          const uint32_t rk = __popcll(km & below);
-          const u64 slot_h = (u64)cf.out_hdr + h0 + rk;
-          const u64 slot_w = cf.out_word + w0 + (u64)rk * 2 * W;
-          if (slot_h < cf.hdr_cap && slot_w + 2 * W <= cf.word_cap) {
+        if (!held && __popcll(km) == 1) {
+          // the first kept child: hold it back
+          held = true;
+          if (keep) {
             if (wi < (int)W) {
-              cf.words[slot_w + wi] = s_vw[wv][wi] | a | jbit;
-              cf.words[slot_w + W + wi] = xc;
+              s_cv[wi] = s_vw[wi] | a | jbit;
+              s_cx[wi] = xc;
             }
             if (wi == 0) {
-              CRec ch;
-              ch.score = score2;
-              ch.bound = bound2;
-              ch.woff = slot_w;
-              ch.root = r;
-              ch.last = (int16_t)j;
-              ch.qid = (uint16_t)q;
-              cf.hdr[slot_h] = ch;
+              s_cscore[wv] = score2;
+              s_cbound[wv] = bound2;
+              s_cj[wv] = (int)j;
+              s_ccnt[wv] = cnt;
             }
-          } else if (wi == 0) {
-            atomicAdd(&qs[q].overflow, 1u);
           }
-          if (wi == 0) {
-            u64 cc = (u64)(d - j - 1);
-            st_cost_c += cc;
-            st_cost_w += cc * 2 * W;
-            st_max_cc = cc > st_max_cc ? cc : st_max_cc;
-            st_maxb = bound2 > st_maxb ? bound2 : st_maxb;
-            st_bytes += 32 + 16ull * W;
+          wave_sync();
+        } else {
+          // write these children, and the held one if it is still held
+          const uint32_t extra = (held && !spilled) ? 1u : 0u;
+          const uint32_t nk = __popcll(km) + extra;
+          unsigned int h0 = 0;
+          u64 w0 = 0;
+          if (lane == 0) {
+            h0 = atomicAdd(&qs[q].n_out, nk);
+            w0 = atomicAdd(&qs[q].out_words, (u64)nk * 2 * W);
           }
+          h0 = __shfl(h0, 0, 64);
+          w0 = __shfl(w0, 0, 64);
+          const bool fits0 = (u64)cf.out_hdr + h0 + nk <= cf.hdr_cap &&
+                             cf.out_word + w0 + (u64)nk * 2 * W <= cf.word_cap;
+          if (!fits0) {
+            if (lane == 0) atomicAdd(&qs[q].overflow, 1u);
+          } else {
+            if (extra) {
+              write_held((u64)cf.out_hdr + h0, cf.out_word + w0);
+              spilled = true;
+            }
+            if (keep) {
+              const uint32_t rk = extra + __popcll(km & below);
+              const u64 slot_w = cf.out_word + w0 + (u64)rk * 2 * W;
+              if (wi < (int)W) {
+                cf.words[slot_w + wi] = s_vw[wi] | a | jbit;
+                cf.words[slot_w + W + wi] = xc;
+              }
+              if (wi == 0) {
+                put_crec(cf.hdr, (u64)cf.out_hdr + h0 + rk, score2, bound2, slot_w, r, (int)j, q);
+                const u64 cc = (u64)(d - j - 1);
+                st_cost_c += cc;
+                st_cost_w += cc * 2 * W;
+                st_max_cc = cc > st_max_cc ? cc : st_max_cc;
+                st_maxb = bound2 > st_maxb ? bound2 : st_maxb;
+                st_bytes += 32 + 16ull * W;
+              }
+            }
+          }
+          held = true;
+          spilled = true;
         }
       }
       if (fm) {
@@ -550,7 +626,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
           const u64 slot_l = (u64)l0 + rk;
           const u64 slot_w = w0 + (u64)rk * W;
           if (slot_l < leaf_cap && slot_w + W <= leaf_word_cap) {
-            if (wi < (int)W) leaf_words[slot_w + wi] = s_vw[wv][wi] | jbit;
+            if (wi < (int)W) leaf_words[slot_w + wi] = s_vw[wi] | jbit;
             if (wi == 0) {
               LRec l;
               l.score = score2;
@@ -567,7 +643,56 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         }
       }
     }
+    if (!held || spilled) break;
+    // exactly one kept child.  Expand it next, in this wave, if a k-th
+    // score is known (without one nothing is cut, and thousands of chains
+    // would each run to full depth unpruned) and the leaf buffer has room
+    // for every leaf it can offer (at most one per candidate); otherwise
+    // write it to the frontier like any other child.
+    {
+      // leaf slots are reserved in chunks of several links' worth; unused
+      // credit is handed back when the chain ends
+      const u64 m = s_ccnt[wv];
+      int ok = 0;
+      if (lane == 0 && theta != LLONG_MIN) {
+        if (credit < m) {
+          for (u64 want = 8 * m; want >= m && !ok; want = want == m ? 0 : m) {
+            const u64 oc = atomicAdd(&hdr->chain_c, want);
+            if (oc + want <= chain_cap) {
+              credit += want;
+              ok = 1;
+            } else {
+              atomicSub(&hdr->chain_c, want);
+            }
+          }
+        } else {
+          ok = 1;
+        }
+        if (ok) credit -= m;
+      }
+      ok = __shfl(ok, 0, 64);
+      if (!ok) {
+        unsigned int h0 = 0;
+        u64 w0 = 0;
+        if (lane == 0) {
+          h0 = atomicAdd(&qs[q].n_out, 1u);
+          w0 = atomicAdd(&qs[q].out_words, 2ull * W);
+        }
+        h0 = __shfl(h0, 0, 64);
+        w0 = __shfl(w0, 0, 64);
+        if ((u64)cf.out_hdr + h0 + 1 <= cf.hdr_cap && cf.out_word + w0 + 2ull * W <= cf.word_cap)
+          write_held((u64)cf.out_hdr + h0, cf.out_word + w0);
+        else if (lane == 0)
+          atomicAdd(&qs[q].overflow, 1u);
+        break;
+      }
+    }
+    p.score = s_cscore[wv];
+    p.bound = s_cbound[wv];
+    p.last = (int16_t)s_cj[wv];
+    carried = true;
   }
+  if (lane == 0 && credit) atomicSub(&hdr->chain_c, credit);
   // flush per-wave statistics with one atomic each
   st_cost_c = wave_sum(st_cost_c);
   st_cost_w = wave_sum(st_cost_w);
@@ -576,7 +701,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   st_maxb = wave_max(st_maxb);
   if (lane == 0) {
     QCtr &C = ctr[q];
-    atomicAdd(&C.popped, 1ull);
+    atomicAdd(&C.popped, st_popped);
     if (st_pruned_pop) atomicAdd(&C.pruned_pop, st_pruned_pop);
     if (st_expanded) atomicAdd(&C.expanded, st_expanded);
     if (st_children) atomicAdd(&C.children, st_children);
@@ -806,6 +931,7 @@ struct Engine {
   PoolBuf<LRec> leaves;
   PoolBuf<u64> leaf_words;
   PoolBuf<Cand> cands;
+  PoolBuf<uint32_t> mpos;  // merge: position of each candidate among the top-k
   PoolBuf<uint32_t> cand_ids;
   PoolBuf<unsigned int> d_hist;
   PoolBuf<u64> d_hchild;
@@ -818,6 +944,9 @@ struct Engine {
   u64 leaf_word_cap = 0;
   uint32_t B = 0, root_B = 0;
   u64 step_children = 0, step_words = 0;
+  u64 plan_c = 0, plan_w = 0;  // children and words the current step may write
+  uint32_t ex_wst = 0, ex_lst = 0;
+  size_t expand_lds = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::unique_ptr<StepLayout> L;
   bool trace = false;  // NURI_TRACE=1: one line per step on stderr
@@ -913,11 +1042,19 @@ struct Engine {
     step_children = std::max<u64>(1ull << 16, std::min<u64>(step_words, 32ull << 20));
     batch_cap = (uint32_t)std::min<u64>((u64)nq * std::max(B, root_B), 1u << 26);
     batch.alloc(g.pool, batch_cap);
-    leaf_cap = (uint32_t)step_children;
-    leaf_word_cap = step_words;
+    // leaves of one step: at most one per planned child plus one per unit
+    // subgraph, and the reserve that chained expansion draws from
+    leaf_cap = (uint32_t)(2 * step_children + batch_cap);
+    leaf_word_cap = 2 * step_words;
+    // LDS of k_expand: five bitmaps of the widest local row and a candidate
+    // list as long as the largest out-degree, per wave
+    ex_wst = std::max<uint32_t>(1, (g.degeneracy + 63) / 64);
+    ex_lst = (g.degeneracy + 8) & ~7u;
+    expand_lds = (size_t)kExpandWaves * (5ull * 8 * ex_wst + 2ull * ex_lst);
     leaves.alloc(g.pool, leaf_cap);
     leaf_words.alloc(g.pool, leaf_word_cap);
     cands.alloc(g.pool, kCandChunk);
+    mpos.alloc(g.pool, kCandChunk);
     cand_ids.alloc(g.pool, (u64)kCandChunk * lmax);
     d_hist.alloc(g.pool, (u64)nq * kBins);
     d_hchild.alloc(g.pool, (u64)nq * kBins);
@@ -1111,6 +1248,8 @@ struct Engine {
       for (uint32_t i = 0; i < nq; ++i)
         if (qh[i].active && !qh[i].done)
           fail(i, NURI_EBUDGET, "frontier budget too small to make progress");
+    plan_c = step_children - left_c;
+    plan_w = step_words - left_w;
     return any;
   }
 
@@ -1165,9 +1304,11 @@ struct Engine {
     if (batch_ub) {
       if (o.profile) NURI_HIP(hipEventRecord(ev0, s));
       const uint32_t blocks = (batch_ub + kExpandWaves - 1) / kExpandWaves;
-      hipLaunchKernelGGL(k_expand, dim3(blocks), dim3(64 * kExpandWaves), 0, s, gv, batch.p, dh,
-                         dcfg, dqs, d_ctr.p, d_res.p, leaves.p, leaf_words.p, leaf_cap,
-                         leaf_word_cap);
+      hipLaunchKernelGGL(k_expand, dim3(blocks), dim3(64 * kExpandWaves), expand_lds, s, gv,
+                         batch.p, dh, dcfg, dqs, d_ctr.p, d_res.p, leaves.p, leaf_words.p,
+                         leaf_cap, leaf_word_cap, ex_wst, ex_lst,
+                         std::min<u64>((u64)leaf_cap - plan_c - batch_ub,
+                                       (leaf_word_cap - plan_w) / ex_wst));
       NURI_HIP(hipGetLastError());
       if (o.profile) NURI_HIP(hipEventRecord(ev1, s));
     }
@@ -1220,7 +1361,6 @@ struct Engine {
       uint32_t kmax = 0;
       for (auto &Q : qh)
         if (Q.active) kmax = std::max(kmax, Q.k);
-      const uint32_t mx = (kmax + kCandChunk + 255) / 256;
       for (uint32_t f = 0; f < nleaf; f += kCandChunk) {
         const uint32_t cnt = std::min<uint32_t>(kCandChunk, nleaf - f);
         NURI_HIP(hipMemsetAsync(&dh->cand_count, 0, sizeof(unsigned int), s));
@@ -1228,12 +1368,7 @@ struct Engine {
                            leaf_words.p, d_res.p, cands.p, &dh->cand_count, cand_ids.p, lmax,
                            d_ctr.p);
         NURI_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_merge_rank, dim3(mx, nq), dim3(256), 0, s, cands.p, dh, cand_ids.p,
-                           lmax, d_res.p, d_k.p);
-        NURI_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_merge_finish, dim3(nq), dim3(256), 0, s, cands.p, dh, d_res.p,
-                           d_k.p);
-        NURI_HIP(hipGetLastError());
+        launch_merge(cands.p, dh, cand_ids.p, lmax, d_res.p, d_k.p, mpos.p, nq, kmax, cnt, s);
       }
       NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
       NURI_HIP(hipStreamSynchronize(s));

@@ -21,6 +21,7 @@ struct Cand {  // a result offered to the result set (its ids are stored apart)
 struct StepHdr {  // global counters of one step (zeroed by the step upload)
   unsigned int batch_count, leaf_count, cand_count, pad;
   u64 leaf_word_count;
+  u64 chain_c;  // leaf slots reserved by chained expansion (each with the widest row)
 };
 
 struct QRes {  // per query result state
@@ -125,107 +126,186 @@ __device__ inline bool before(long long sa, const uint32_t *a, uint32_t la, long
   return la < lb;
 }
 
-// Ranks are computed against the current top-k plus this chunk's
-// candidates of the query (all-pairs comparison, one thread per item,
-// grid (x, query)); items ranked below k are written to the other top-k
-// buffer at their rank, so the order of candidates in the buffer never
-// matters.
-__global__ void __launch_bounds__(256)
+// The same order, decided by a whole wavefront: 64 ids are compared per
+// load, so lists that share a long prefix (cliques of one dense region)
+// cost a few wave steps instead of hundreds of serial loads.  Every lane
+// returns the same value.
+__device__ inline bool wave_before(long long sa, const uint32_t *a, uint32_t la, long long sb,
+                                   const uint32_t *b, uint32_t lb, int lane) {
+  if (sa != sb) return sa > sb;
+  const uint32_t n = la < lb ? la : lb;
+  for (uint32_t base = 0; base < n; base += 64) {
+    const uint32_t i = base + lane;
+    const bool diff = i < n && a[i] != b[i];
+    const u64 m = __ballot(diff);
+    if (m) {
+      const uint32_t f = base + __ffsll((long long)m) - 1;
+      return a[f] < b[f];
+    }
+  }
+  return la < lb;
+}
+
+// The merge of one chunk of candidates into each query's top-k takes
+// three launches.
+//   k_merge_pos: one wave per candidate finds, by binary search, how many
+//     current top-k items precede it.  A candidate preceded by k or more
+//     can never enter (everything that will precede a member of the new
+//     top-k precedes it too), so it is dropped.
+//   k_merge_rank: one wave per item of (top-k, surviving candidates) of a
+//     query counts the survivors that precede it; with its position in
+//     the top-k that is its rank in the union.  Items ranked below k are
+//     written to the other top-k buffer at their rank, so the order of
+//     candidates in the chunk never matters.
+//   k_merge_finish: switches to the merged buffer and sets the threshold.
+constexpr uint32_t kDropped = 0xFFFFFFFFu;
+constexpr int kMergeWaves = 4;
+
+__global__ void __launch_bounds__(64 * kMergeWaves)
+    k_merge_pos(const Cand *cands, const StepHdr *hdr, const uint32_t *cand_ids, uint32_t lmax,
+                const QRes *res, const uint32_t *ks, uint32_t *pos) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t c = blockIdx.x * kMergeWaves + (threadIdx.x >> 6);
+  if (c >= hdr->cand_count) return;
+  const Cand cd = cands[c];
+  const QRes &R = res[cd.qid];
+  const uint32_t cur = R.cur, n = R.tk_n;
+  const uint32_t *ids = cand_ids + (u64)c * lmax;
+  uint32_t lo = 0, hi = n;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (wave_before(R.tk_score[cur][mid], R.tk_ids[cur] + (u64)mid * lmax, R.tk_len[cur][mid],
+                    cd.score, ids, cd.len, lane))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  if (lane == 0) pos[c] = lo < ks[cd.qid] ? lo : kDropped;
+}
+
+__global__ void __launch_bounds__(64 * kMergeWaves)
     k_merge_rank(const Cand *cands, const StepHdr *hdr, const uint32_t *cand_ids, uint32_t lmax,
-                 const QRes *res, const uint32_t *ks) {
+                 const QRes *res, const uint32_t *ks, const uint32_t *pos) {
   __shared__ uint32_t s_idx[kCandChunk];
-  __shared__ uint32_t s_cnt[256];
-  __shared__ uint32_t s_nc;
-  constexpr uint32_t per = kCandChunk / 256;
+  __shared__ uint32_t s_cnt[64 * kMergeWaves];
+  __shared__ uint32_t s_ns;
+  constexpr uint32_t per = kCandChunk / (64 * kMergeWaves);
   const uint32_t q = blockIdx.y;
   const uint32_t nc_all = hdr->cand_count;
   const uint32_t b0 = threadIdx.x * per;
   uint32_t mine = 0;
-  for (uint32_t i = b0; i < b0 + per && i < nc_all; ++i) mine += cands[i].qid == q;
+  for (uint32_t i = b0; i < b0 + per && i < nc_all; ++i)
+    mine += cands[i].qid == q && pos[i] != kDropped;
   s_cnt[threadIdx.x] = mine;
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t run = 0;
-    for (int t = 0; t < 256; ++t) {
-      uint32_t c = s_cnt[t];
+    for (int t = 0; t < 64 * kMergeWaves; ++t) {
+      const uint32_t c = s_cnt[t];
       s_cnt[t] = run;
       run += c;
     }
-    s_nc = run;
+    s_ns = run;
   }
   __syncthreads();
   uint32_t o = s_cnt[threadIdx.x];
   for (uint32_t i = b0; i < b0 + per && i < nc_all; ++i)
-    if (cands[i].qid == q) s_idx[o++] = i;
+    if (cands[i].qid == q && pos[i] != kDropped) s_idx[o++] = i;
   __syncthreads();
-  const uint32_t nc = s_nc;
-  if (nc == 0) return;
-  const QRes R = res[q];
+  const uint32_t ns = s_ns;
+  if (ns == 0) return;
+  const int lane = threadIdx.x & 63;
+  const QRes &R = res[q];
   const uint32_t k = ks[q];
   const uint32_t cur = R.cur, alt = cur ^ 1u;
-  const uint32_t N = R.tk_n + nc;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
+  const uint32_t nt = R.tk_n < k ? R.tk_n : k;
+  const uint32_t it = blockIdx.x * kMergeWaves + (threadIdx.x >> 6);
+  if (it >= nt + ns) return;
   long long si;
   const uint32_t *ai;
-  uint32_t li;
-  if (i < R.tk_n) {
-    si = R.tk_score[cur][i];
-    ai = R.tk_ids[cur] + (u64)i * lmax;
-    li = R.tk_len[cur][i];
+  uint32_t li, rank;
+  if (it < nt) {
+    si = R.tk_score[cur][it];
+    ai = R.tk_ids[cur] + (u64)it * lmax;
+    li = R.tk_len[cur][it];
+    rank = it;
   } else {
-    uint32_t c = s_idx[i - R.tk_n];
+    const uint32_t c = s_idx[it - nt];
     si = cands[c].score;
     ai = cand_ids + (u64)c * lmax;
     li = cands[c].len;
+    rank = pos[c];
   }
-  uint32_t rank = 0;
-  for (uint32_t j = 0; j < N && rank < k; ++j) {
-    if (j == i) continue;
-    long long sj;
-    const uint32_t *aj;
-    uint32_t lj;
-    if (j < R.tk_n) {
-      sj = R.tk_score[cur][j];
-      aj = R.tk_ids[cur] + (u64)j * lmax;
-      lj = R.tk_len[cur][j];
-    } else {
-      uint32_t c = s_idx[j - R.tk_n];
-      sj = cands[c].score;
-      aj = cand_ids + (u64)c * lmax;
-      lj = cands[c].len;
+  // survivors that precede this item: scores decide 64 at a time, ties
+  // are settled one by one by the whole wave
+  for (uint32_t base = 0; base < ns && rank < k; base += 64) {
+    const uint32_t j = base + lane;
+    long long sj = 0;
+    uint32_t cj = 0;
+    if (j < ns) {
+      cj = s_idx[j];
+      sj = cands[cj].score;
     }
-    rank += before(sj, aj, lj, si, ai, li);
+    const bool self = it >= nt && j == it - nt;
+    rank += __popcll(__ballot(j < ns && !self && sj > si));
+    u64 tie = __ballot(j < ns && !self && sj == si);
+    while (tie) {
+      const int t = __ffsll((long long)tie) - 1;
+      tie &= tie - 1;
+      const uint32_t ct = __shfl(cj, t, 64);
+      rank += wave_before(si, cand_ids + (u64)ct * lmax, cands[ct].len, si, ai, li, lane);
+    }
   }
   if (rank < k) {
-    R.tk_score[alt][rank] = si;
-    R.tk_len[alt][rank] = li;
+    if (lane == 0) {
+      R.tk_score[alt][rank] = si;
+      R.tk_len[alt][rank] = li;
+    }
     uint32_t *dst = R.tk_ids[alt] + (u64)rank * lmax;
-    for (uint32_t t = 0; t < li; ++t) dst[t] = ai[t];
+    for (uint32_t t = lane; t < li; t += 64) dst[t] = ai[t];
   }
 }
 
 // one block per query: switch to the merged buffer and set the threshold
 __global__ void __launch_bounds__(256)
-    k_merge_finish(const Cand *cands, const StepHdr *hdr, QRes *res, const uint32_t *ks) {
+    k_merge_finish(const Cand *cands, const StepHdr *hdr, QRes *res, const uint32_t *ks,
+                   const uint32_t *pos) {
   __shared__ uint32_t s_n;
   const uint32_t q = blockIdx.x;
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
   const uint32_t nc_all = hdr->cand_count;
   uint32_t mine = 0;
-  for (uint32_t i = threadIdx.x; i < nc_all; i += blockDim.x) mine += cands[i].qid == q;
+  for (uint32_t i = threadIdx.x; i < nc_all; i += blockDim.x)
+    mine += cands[i].qid == q && pos[i] != kDropped;
   if (mine) atomicAdd(&s_n, mine);
   __syncthreads();
   if (threadIdx.x != 0 || s_n == 0) return;
   QRes &R = res[q];
   const uint32_t k = ks[q];
-  const uint32_t N = R.tk_n + s_n;
+  const uint32_t N = (R.tk_n < k ? R.tk_n : k) + s_n;
   const uint32_t nn = N < k ? N : k;
   const uint32_t alt = R.cur ^ 1u;
   R.tk_n = nn;
   R.cur = alt;
   R.theta = nn == k ? R.tk_score[alt][k - 1] : LLONG_MIN;
+}
+
+// launch the three merge kernels for a chunk of at most `ub` candidates
+// (the exact count is read on the device from hdr->cand_count)
+inline void launch_merge(const Cand *cands, const StepHdr *hdr, const uint32_t *ids,
+                         uint32_t lmax, QRes *res, const uint32_t *ks, uint32_t *pos, uint32_t nq,
+                         uint32_t kmax, uint32_t ub, hipStream_t s) {
+  if (!ub) return;
+  hipLaunchKernelGGL(k_merge_pos, dim3((ub + kMergeWaves - 1) / kMergeWaves),
+                     dim3(64 * kMergeWaves), 0, s, cands, hdr, ids, lmax, res, ks, pos);
+  NURI_HIP(hipGetLastError());
+  const uint32_t items = kmax + std::min<uint32_t>(ub, kCandChunk);
+  hipLaunchKernelGGL(k_merge_rank, dim3((items + kMergeWaves - 1) / kMergeWaves, nq),
+                     dim3(64 * kMergeWaves), 0, s, cands, hdr, ids, lmax, res, ks, pos);
+  NURI_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_merge_finish, dim3(nq), dim3(256), 0, s, cands, hdr, res, ks, pos);
+  NURI_HIP(hipGetLastError());
 }
 
 // page-locked host staging buffer

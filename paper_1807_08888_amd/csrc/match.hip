@@ -701,6 +701,7 @@ struct MatchEngine {
   PoolBuf<QRes> d_res;
   PoolBuf<uint32_t> d_k, d_rootq;
   PoolBuf<Cand> cands, cands2;
+  PoolBuf<uint32_t> mpos;  // merge: position of each candidate among the top-k
   PoolBuf<uint32_t> cand_ids, cand_ids2;
   PoolBuf<CPre> d_pre;
   PinBuf<CPre> h_pre;
@@ -800,6 +801,7 @@ struct MatchEngine {
     cands.alloc(g.pool, cand_cap);
     cand_ids.alloc(g.pool, (u64)cand_cap * QM);
     cands2.alloc(g.pool, cand_cap);
+    mpos.alloc(g.pool, kCandChunk);
     cand_ids2.alloc(g.pool, (u64)cand_cap * QM);
     d_pre.alloc(g.pool, nq);
     h_pre.alloc(nq);
@@ -1124,16 +1126,12 @@ struct MatchEngine {
       for (uint32_t i = 0; i < nq; ++i)
         if (sms()[i].cand_n) qh[i].top_seen = std::max(qh[i].top_seen, sms()[i].cand_max);
     }
-    const uint32_t mx = (kmax + kCandChunk + 255) / 256;
     for (uint32_t f = 0; f < ncand; f += kCandChunk) {
       h_ccount.p[0] = std::min<uint32_t>(kCandChunk, ncand - f);
       // the merge kernels read the chunk size through StepHdr::cand_count
       NURI_HIP(hipMemcpyAsync(&dh->cand_count, h_ccount.p, 4, hipMemcpyHostToDevice, s));
-      hipLaunchKernelGGL(k_merge_rank, dim3(mx, nq), dim3(256), 0, s, mc + f, dh,
-                         mids + (u64)f * QM, (uint32_t)QM, d_res.p, d_k.p);
-      NURI_HIP(hipGetLastError());
-      hipLaunchKernelGGL(k_merge_finish, dim3(nq), dim3(256), 0, s, mc + f, dh, d_res.p, d_k.p);
-      NURI_HIP(hipGetLastError());
+      launch_merge(mc + f, dh, mids + (u64)f * QM, (uint32_t)QM, d_res.p, d_k.p, mpos.p, nq, kmax,
+                   h_ccount.p[0], s);
       NURI_HIP(hipStreamSynchronize(s));  // the pinned chunk size is rewritten next round
     }
     NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
