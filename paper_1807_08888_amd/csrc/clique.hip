@@ -91,8 +91,8 @@ struct QCtr {  // per query, cumulative counters
 };
 
 struct GView {
-  const uint32_t *dplus, *split, *oplus, *orig, *rcol;
-  const uint64_t *ooff, *bm_off, *rrow;
+  const uint32_t *dplus, *split, *oplus, *orig, *rcol, *hcol;
+  const uint64_t *ooff, *bm_off, *rrow, *hrow;
   const u64 *bm;
   const int32_t *wloc, *vw;
   const int64_t *wplus;
@@ -263,6 +263,75 @@ __global__ void k_copy_back(const SelSeg *segs, const QCfg *cfg, const CRec *tem
 }
 
 // ------------------------------------------------------------------
+// seed cliques: an early k-th score
+// ------------------------------------------------------------------
+// Before the search, one wavefront per root (the first `count` roots in
+// bound order) builds a clique greedily: starting from the root's later
+// neighbours it adds the highest remaining position and keeps the
+// positions adjacent to it, until none is left.  The result goes through
+// the same maximality check and merge as any leaf, so the k-th score
+// starts at the k-th best of these cliques instead of at minus infinity;
+// any k maximal cliques give a valid lower bound of the final k-th score.
+// The search later finds these cliques again; the merge drops a candidate
+// equal to an item already in the top-k.
+struct SeedSeg {
+  uint32_t qid, kind, count, pad;
+};
+
+__global__ void __launch_bounds__(256)
+    k_seed_dive(GView g, const SeedSeg *segs, LRec *leaves, u64 *leaf_words, StepHdr *hdr,
+                uint32_t leaf_cap, u64 leaf_word_cap, QStep *qs) {
+  const int lane = threadIdx.x & 63;
+  const SeedSeg sg = segs[blockIdx.y];
+  const uint32_t i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= sg.count) return;
+  const uint32_t r = g.root_order[sg.kind][i];
+  const uint32_t d = g.dplus[r];
+  const uint32_t W = words_of(d);
+  const int32_t *wl = g.wloc + g.ooff[r];
+  const u64 *rows = g.bm + g.bm_off[r];
+  long long score = sg.kind ? (long long)g.vw[r] : 1ll;
+  u64 P = (lane < (int)W) ? lt_mask(lane, d) : 0ull, V = 0;
+  int last = -1;
+  while (__ballot(P != 0)) {
+    int hb = P ? lane * 64 + 63 - (int)__clzll(P) : -1;
+    for (int o2 = 32; o2 > 0; o2 >>= 1) {
+      const int y = __shfl_xor(hb, o2, 64);
+      hb = y > hb ? y : hb;
+    }
+    last = hb;
+    score += sg.kind ? (long long)wl[hb] : 1ll;
+    if (lane == (hb >> 6)) {
+      V |= 1ull << (hb & 63);
+      P &= ~(1ull << (hb & 63));
+    }
+    if (lane < (int)W) P &= rows[(u64)hb * W + lane];
+  }
+  unsigned int slot = 0;
+  u64 w0 = 0;
+  if (lane == 0) {
+    slot = atomicAdd(&hdr->leaf_count, 1u);
+    w0 = atomicAdd(&hdr->leaf_word_count, (u64)W);
+  }
+  slot = __shfl(slot, 0, 64);
+  w0 = __shfl(w0, 0, 64);
+  if (slot >= leaf_cap || w0 + W > leaf_word_cap) {
+    if (lane == 0) atomicAdd(&qs[sg.qid].overflow, 1u);
+    return;
+  }
+  if (lane < (int)W) leaf_words[w0 + lane] = V;
+  if (lane == 0) {
+    LRec l;
+    l.score = score;
+    l.woff = w0;
+    l.root = r;
+    l.last = (int16_t)last;
+    l.qid = (uint16_t)sg.qid;
+    leaves[slot] = l;
+  }
+}
+
+// ------------------------------------------------------------------
 // expand (Algorithm 1, lines 11-16)
 // ------------------------------------------------------------------
 // One wavefront per record.  The record's candidate positions are listed
@@ -309,6 +378,8 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   __shared__ long long s_cscore[kExpandWaves], s_cbound[kExpandWaves];
   __shared__ int s_cj[kExpandWaves];
   __shared__ uint32_t s_ccnt[kExpandWaves];
+  __shared__ u64 s_cost[kExpandWaves], s_maxcc[kExpandWaves];
+  __shared__ long long s_maxb[kExpandWaves];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   u64 *s_pw = s_dyn + (u64)wv * 5 * wst;
   u64 *s_vw = s_pw + wst;
@@ -323,9 +394,15 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   const QCfg cf = cfg[q];
   const long long theta = res[q].theta;
   const bool weighted = cf.weighted != 0;
+  // wave-uniform counters; the per-child ones of written children are
+  // gathered in LDS by the lanes that write them
   u64 st_popped = 0, st_pruned_pop = 0, st_expanded = 0, st_children = 0, st_pruned_new = 0,
-      st_leaves = 0, st_bytes = 0, st_cost_c = 0, st_cost_w = 0, st_max_cc = 0;
-  long long st_maxb = LLONG_MIN;
+      st_leaves = 0, st_bytes = 0;
+  if (lane == 0) {
+    s_cost[wv] = 0;
+    s_maxcc[wv] = 0;
+    s_maxb[wv] = LLONG_MIN;
+  }
 
   const uint32_t r = p.root;
   const uint32_t d = g.dplus[r];
@@ -350,12 +427,11 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       const int jc = s_cj[wv];
       put_crec(cf.hdr, hs, s_cscore[wv], s_cbound[wv], ws, r, jc, q);
       const u64 cc = (u64)(d - jc - 1);
-      st_cost_c += cc;
-      st_cost_w += cc * 2 * W;
-      st_max_cc = cc > st_max_cc ? cc : st_max_cc;
-      st_maxb = s_cbound[wv] > st_maxb ? s_cbound[wv] : st_maxb;
-      st_bytes += 32 + 16ull * W;
+      atomicAdd(&s_cost[wv], cc);
+      atomicMax(&s_maxcc[wv], cc);
+      atomicMax(&s_maxb[wv], s_cbound[wv]);
     }
+    st_bytes += 32 + 16ull * W;
   };
 
   for (;;) {
@@ -411,17 +487,32 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     // idx, idx+1, ...); past the first idx where that is below theta every
     // child is dominated
     uint32_t n_eff = nchild;
+    // whole: every candidate is needed to reach theta (dropping any one
+    // falls below it), so the only clique of this subtree that can enter
+    // the top-k is V + P, and it exists iff P is a clique
+    bool whole = false;
     if (theta != LLONG_MIN) {
       if (!weighted) {
         // each candidate weighs 1: child idx reaches score + nchild - idx
         const long long R = p.score + (long long)nchild - theta;
         n_eff = R < 0 ? 0u : (uint32_t)(R + 1 < (long long)nchild ? R + 1 : nchild);
+        whole = R == 0 && nchild > 0;
       } else {
         long long lsum = 0;
-        for (u64 t = pw; t; t &= t - 1) lsum += wl[lane * 64 + __ffsll((long long)t) - 1];
+        int32_t lmin = INT32_MAX;
+        for (u64 t = pw; t; t &= t - 1) {
+          const int32_t wt = wl[lane * 64 + __ffsll((long long)t) - 1];
+          lsum += wt;
+          lmin = wt < lmin ? wt : lmin;
+        }
+        for (int o2 = 32; o2 > 0; o2 >>= 1) {
+          const int32_t y = __shfl_xor(lmin, o2, 64);
+          lmin = y < lmin ? y : lmin;
+        }
         const long long lexcl = wave_excl_scan64(lsum, lane);
         const long long total = __shfl(lexcl + lsum, 63, 64);
         const long long R = total + p.score - theta;
+        whole = R >= 0 && R < (long long)lmin && nchild > 0;
         uint32_t cut = 0xFFFFFFFFu;
         if (R < 0) {
           cut = 0;
@@ -451,7 +542,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       // Classes are built until that sum reaches theta - score; children
       // above the top of the last class built are dominated.
       const long long need = theta - p.score;
-      if (cf.colour_min && n_eff >= cf.colour_min && need > 0) {
+      if (!whole && cf.colour_min && n_eff >= cf.colour_min && need > 0) {
         u64 U = pw, Q = 0;
         long long run = 0;
         int cut_pos = -1;  // children at positions <= cut_pos survive
@@ -491,16 +582,80 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       }
     }
     // list the positions of the children that get built
+    const uint32_t n_list = whole ? nchild : n_eff;
     {
       uint32_t o = off;
-      for (u64 t = pw; t && o < n_eff; t &= t - 1)
+      for (u64 t = pw; t && o < n_list; t &= t - 1)
         s_list[o++] = (uint16_t)(lane * 64 + __ffsll((long long)t) - 1);
     }
     wave_sync();
-    if (last >= 0 && !carried && lane == 0) st_bytes += 32 + 16ull * W;  // the parent record
+    if (last >= 0) st_bytes += 32 + 16ull * W;  // the parent record
     if (nchild) st_expanded += 1;
     st_children += nchild;
-    st_pruned_new += nchild - n_eff;
+    if (whole) {
+      // test every candidate's row against the rest of P at once (the
+      // loads are independent) instead of one chained step per member
+      // also: a vertex of X adjacent to all of P extends V + P, which is
+      // then not maximal
+      bool clique = true;
+      u64 xacc = (wi < (int)W) ? s_xw[wi] : 0ull;
+      for (uint32_t b0 = 0; b0 < nchild && clique; b0 += 8 * per) {
+        int bad = 0;
+        for (uint32_t u = 0; u < 8; ++u) {
+          const uint32_t ci = b0 + u * per + lane / G;
+          if (ci < nchild && wi < (int)W) {
+            const uint32_t j = s_list[ci];
+            const u64 own = (wi == (int)(j >> 6)) ? (1ull << (j & 63)) : 0ull;
+            const u64 row = rows[(u64)j * W + wi];
+            bad |= (s_pw[wi] & ~own & ~row) != 0ull;
+            xacc &= row;
+          }
+        }
+        clique = __ballot(bad) == 0;
+      }
+      st_bytes += 8ull * W * nchild;
+      // AND the X accumulators of the lane groups holding the same word
+      for (uint32_t o2 = G; o2 < 64; o2 <<= 1) xacc &= __shfl_xor(xacc, o2, 64);
+      if (clique && __ballot(wi < (int)W && xacc != 0ull)) clique = false;
+      st_pruned_new += nchild - (clique ? 1 : 0);
+      n_eff = 0;  // no child is built one by one
+      if (clique) {
+        // offer V + P (every candidate added) as a leaf
+        st_leaves += 1;
+        long long tot = 0;
+        if (weighted) {
+          for (u64 t = pw; t; t &= t - 1) tot += wl[lane * 64 + __ffsll((long long)t) - 1];
+          tot = (long long)wave_sum((u64)tot);
+        } else {
+          tot = nchild;
+        }
+        unsigned int l0 = 0;
+        u64 w0 = 0;
+        if (lane == 0) {
+          l0 = atomicAdd(&hdr->leaf_count, 1u);
+          w0 = atomicAdd(&hdr->leaf_word_count, (u64)W);
+        }
+        l0 = __shfl(l0, 0, 64);
+        w0 = __shfl(w0, 0, 64);
+        if (l0 < leaf_cap && w0 + W <= leaf_word_cap) {
+          if (lane < (int)W) leaf_words[w0 + lane] = s_vw[lane] | s_pw[lane];
+          if (lane == 0) {
+            LRec l;
+            l.score = p.score + tot;
+            l.woff = w0;
+            l.root = r;
+            l.last = (int16_t)last;
+            l.qid = (uint16_t)q;
+            leaves[l0] = l;
+          }
+          st_bytes += 24 + 8ull * W;
+        } else if (lane == 0) {
+          atomicAdd(&qs[q].overflow, 1u);
+        }
+      }
+    } else {
+      st_pruned_new += nchild - n_eff;
+    }
     // kept children: the first is held back (in s_cv/s_cx) in case it
     // stays the only one; `spilled` once it has been written out
     bool held = false, spilled = false;
@@ -548,8 +703,8 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       const u64 fm = __ballot(leader && offer);
       st_pruned_new += __popcll(__ballot(leader && prune));
       st_leaves += __popcll(__ballot(leader && leaf));
-      if (lane == 0) st_bytes += 8ull * W * __popcll(lm);  // adjacency rows read
-      if (wi == 0 && valid && x0 != 0x7FFFFFFF) st_bytes += 8ull * W;  // witness row
+      st_bytes += 8ull * W * __popcll(lm);  // adjacency rows read
+      st_bytes += 8ull * W * __popcll(__ballot(wi == 0 && valid && x0 != 0x7FFFFFFF));  // witness
       const u64 jbit = (wi == (int)(j >> 6)) ? (1ull << (j & 63)) : 0ull;
       if (km) {
         if (!held && __popcll(km) == 1) {
@@ -599,13 +754,12 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
               if (wi == 0) {
                 put_crec(cf.hdr, (u64)cf.out_hdr + h0 + rk, score2, bound2, slot_w, r, (int)j, q);
                 const u64 cc = (u64)(d - j - 1);
-                st_cost_c += cc;
-                st_cost_w += cc * 2 * W;
-                st_max_cc = cc > st_max_cc ? cc : st_max_cc;
-                st_maxb = bound2 > st_maxb ? bound2 : st_maxb;
-                st_bytes += 32 + 16ull * W;
+                atomicAdd(&s_cost[wv], cc);
+                atomicMax(&s_maxcc[wv], cc);
+                atomicMax(&s_maxb[wv], bound2);
               }
             }
+            st_bytes += (32 + 16ull * W) * __popcll(km);
           }
           held = true;
           spilled = true;
@@ -613,6 +767,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       }
       if (fm) {
         const uint32_t nf = __popcll(fm);
+        st_bytes += (24 + 8ull * W) * nf;
         unsigned int l0 = 0;
         u64 w0 = 0;
         if (lane == 0) {
@@ -635,7 +790,6 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
               l.last = (int16_t)j;
               l.qid = (uint16_t)q;
               leaves[slot_l] = l;
-              st_bytes += 24 + 8ull * W;
             }
           } else if (wi == 0) {
             atomicAdd(&qs[q].overflow, 1u);
@@ -694,11 +848,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   }
   if (lane == 0 && credit) atomicSub(&hdr->chain_c, credit);
   // flush per-wave statistics with one atomic each
-  st_cost_c = wave_sum(st_cost_c);
-  st_cost_w = wave_sum(st_cost_w);
-  st_bytes = wave_sum(st_bytes);
-  st_max_cc = wave_max_u64(st_max_cc);
-  st_maxb = wave_max(st_maxb);
+  wave_sync();
   if (lane == 0) {
     QCtr &C = ctr[q];
     atomicAdd(&C.popped, st_popped);
@@ -709,13 +859,14 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     if (st_leaves) atomicAdd(&C.leaves, st_leaves);
     if (st_bytes) atomicAdd(&C.logical_bytes, st_bytes);
     QStep &S = qs[q];
-    if (st_cost_c) {
-      atomicAdd(&S.out_cost_children, st_cost_c);
-      atomicAdd(&S.out_cost_words, st_cost_w);
-      atomicMax(&S.out_max_cc, st_max_cc);
+    const u64 cost = s_cost[wv];
+    if (cost) {
+      atomicAdd(&S.out_cost_children, cost);
+      atomicAdd(&S.out_cost_words, cost * 2 * W);
+      atomicMax(&S.out_max_cc, s_maxcc[wv]);
       atomicMax(&S.out_max_w, W);
     }
-    if (st_maxb != LLONG_MIN) atomicMax(&S.out_max_bound, st_maxb);
+    if (s_maxb[wv] != LLONG_MIN) atomicMax(&S.out_max_bound, s_maxb[wv]);
   }
 }
 
@@ -757,35 +908,43 @@ __global__ void __launch_bounds__(64)
     uint32_t o = off;
     while (t) {
       int b = __ffsll((long long)t) - 1;
-      s_rank[o++] = np[lane * 64 + b];
+      s_rank[o] = np[lane * 64 + b];
+      s_sorted[o++] = lane * 64 + b;  // local positions, for (a)
       t &= t - 1;
     }
   }
   if (lane == 0) s_rank[nm] = r;
   wave_sync();
   const uint32_t nc = nm + 1;  // clique size
-  // (a) local extension
+  // (a) local extension: groups of G lanes AND the members' rows, 64/G
+  // members per round (independent loads), then the groups are combined
   if (d) {
-    u64 x = (lane < (int)W) ? (~v & lt_mask(lane, d)) : 0ull;
     const u64 *rows = g.bm + g.bm_off[r];
-    // walk members in position order via their bits
-    for (int w = 0; w < (int)W && __ballot(x != 0); ++w) {
-      u64 mw = __shfl(v, w, 64);
-      while (mw && __ballot(x != 0)) {
-        int b = __ffsll((long long)mw) - 1;
-        uint32_t i = w * 64 + b;
-        if (lane < (int)W) x &= rows[(u64)i * W + lane];
-        mw &= mw - 1;
-      }
+    uint32_t G = 1;
+    while (G < W) G <<= 1;
+    const uint32_t per = 64 / G;
+    const int wi = lane & (G - 1);
+    u64 acc = ~0ull;
+#pragma unroll 8
+    for (uint32_t b0 = 0; b0 < nm; b0 += per) {
+      const uint32_t ci = b0 + lane / G;
+      if (ci < nm && wi < (int)W) acc &= rows[(u64)s_sorted[ci] * W + wi];
     }
+    for (uint32_t o2 = G; o2 < 64; o2 <<= 1) acc &= __shfl_xor(acc, o2, 64);
+    const u64 x = (lane < (int)W) ? (~v & lt_mask(lane, d) & acc) : 0ull;
     if (__ballot(x != 0)) return;
   }
+  wave_sync();  // s_sorted is rewritten below
   // (b) extension by a vertex ranked below r
   {
-    // member with the fewest lower neighbours
+    // an extender u has |N+(u)| >= nc; for nc >= kHeavy only the heavy
+    // part of the lower neighbour lists can hold one
+    const bool heavy = nc >= kHeavy;
+    // member with the fewest (heavy) lower neighbours
     uint32_t bestc = 0xFFFFFFFFu, besti = 0;
     for (uint32_t t = lane; t < nc; t += 64) {
-      uint32_t s = g.split[s_rank[t]];
+      const uint32_t m = s_rank[t];
+      const uint32_t s = heavy ? (uint32_t)(g.hrow[m + 1] - g.hrow[m]) : g.split[m];
       if (s < bestc) { bestc = s; besti = t; }
     }
     for (int o2 = 32; o2 > 0; o2 >>= 1) {
@@ -793,34 +952,44 @@ __global__ void __launch_bounds__(64)
       if (oc < bestc || (oc == bestc && oi < besti)) { bestc = oc; besti = oi; }
     }
     const uint32_t cs = s_rank[besti];
-    const uint32_t *lo_list = g.rcol + g.rrow[cs];
-    // entries of N-(cs) below r form a prefix (rows are sorted)
-    uint32_t lo = 0, hi = g.split[cs];
+    const uint32_t *lo_list = heavy ? g.hcol + g.hrow[cs] : g.rcol + g.rrow[cs];
+    // entries below r form a prefix (lists are sorted by rank)
+    uint32_t lo = 0, hi = bestc;
     while (lo < hi) {
       uint32_t mid = (lo + hi) >> 1;
       if (lo_list[mid] < r) lo = mid + 1; else hi = mid;
     }
     const uint32_t nu = lo;
+    // u is ranked below every member and adjacent to all nc of them, so
+    // |N+(u)| >= nc: that one load rejects almost every u.  Each remaining
+    // u is then tested by the whole wave, 64 members at a time.
     for (uint32_t b0 = 0; b0 < nu; b0 += 64) {
-      bool ext = false;
-      uint32_t t = b0 + lane;
-      if (t < nu) {
-        uint32_t u = lo_list[t];
-        const uint32_t *up = g.oplus + g.ooff[u];
-        uint32_t du = g.dplus[u];
-        ext = true;
-        for (uint32_t m = 0; m < nc && ext; ++m) {
-          if (m == besti) continue;
-          uint32_t x = s_rank[m];
-          uint32_t a = 0, z = du;
-          while (a < z) {
-            uint32_t mid = (a + z) >> 1;
-            if (up[mid] < x) a = mid + 1; else z = mid;
+      const uint32_t t = b0 + lane;
+      const uint32_t u = t < nu ? lo_list[t] : 0u;
+      u64 cand = __ballot(t < nu && g.dplus[u] >= nc);
+      while (cand) {
+        const int src = __ffsll((long long)cand) - 1;
+        cand &= cand - 1;
+        const uint32_t uu = __shfl(u, src, 64);
+        const uint32_t *up = g.oplus + g.ooff[uu];
+        const uint32_t du = g.dplus[uu];
+        bool all = true;
+        for (uint32_t m0 = 0; m0 < nc && all; m0 += 64) {
+          const uint32_t m = m0 + lane;
+          bool miss = false;
+          if (m < nc) {
+            const uint32_t x = s_rank[m];
+            uint32_t a = 0, z = du;
+            while (a < z) {
+              const uint32_t mid = (a + z) >> 1;
+              if (up[mid] < x) a = mid + 1; else z = mid;
+            }
+            miss = !(a < du && up[a] == x);
           }
-          ext = a < du && up[a] == x;
+          all = __ballot(miss) == 0;
         }
+        if (all) return;
       }
-      if (__ballot(ext)) return;
     }
   }
   // maximal: emit (score, ascending original ids)
@@ -868,6 +1037,7 @@ struct QHost {
   std::vector<Level> stack;
   uint64_t cursor = 0;
   long long theta = LLONG_MIN;
+  bool seeded = false;  // seed cliques offered
   uint32_t hdr_cap = 0;
   u64 word_cap = 0;
   uint64_t t_admit = 0, steps = 0, expand_ns = 0, launches = 0, peak_bytes = 0;
@@ -932,6 +1102,8 @@ struct Engine {
   PoolBuf<u64> leaf_words;
   PoolBuf<Cand> cands;
   PoolBuf<uint32_t> mpos;  // merge: position of each candidate among the top-k
+  PinBuf<SeedSeg> h_seed;
+  PoolBuf<SeedSeg> d_seed;
   PoolBuf<uint32_t> cand_ids;
   PoolBuf<unsigned int> d_hist;
   PoolBuf<u64> d_hchild;
@@ -971,6 +1143,8 @@ struct Engine {
     v.ooff = g.ooff.p;
     v.bm_off = g.bm_off.p;
     v.rrow = g.rrow.p;
+    v.hrow = g.hrow.p;
+    v.hcol = g.hcol.p;
     v.bm = (const u64 *)g.bm.p;
     v.wloc = g.wloc.p;
     v.vw = g.vw.p;
@@ -1055,6 +1229,8 @@ struct Engine {
     leaf_words.alloc(g.pool, leaf_word_cap);
     cands.alloc(g.pool, kCandChunk);
     mpos.alloc(g.pool, kCandChunk);
+    h_seed.alloc(nq);
+    d_seed.alloc(g.pool, nq);
     cand_ids.alloc(g.pool, (u64)kCandChunk * lmax);
     d_hist.alloc(g.pool, (u64)nq * kBins);
     d_hchild.alloc(g.pool, (u64)nq * kBins);
@@ -1354,33 +1530,73 @@ struct Engine {
                                                         T.wend * 8);
       }
     }
-    // leaves -> maximality check -> merge, in chunks
-    const uint32_t nleaf = sh()->leaf_count;
+    offer_leaves(sh()->leaf_count);
+  }
+
+  // leaves in the leaf buffer -> maximality check -> merge, in chunks;
+  // then every query's k-th score is read back
+  void offer_leaves(uint32_t nleaf) {
     if (nleaf > leaf_cap) throw Error{NURI_EBUDGET, "leaf buffer overflow (internal)"};
-    if (nleaf) {
-      uint32_t kmax = 0;
-      for (auto &Q : qh)
-        if (Q.active) kmax = std::max(kmax, Q.k);
-      for (uint32_t f = 0; f < nleaf; f += kCandChunk) {
-        const uint32_t cnt = std::min<uint32_t>(kCandChunk, nleaf - f);
-        NURI_HIP(hipMemsetAsync(&dh->cand_count, 0, sizeof(unsigned int), s));
-        hipLaunchKernelGGL(k_leaf_check, dim3(cnt), dim3(64), 0, s, gv, leaves.p, f,
-                           leaf_words.p, d_res.p, cands.p, &dh->cand_count, cand_ids.p, lmax,
-                           d_ctr.p);
-        NURI_HIP(hipGetLastError());
-        launch_merge(cands.p, dh, cand_ids.p, lmax, d_res.p, d_k.p, mpos.p, nq, kmax, cnt, s);
-      }
-      NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
-      NURI_HIP(hipStreamSynchronize(s));
-      for (uint32_t i = 0; i < nq; ++i)
-        if (qh[i].active) qh[i].theta = h_res.p[i].theta;
+    if (!nleaf) return;
+    GView gv = view();
+    StepHdr *dh = dev<StepHdr>(0);
+    uint32_t kmax = 0;
+    for (auto &Q : qh)
+      if (Q.active) kmax = std::max(kmax, Q.k);
+    for (uint32_t f = 0; f < nleaf; f += kCandChunk) {
+      const uint32_t cnt = std::min<uint32_t>(kCandChunk, nleaf - f);
+      NURI_HIP(hipMemsetAsync(&dh->cand_count, 0, sizeof(unsigned int), s));
+      hipLaunchKernelGGL(k_leaf_check, dim3(cnt), dim3(64), 0, s, gv, leaves.p, f, leaf_words.p,
+                         d_res.p, cands.p, &dh->cand_count, cand_ids.p, lmax, d_ctr.p);
+      NURI_HIP(hipGetLastError());
+      launch_merge(cands.p, dh, cand_ids.p, lmax, d_res.p, d_k.p, mpos.p, nq, kmax, cnt, s);
     }
+    NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
+    NURI_HIP(hipStreamSynchronize(s));
+    for (uint32_t i = 0; i < nq; ++i)
+      if (qh[i].active) qh[i].theta = h_res.p[i].theta;
+  }
+
+  // seed cliques for queries that have none yet (see k_seed_dive)
+  void seed_new() {
+    uint32_t ns = 0, maxc = 0;
+    u64 total = 0;
+    for (uint32_t i = 0; i < nq; ++i) {
+      QHost &Q = qh[i];
+      if (!Q.active || Q.done || Q.seeded) continue;
+      const u64 want = std::min<u64>(g.n, std::max<u64>(2ull * Q.k, 512));
+      const u64 room = std::min<u64>(leaf_cap, leaf_word_cap / ex_wst);
+      if (total + want > room) break;  // the rest seed at the next step
+      Q.seeded = true;
+      SeedSeg &sg = h_seed.p[ns++];
+      sg.qid = i;
+      sg.kind = (uint32_t)Q.kind;
+      sg.count = (uint32_t)want;
+      sg.pad = 0;
+      total += want;
+      maxc = std::max<uint32_t>(maxc, sg.count);
+    }
+    if (!ns) return;
+    StepHdr *dh = dev<StepHdr>(0);
+    QStep *dqs = dev<QStep>(L->qs);
+    NURI_HIP(hipMemsetAsync(d_step.p, 0, L->cfg, s));  // counters and overflow flags
+    NURI_HIP(hipMemcpyAsync(d_seed.p, h_seed.p, ns * sizeof(SeedSeg), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_seed_dive, dim3((maxc + 3) / 4, ns), dim3(256), 0, s, view(), d_seed.p,
+                       leaves.p, leaf_words.p, dh, leaf_cap, leaf_word_cap, dqs);
+    NURI_HIP(hipGetLastError());
+    NURI_HIP(hipMemcpyAsync(h_step.p, d_step.p, L->readback(), hipMemcpyDeviceToHost, s));
+    NURI_HIP(hipStreamSynchronize(s));
+    for (uint32_t t = 0; t < ns; ++t)
+      if (sq()[h_seed.p[t].qid].overflow)
+        throw Error{NURI_EBUDGET, "leaf buffer overflow while seeding (internal)"};
+    offer_leaves(sh()->leaf_count);
   }
 
   // one step for every live query; false when none has work left
   bool step_all() {
     uint32_t nseg, nrseg, batch_ub, mseg, mrseg;
     u64 temp_need;
+    seed_new();
     const uint64_t t0 = trace ? now_ns() : 0;
     if (!plan(nseg, nrseg, batch_ub, temp_need, mseg, mrseg)) return false;
     const uint64_t t1 = trace ? now_ns() : 0;

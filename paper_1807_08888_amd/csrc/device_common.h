@@ -151,7 +151,8 @@ __device__ inline bool wave_before(long long sa, const uint32_t *a, uint32_t la,
 //   k_merge_pos: one wave per candidate finds, by binary search, how many
 //     current top-k items precede it.  A candidate preceded by k or more
 //     can never enter (everything that will precede a member of the new
-//     top-k precedes it too), so it is dropped.
+//     top-k precedes it too), so it is dropped; so is a candidate equal to
+//     a top-k item (a result offered twice).
 //   k_merge_rank: one wave per item of (top-k, surviving candidates) of a
 //     query counts the survivors that precede it; with its position in
 //     the top-k that is its rank in the union.  Items ranked below k are
@@ -180,7 +181,10 @@ __global__ void __launch_bounds__(64 * kMergeWaves)
     else
       hi = mid;
   }
-  if (lane == 0) pos[c] = lo < ks[cd.qid] ? lo : kDropped;
+  // an item equal to the candidate (it was offered before) drops it
+  const bool dup = lo < n && !wave_before(cd.score, ids, cd.len, R.tk_score[cur][lo],
+                                          R.tk_ids[cur] + (u64)lo * lmax, R.tk_len[cur][lo], lane);
+  if (lane == 0) pos[c] = lo < ks[cd.qid] && !dup ? lo : kDropped;
 }
 
 __global__ void __launch_bounds__(64 * kMergeWaves)

@@ -176,7 +176,8 @@ __global__ void __launch_bounds__(256) k_build_bitmaps(
 }
 
 uint64_t Graph::device_bytes() const {
-  return rrow.bytes() + rcol.bytes() + split.bytes() + dplus.bytes() + orig.bytes() + vw.bytes() +
+  return rrow.bytes() + rcol.bytes() + split.bytes() + dplus.bytes() + hrow.bytes() +
+         hcol.bytes() + orig.bytes() + vw.bytes() +
          bm_off.bytes() + bm.bytes() + wplus.bytes() + best.bytes() +
          orow.bytes() + lcol.bytes() + lew.bytes() + loff.bytes() + lab_vert.bytes() +
          root_order[0].bytes() + root_order[1].bytes() + ooff.bytes() + oplus.bytes() +
@@ -243,6 +244,20 @@ Graph *load_graph(const nuri_csr *csr, hipStream_t stream) {
   });
   g.h_dplus = dplus;
   g.degeneracy = n ? *std::max_element(dplus.begin(), dplus.end()) : 0;
+  std::vector<uint64_t> hrow(n + 1, 0);
+  for (uint32_t r = 0; r < n; ++r) {
+    uint64_t h = 0;
+    for (uint64_t k = rrow[r]; k < rrow[r] + split[r]; ++k) h += dplus[rcol[k]] >= kHeavy;
+    hrow[r + 1] = hrow[r] + h;
+  }
+  std::vector<uint32_t> hcol(hrow[n]);
+  parallel_chunks(n, [&](uint64_t b, uint64_t e) {
+    for (uint64_t r = b; r < e; ++r) {
+      uint64_t o = hrow[r];
+      for (uint64_t k = rrow[r]; k < rrow[r] + split[r]; ++k)
+        if (dplus[rcol[k]] >= kHeavy) hcol[o++] = rcol[k];
+    }
+  });
   if (g.degeneracy > kMaxLocal)
     fail("degeneracy " + std::to_string(g.degeneracy) + " exceeds the supported maximum 4096");
 
@@ -341,6 +356,9 @@ Graph *load_graph(const nuri_csr *csr, hipStream_t stream) {
   upload(g.rcol, rcol.data(), rcol.size(), s);
   upload(g.split, split.data(), n, s);
   upload(g.dplus, dplus.data(), n, s);
+  upload(g.hrow, hrow.data(), n + 1, s);
+  if (hcol.empty()) hcol.push_back(0);  // keep the device pointer valid
+  upload(g.hcol, hcol.data(), hcol.size(), s);
   upload(g.orig, g.h_orig.data(), n, s);
   upload(g.vw, vwr.data(), n, s);
   upload(g.bm_off, bm_off.data(), n + 1, s);

@@ -18,6 +18,7 @@ namespace nuri {
 // of a 64-wide wavefront.
 constexpr uint32_t kMaxLocal = 4096;
 constexpr uint32_t kMaxWords = kMaxLocal / 64;
+constexpr uint32_t kHeavy = 32;
 
 // ------------------------------------------------------------------
 // errors
@@ -155,6 +156,11 @@ struct Graph {
   DevBuf<uint32_t> rcol;
   DevBuf<uint32_t> split;
   DevBuf<uint32_t> dplus;     // |N+(r)|
+  // heavy lower neighbours: the part of N-(r) whose |N+(u)| >= kHeavy,
+  // sorted by rank (a vertex that extends a clique of c >= kHeavy members
+  // ranked above it has |N+(u)| >= c)
+  DevBuf<uint64_t> hrow;
+  DevBuf<uint32_t> hcol;
   DevBuf<uint32_t> orig;      // rank -> original id
   DevBuf<int32_t> vw;         // vertex weight by rank
   DevBuf<uint64_t> bm_off;    // [n+1] word offset of r's local bitmap
