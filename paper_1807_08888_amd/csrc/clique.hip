@@ -79,7 +79,7 @@ struct QCfg {  // per query, written by the host each step
 };
 
 struct QStep {  // per query, this step's counters (zeroed by the step upload)
-  unsigned int n_out, n_kept;
+  unsigned int n_out, pad;
   u64 out_words, out_cost_children, out_cost_words;
   long long out_max_bound;
   u64 out_max_cc;  // largest children bound of one appended record
@@ -252,14 +252,13 @@ __global__ void k_sel_part(const SelSeg *segs, const QCfg *cfg, const QRes *res,
 }
 
 __global__ void k_copy_back(const SelSeg *segs, const QCfg *cfg, const CRec *temp,
-                            const unsigned int *temp_count, QStep *qs) {
+                            const unsigned int *temp_count) {
   const uint32_t s = blockIdx.y;
   const SelSeg sg = segs[s];
   const unsigned int kept = sg.take_all ? 0u : temp_count[s];
   CRec *h = cfg[sg.qid].hdr + sg.begin;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < kept; i += gridDim.x * blockDim.x)
     h[i] = temp[sg.temp_off + i];
-  if (blockIdx.x == 0 && threadIdx.x == 0) qs[sg.qid].n_kept = kept;
 }
 
 // ------------------------------------------------------------------
@@ -1045,7 +1044,7 @@ struct QHost {
   int plan = 0;  // 0 idle, 1 roots, 2 level
   uint32_t new_begin = 0;
   u64 new_wbegin = 0;
-  int sel_seg = -1;
+  uint32_t seg0 = 0, nsegs = 0;  // this step's segments: seg0 .. seg0 + nsegs - 1
 };
 
 // per-slot top-k buffers (two of each, switched by every merge)
@@ -1057,28 +1056,34 @@ struct SlotTopk {
 // Layout of the per-step block that one host-to-device copy uploads and
 // one device-to-host copy (of its first part) reads back.
 struct StepLayout {
-  size_t qs, cfg, seg, rseg, taken, tempc, thr, quota, total;
-  explicit StepLayout(uint32_t nq) {
+  // StepHdr | QStep[nq] | tempc[ns] (read back) | cfg[nq] | rseg[nq] |
+  // taken[ns] | thr[ns] | quota[ns] | seg[ns] (uploaded up to the last used)
+  size_t qs, tempc, cfg, rseg, taken, thr, quota, seg, total;
+  uint32_t nseg_cap;
+  StepLayout(uint32_t nq, uint32_t ns) : nseg_cap(ns) {
     size_t o = sizeof(StepHdr);
     qs = o;
     o += nq * sizeof(QStep);
+    tempc = o;
+    o += ns * 4;
+    o = (o + 15) & ~size_t(15);
     cfg = o;
     o += nq * sizeof(QCfg);
-    seg = o;
-    o += nq * sizeof(SelSeg);
     rseg = o;
     o += nq * sizeof(RootSeg);
     taken = o;
-    o += nq * 4;
-    tempc = o;
-    o += nq * 4;
+    o += ns * 4;
     thr = o;
-    o += nq * 4;
+    o += ns * 4;
     quota = o;
-    o += nq * 4;
+    o += ns * 4;
+    o = (o + 15) & ~size_t(15);
+    seg = o;
+    o += ns * sizeof(SelSeg);
     total = (o + 255) & ~size_t(255);
   }
-  size_t readback() const { return cfg; }  // StepHdr + QStep[nq]
+  size_t readback() const { return cfg; }  // StepHdr + QStep[nq] + tempc[ns]
+  size_t upload(uint32_t nseg) const { return seg + nseg * sizeof(SelSeg); }
 };
 
 struct Engine {
@@ -1105,6 +1110,10 @@ struct Engine {
   PinBuf<SeedSeg> h_seed;
   PoolBuf<SeedSeg> d_seed;
   PoolBuf<uint32_t> cand_ids;
+  // selection segments: up to kSegPerQuery levels of one query per step
+  static constexpr uint32_t kSegPerQuery = 8;
+  uint32_t seg_cap = 0;
+  std::vector<uint32_t> seg_level;  // level index (in its query's stack) of each segment
   PoolBuf<unsigned int> d_hist;
   PoolBuf<u64> d_hchild;
   PoolBuf<unsigned char> d_step;
@@ -1180,7 +1189,9 @@ struct Engine {
     cfg.assign(nq, QCfg{});
     tk.clear();
     for (uint32_t i = 0; i < nq; ++i) tk.emplace_back(new SlotTopk);
-    L.reset(new StepLayout(nq));
+    seg_cap = std::min<uint32_t>(nq * kSegPerQuery, std::max<uint32_t>(nq, 1024));
+    L.reset(new StepLayout(nq, seg_cap));
+    seg_level.assign(seg_cap, 0);
     const u64 budget = o.frontier_budget;
     const u64 per_q = budget / nq;
     u64 hdr_per_q = std::max<u64>(1024, per_q / 3 / sizeof(CRec));
@@ -1232,8 +1243,8 @@ struct Engine {
     h_seed.alloc(nq);
     d_seed.alloc(g.pool, nq);
     cand_ids.alloc(g.pool, (u64)kCandChunk * lmax);
-    d_hist.alloc(g.pool, (u64)nq * kBins);
-    d_hchild.alloc(g.pool, (u64)nq * kBins);
+    d_hist.alloc(g.pool, (u64)seg_cap * kBins);
+    d_hchild.alloc(g.pool, (u64)seg_cap * kBins);
     NURI_HIP(hipMemsetAsync(d_hist.p, 0, d_hist.bytes(), s));
     NURI_HIP(hipMemsetAsync(d_hchild.p, 0, d_hchild.bytes(), s));
     d_step.alloc(g.pool, L->total);
@@ -1317,7 +1328,7 @@ struct Engine {
     bool any = false;
     for (uint32_t i = 0; i < nq; ++i) {
       qh[i].plan = 0;
-      qh[i].sel_seg = -1;
+      qh[i].nsegs = 0;
     }
     rr = (rr + 1) % nq;  // the query served first rotates between steps
     for (uint32_t t = 0; t < nq; ++t) {
@@ -1375,49 +1386,71 @@ struct Engine {
         any = true;
         continue;
       }
-      Level &Lv = Q.stack.back();
-      const u64 free_h = Q.hdr_cap - (u64)(Lv.begin + Lv.count);
-      const u64 free_w = Q.word_cap - Lv.wend;
-      const u64 lim_c = std::min<u64>(cap_c, free_h), lim_w = std::min<u64>(cap_w, free_w);
-      // one record of this level must always fit
-      const u64 rec_c = std::max<u64>(1, Lv.maxcc), rec_w = rec_c * 2 * std::max(1u, Lv.maxw);
+      const Level &Top = Q.stack.back();
+      const u64 free_h = Q.hdr_cap - (u64)(Top.begin + Top.count);
+      const u64 free_w = Q.word_cap - Top.wend;
+      u64 lim_c = std::min<u64>(cap_c, free_h), lim_w = std::min<u64>(cap_w, free_w);
+      // one record of the top level must always fit
+      const u64 rec_c = std::max<u64>(1, Top.maxcc), rec_w = rec_c * 2 * std::max(1u, Top.maxw);
       if (free_h < rec_c || free_w < rec_w) {
         fail(i, NURI_EBUDGET, "frontier budget exhausted");
         continue;
       }
       if (lim_c < rec_c || lim_w < rec_w) continue;  // next step
-      const uint32_t room = batch_cap - batch_ub;
-      if (room == 0) continue;
-      SelSeg &sg = sseg()[nseg];
-      sg = SelSeg{};
-      sg.qid = i;
-      sg.begin = Lv.begin;
-      sg.count = Lv.count;
-      sg.max_records = std::min<u64>(B, room);
-      sg.max_children = lim_c;
-      sg.max_words = lim_w;
-      sg.take_all =
-          Lv.count <= sg.max_records && Lv.cost_children <= lim_c && Lv.cost_words <= lim_w;
-      sg.top = Lv.max_bound;
-      sg.maxcc = Lv.maxcc;
-      sg.wpc = 2ull * Lv.maxw;
-      const long long floor_b = Q.theta == LLONG_MIN ? 0 : Q.theta;
-      const long long span = Lv.max_bound - floor_b;
-      uint32_t shift = 0;
-      while (span > 0 && (span >> shift) >= kBins - 1) ++shift;
-      sg.shift = shift;
-      sg.temp_off = (uint32_t)temp_need;
-      if (!sg.take_all) temp_need += Lv.count;
-      max_seg_count = std::max(max_seg_count, Lv.count);
-      Q.sel_seg = (int)nseg++;
+      // levels from the top down: whole levels while they fit, then a
+      // selection of the best records of the next one.  Taking from more
+      // than the deepest level keeps the device busy when the deepest
+      // levels are narrow; the new level still goes on top of the stack.
+      Q.seg0 = nseg;
+      Q.nsegs = 0;
+      u64 rec_left = B;
+      for (int li = (int)Q.stack.size() - 1; li >= 0; --li) {
+        if (nseg >= L->nseg_cap || Q.nsegs >= kSegPerQuery || rec_left == 0) break;
+        const Level &Lv = Q.stack[li];
+        if (Lv.count == 0) continue;
+        const uint32_t room = batch_cap - batch_ub;
+        if (room == 0) break;
+        const u64 lrc = std::max<u64>(1, Lv.maxcc), lrw = lrc * 2 * std::max(1u, Lv.maxw);
+        if (lim_c < lrc || lim_w < lrw) break;
+        SelSeg &sg = sseg()[nseg];
+        sg = SelSeg{};
+        sg.qid = i;
+        sg.begin = Lv.begin;
+        sg.count = Lv.count;
+        sg.max_records = std::min<u64>(rec_left, room);
+        sg.max_children = lim_c;
+        sg.max_words = lim_w;
+        sg.take_all =
+            Lv.count <= sg.max_records && Lv.cost_children <= lim_c && Lv.cost_words <= lim_w;
+        sg.top = Lv.max_bound;
+        sg.maxcc = Lv.maxcc;
+        sg.wpc = 2ull * Lv.maxw;
+        const long long floor_b = Q.theta == LLONG_MIN ? 0 : Q.theta;
+        const long long span = Lv.max_bound - floor_b;
+        uint32_t shift = 0;
+        while (span > 0 && (span >> shift) >= kBins - 1) ++shift;
+        sg.shift = shift;
+        sg.temp_off = (uint32_t)temp_need;
+        if (!sg.take_all) temp_need += Lv.count;
+        max_seg_count = std::max(max_seg_count, Lv.count);
+        seg_level[nseg] = (uint32_t)li;
+        ++nseg;
+        ++Q.nsegs;
+        const u64 nb = sg.take_all ? Lv.count : sg.max_records;
+        batch_ub += (uint32_t)nb;
+        rec_left -= std::min(rec_left, nb);
+        const u64 uc = sg.take_all ? Lv.cost_children : lim_c;
+        const u64 uw = sg.take_all ? Lv.cost_words : lim_w;
+        lim_c -= std::min(lim_c, uc);
+        lim_w -= std::min(lim_w, uw);
+        left_c -= std::min(left_c, uc);
+        left_w -= std::min(left_w, uw);
+        if (!sg.take_all) break;  // a selection uses up this query's limits
+      }
+      if (Q.nsegs == 0) continue;
       Q.plan = 2;
-      Q.new_begin = Lv.begin + Lv.count;
-      Q.new_wbegin = Lv.wend;
-      batch_ub += (uint32_t)(sg.take_all ? Lv.count : sg.max_records);
-      const u64 uc = sg.take_all ? Lv.cost_children : lim_c;
-      const u64 uw = sg.take_all ? Lv.cost_words : lim_w;
-      left_c -= std::min(left_c, uc);
-      left_w -= std::min(left_w, uw);
+      Q.new_begin = Top.begin + Top.count;
+      Q.new_wbegin = Top.wend;
       any = true;
     }
     if (!any)
@@ -1440,8 +1473,8 @@ struct Engine {
       sq()[i].out_max_bound = LLONG_MIN;
     }
     memcpy(h_step.p + L->cfg, cfg.data(), nq * sizeof(QCfg));
-    memset(h_step.p + L->taken, 0, 8ull * nq);  // taken, tempc
-    NURI_HIP(hipMemcpyAsync(d_step.p, h_step.p, L->total, hipMemcpyHostToDevice, s));
+    memset(h_step.p + L->taken, 0, 4ull * L->nseg_cap);  // taken (tempc is in the zeroed part)
+    NURI_HIP(hipMemcpyAsync(d_step.p, h_step.p, L->upload(nseg), hipMemcpyHostToDevice, s));
     StepHdr *dh = dev<StepHdr>(0);
     QStep *dqs = dev<QStep>(L->qs);
     QCfg *dcfg = dev<QCfg>(L->cfg);
@@ -1472,7 +1505,7 @@ struct Engine {
       NURI_HIP(hipGetLastError());
       if (any_sel) {
         hipLaunchKernelGGL(k_copy_back, dim3(bx, nseg), dim3(256), 0, s, dseg, dcfg, temp.p,
-                           dev<unsigned int>(L->tempc), dqs);
+                           dev<unsigned int>(L->tempc));
         NURI_HIP(hipGetLastError());
       }
     }
@@ -1508,8 +1541,11 @@ struct Engine {
         continue;
       }
       if (Q.plan == 2) {
-        Level &Lv = Q.stack.back();
-        Lv.count = sseg()[Q.sel_seg].take_all ? 0 : c.n_kept;
+        const unsigned int *kept = (const unsigned int *)(h_step.p + L->tempc);
+        for (uint32_t t = 0; t < Q.nsegs; ++t) {
+          const uint32_t sx = Q.seg0 + t;
+          Q.stack[seg_level[sx]].count = sseg()[sx].take_all ? 0 : kept[sx];
+        }
       }
       if (c.n_out) {
         Level N;
@@ -1604,10 +1640,13 @@ struct Engine {
     if (trace) {
       uint32_t live = 0;
       for (auto &Q : qh) live += Q.active && !Q.done;
+      size_t depth = 0;
+      for (auto &Q : qh) depth = std::max(depth, Q.stack.size());
       fprintf(stderr, "[nuri] step live=%u segs=%u roots=%u batch<=%u maxlevel=%u temp=%llu "
-              "leaves=%u plan_us=%llu step_us=%llu\n", live, nseg, nrseg, batch_ub, mseg,
-              (unsigned long long)temp_need, sh()->leaf_count,
-              (unsigned long long)(t1 - t0) / 1000, (unsigned long long)(now_ns() - t1) / 1000);
+              "leaves=%u plan_us=%llu step_us=%llu theta0=%lld depth=%zu\n", live, nseg, nrseg,
+              batch_ub, mseg, (unsigned long long)temp_need, sh()->leaf_count,
+              (unsigned long long)(t1 - t0) / 1000, (unsigned long long)(now_ns() - t1) / 1000,
+              qh[0].theta, depth);
     }
     return true;
   }
