@@ -30,6 +30,40 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+HERE = os.path.dirname(os.path.abspath(__file__))
+# HBM traffic of k_expand per launch comes from rocprofv3 PMC counters
+# (FETCH_SIZE, WRITE_SIZE) summarised in this file, valid only while the
+# kernel source hashes to the value recorded there
+TRAFFIC_SUMMARY = os.path.join(HERE, "profiles", "k_expand_chung_lu_top100.md")
+KERNEL_SOURCES = [os.path.join(HERE, "paper_1807_08888_amd", "csrc", f)
+                  for f in ("clique.hip", "device_common.h")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_expand launch from the committed counter summary, or
+    None when there is none or the kernel source changed since."""
+    try:
+        fields = {}
+        with open(TRAFFIC_SUMMARY) as fh:
+            for line in fh:
+                if ":" in line and line.strip().startswith(("traffic_bytes_per_launch",
+                                                            "kernel_source_sha256")):
+                    k, v = line.strip().split(":", 1)
+                    fields[k.strip()] = v.strip().strip("`")
+        if fields.get("kernel_source_sha256") != kernel_source_hash():
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 WORKLOAD = "chung_lu_n1M_m20M_beta2.1_cap20k_planted200x20-40_top100_maximal_cliques_size"
 
 
@@ -297,7 +331,7 @@ def main() -> int:
                    "children_per_query": children // args.steps,
                    "preprocess_ms": info["preprocess_ns"] / 1e6},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "k_expand", "avg_launch_us": ens / launches / 1e3 if launches else 0,
                      "launches_per_query": launches // args.steps},
     }

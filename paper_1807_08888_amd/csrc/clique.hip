@@ -293,11 +293,7 @@ __global__ void __launch_bounds__(256)
   u64 P = (lane < (int)W) ? lt_mask(lane, d) : 0ull, V = 0;
   int last = -1;
   while (__ballot(P != 0)) {
-    int hb = P ? lane * 64 + 63 - (int)__clzll(P) : -1;
-    for (int o2 = 32; o2 > 0; o2 >>= 1) {
-      const int y = __shfl_xor(hb, o2, 64);
-      hb = y > hb ? y : hb;
-    }
+    const int hb = wave_highest_bit(P);
     last = hb;
     score += sg.kind ? (long long)wl[hb] : 1ll;
     if (lane == (hb >> 6)) {
@@ -550,11 +546,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
           long long cmax = 0;
           int top = -1;
           while (__ballot(Q != 0)) {
-            int hb = (Q != 0) ? lane * 64 + 63 - (int)__clzll(Q) : -1;
-            for (int o2 = 32; o2 > 0; o2 >>= 1) {
-              int y = __shfl_xor(hb, o2, 64);
-              hb = y > hb ? y : hb;
-            }
+            const int hb = wave_highest_bit(Q);
             if (top < 0) top = hb;
             const long long wv2 = weighted ? (long long)wl[hb] : 1ll;
             cmax = wv2 > cmax ? wv2 : cmax;
@@ -1106,7 +1098,7 @@ struct Engine {
   PoolBuf<LRec> leaves;
   PoolBuf<u64> leaf_words;
   PoolBuf<Cand> cands;
-  PoolBuf<uint32_t> mpos;  // merge: position of each candidate among the top-k
+  MergeBufs mbuf;  // top-k merge: candidate positions and survivor lists
   PinBuf<SeedSeg> h_seed;
   PoolBuf<SeedSeg> d_seed;
   PoolBuf<uint32_t> cand_ids;
@@ -1239,7 +1231,7 @@ struct Engine {
     leaves.alloc(g.pool, leaf_cap);
     leaf_words.alloc(g.pool, leaf_word_cap);
     cands.alloc(g.pool, kCandChunk);
-    mpos.alloc(g.pool, kCandChunk);
+    mbuf.alloc(g.pool, nq, s);
     h_seed.alloc(nq);
     d_seed.alloc(g.pool, nq);
     cand_ids.alloc(g.pool, (u64)kCandChunk * lmax);
@@ -1585,7 +1577,7 @@ struct Engine {
       hipLaunchKernelGGL(k_leaf_check, dim3(cnt), dim3(64), 0, s, gv, leaves.p, f, leaf_words.p,
                          d_res.p, cands.p, &dh->cand_count, cand_ids.p, lmax, d_ctr.p);
       NURI_HIP(hipGetLastError());
-      launch_merge(cands.p, dh, cand_ids.p, lmax, d_res.p, d_k.p, mpos.p, nq, kmax, cnt, s);
+      launch_merge(cands.p, dh, cand_ids.p, lmax, d_res.p, d_k.p, mbuf, nq, kmax, cnt, s);
     }
     NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
     NURI_HIP(hipStreamSynchronize(s));

@@ -41,6 +41,19 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// highest set position over a wave's words (lane l holds word l); the
+// caller guarantees that some lane's word is non-zero.  The lane comes from
+// a ballot and the word from a scalar read of that lane, so the result is
+// wave-uniform without a shuffle reduction.
+__device__ inline int wave_highest_bit(u64 x) {
+  const u64 m = __ballot(x != 0);
+  const int l = 63 - (int)__clzll(m);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  const u64 w = ((u64)hi << 32) | lo;
+  return l * 64 + 63 - (int)__clzll(w);
+}
+
 // bits of word w whose position w*64+b is greater than pos (pos may be -1)
 __device__ inline u64 gt_mask(int w, int pos) {
   int lo = w * 64;
@@ -152,19 +165,32 @@ __device__ inline bool wave_before(long long sa, const uint32_t *a, uint32_t la,
 //     current top-k items precede it.  A candidate preceded by k or more
 //     can never enter (everything that will precede a member of the new
 //     top-k precedes it too), so it is dropped; so is a candidate equal to
-//     a top-k item (a result offered twice).
-//   k_merge_rank: one wave per item of (top-k, surviving candidates) of a
-//     query counts the survivors that precede it; with its position in
-//     the top-k that is its rank in the union.  Items ranked below k are
-//     written to the other top-k buffer at their rank, so the order of
-//     candidates in the chunk never matters.
-//   k_merge_finish: switches to the merged buffer and sets the threshold.
-constexpr uint32_t kDropped = 0xFFFFFFFFu;
+//     a top-k item (a result offered twice).  Survivors are appended to
+//     their query's list (the order of a list does not matter).
+//   k_merge_rank: one wave per item of (top-k, survivors) of a query
+//     counts the survivors that precede it; with its position in the
+//     top-k that is its rank in the union.  Items ranked below k are
+//     written to the other top-k buffer at their rank.
+//   k_merge_finish: switches to the merged buffer, sets the threshold and
+//     empties the survivor list.
 constexpr int kMergeWaves = 4;
+
+// device buffers of the merge: position of each candidate of a chunk, and
+// per query a survivor list (count zero between merges)
+struct MergeBufs {
+  PoolBuf<uint32_t> pos, list, count;
+  void alloc(MemPool &pool, uint32_t nq, hipStream_t s) {
+    pos.alloc(pool, kCandChunk);
+    list.alloc(pool, (u64)nq * kCandChunk);
+    count.alloc(pool, nq);
+    NURI_HIP(hipMemsetAsync(count.p, 0, nq * sizeof(uint32_t), s));
+  }
+};
 
 __global__ void __launch_bounds__(64 * kMergeWaves)
     k_merge_pos(const Cand *cands, const StepHdr *hdr, const uint32_t *cand_ids, uint32_t lmax,
-                const QRes *res, const uint32_t *ks, uint32_t *pos) {
+                const QRes *res, const uint32_t *ks, uint32_t *pos, uint32_t *slist,
+                uint32_t *scount) {
   const int lane = threadIdx.x & 63;
   const uint32_t c = blockIdx.x * kMergeWaves + (threadIdx.x >> 6);
   if (c >= hdr->cand_count) return;
@@ -184,110 +210,84 @@ __global__ void __launch_bounds__(64 * kMergeWaves)
   // an item equal to the candidate (it was offered before) drops it
   const bool dup = lo < n && !wave_before(cd.score, ids, cd.len, R.tk_score[cur][lo],
                                           R.tk_ids[cur] + (u64)lo * lmax, R.tk_len[cur][lo], lane);
-  if (lane == 0) pos[c] = lo < ks[cd.qid] && !dup ? lo : kDropped;
+  if (lane == 0) {
+    pos[c] = lo;
+    if (lo < ks[cd.qid] && !dup)
+      slist[(u64)cd.qid * kCandChunk + atomicAdd(&scount[cd.qid], 1u)] = c;
+  }
 }
 
 __global__ void __launch_bounds__(64 * kMergeWaves)
-    k_merge_rank(const Cand *cands, const StepHdr *hdr, const uint32_t *cand_ids, uint32_t lmax,
-                 const QRes *res, const uint32_t *ks, const uint32_t *pos) {
-  __shared__ uint32_t s_idx[kCandChunk];
-  __shared__ uint32_t s_cnt[64 * kMergeWaves];
-  __shared__ uint32_t s_ns;
-  constexpr uint32_t per = kCandChunk / (64 * kMergeWaves);
+    k_merge_rank(const Cand *cands, const uint32_t *cand_ids, uint32_t lmax, const QRes *res,
+                 const uint32_t *ks, const uint32_t *pos, const uint32_t *slist,
+                 const uint32_t *scount) {
   const uint32_t q = blockIdx.y;
-  const uint32_t nc_all = hdr->cand_count;
-  const uint32_t b0 = threadIdx.x * per;
-  uint32_t mine = 0;
-  for (uint32_t i = b0; i < b0 + per && i < nc_all; ++i)
-    mine += cands[i].qid == q && pos[i] != kDropped;
-  s_cnt[threadIdx.x] = mine;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int t = 0; t < 64 * kMergeWaves; ++t) {
-      const uint32_t c = s_cnt[t];
-      s_cnt[t] = run;
-      run += c;
-    }
-    s_ns = run;
-  }
-  __syncthreads();
-  uint32_t o = s_cnt[threadIdx.x];
-  for (uint32_t i = b0; i < b0 + per && i < nc_all; ++i)
-    if (cands[i].qid == q && pos[i] != kDropped) s_idx[o++] = i;
-  __syncthreads();
-  const uint32_t ns = s_ns;
+  const uint32_t ns = scount[q];
   if (ns == 0) return;
+  const uint32_t *sl = slist + (u64)q * kCandChunk;
   const int lane = threadIdx.x & 63;
   const QRes &R = res[q];
   const uint32_t k = ks[q];
   const uint32_t cur = R.cur, alt = cur ^ 1u;
   const uint32_t nt = R.tk_n < k ? R.tk_n : k;
-  const uint32_t it = blockIdx.x * kMergeWaves + (threadIdx.x >> 6);
-  if (it >= nt + ns) return;
-  long long si;
-  const uint32_t *ai;
-  uint32_t li, rank;
-  if (it < nt) {
-    si = R.tk_score[cur][it];
-    ai = R.tk_ids[cur] + (u64)it * lmax;
-    li = R.tk_len[cur][it];
-    rank = it;
-  } else {
-    const uint32_t c = s_idx[it - nt];
-    si = cands[c].score;
-    ai = cand_ids + (u64)c * lmax;
-    li = cands[c].len;
-    rank = pos[c];
-  }
-  // survivors that precede this item: scores decide 64 at a time, ties
-  // are settled one by one by the whole wave
-  for (uint32_t base = 0; base < ns && rank < k; base += 64) {
-    const uint32_t j = base + lane;
-    long long sj = 0;
-    uint32_t cj = 0;
-    if (j < ns) {
-      cj = s_idx[j];
-      sj = cands[cj].score;
+  for (uint32_t it = blockIdx.x * kMergeWaves + (threadIdx.x >> 6); it < nt + ns;
+       it += gridDim.x * kMergeWaves) {
+    long long si;
+    const uint32_t *ai;
+    uint32_t li, rank;
+    if (it < nt) {
+      si = R.tk_score[cur][it];
+      ai = R.tk_ids[cur] + (u64)it * lmax;
+      li = R.tk_len[cur][it];
+      rank = it;
+    } else {
+      const uint32_t c = sl[it - nt];
+      si = cands[c].score;
+      ai = cand_ids + (u64)c * lmax;
+      li = cands[c].len;
+      rank = pos[c];
     }
-    const bool self = it >= nt && j == it - nt;
-    rank += __popcll(__ballot(j < ns && !self && sj > si));
-    u64 tie = __ballot(j < ns && !self && sj == si);
-    while (tie) {
-      const int t = __ffsll((long long)tie) - 1;
-      tie &= tie - 1;
-      const uint32_t ct = __shfl(cj, t, 64);
-      rank += wave_before(si, cand_ids + (u64)ct * lmax, cands[ct].len, si, ai, li, lane);
+    // survivors that precede this item: scores decide 64 at a time, ties
+    // are settled one by one by the whole wave
+    for (uint32_t base = 0; base < ns && rank < k; base += 64) {
+      const uint32_t j = base + lane;
+      long long sj = 0;
+      uint32_t cj = 0;
+      if (j < ns) {
+        cj = sl[j];
+        sj = cands[cj].score;
+      }
+      const bool self = it >= nt && j == it - nt;
+      rank += __popcll(__ballot(j < ns && !self && sj > si));
+      u64 tie = __ballot(j < ns && !self && sj == si);
+      while (tie) {
+        const int t = __ffsll((long long)tie) - 1;
+        tie &= tie - 1;
+        const uint32_t ct = __shfl(cj, t, 64);
+        rank += wave_before(si, cand_ids + (u64)ct * lmax, cands[ct].len, si, ai, li, lane);
+      }
     }
-  }
-  if (rank < k) {
-    if (lane == 0) {
-      R.tk_score[alt][rank] = si;
-      R.tk_len[alt][rank] = li;
+    if (rank < k) {
+      if (lane == 0) {
+        R.tk_score[alt][rank] = si;
+        R.tk_len[alt][rank] = li;
+      }
+      uint32_t *dst = R.tk_ids[alt] + (u64)rank * lmax;
+      for (uint32_t t = lane; t < li; t += 64) dst[t] = ai[t];
     }
-    uint32_t *dst = R.tk_ids[alt] + (u64)rank * lmax;
-    for (uint32_t t = lane; t < li; t += 64) dst[t] = ai[t];
   }
 }
 
-// one block per query: switch to the merged buffer and set the threshold
-__global__ void __launch_bounds__(256)
-    k_merge_finish(const Cand *cands, const StepHdr *hdr, QRes *res, const uint32_t *ks,
-                   const uint32_t *pos) {
-  __shared__ uint32_t s_n;
-  const uint32_t q = blockIdx.x;
-  if (threadIdx.x == 0) s_n = 0;
-  __syncthreads();
-  const uint32_t nc_all = hdr->cand_count;
-  uint32_t mine = 0;
-  for (uint32_t i = threadIdx.x; i < nc_all; i += blockDim.x)
-    mine += cands[i].qid == q && pos[i] != kDropped;
-  if (mine) atomicAdd(&s_n, mine);
-  __syncthreads();
-  if (threadIdx.x != 0 || s_n == 0) return;
+// one thread per query: switch to the merged buffer and set the threshold
+__global__ void k_merge_finish(QRes *res, const uint32_t *ks, uint32_t *scount, uint32_t nq) {
+  const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nq) return;
+  const uint32_t ns = scount[q];
+  if (ns == 0) return;
+  scount[q] = 0;
   QRes &R = res[q];
   const uint32_t k = ks[q];
-  const uint32_t N = (R.tk_n < k ? R.tk_n : k) + s_n;
+  const uint32_t N = (R.tk_n < k ? R.tk_n : k) + ns;
   const uint32_t nn = N < k ? N : k;
   const uint32_t alt = R.cur ^ 1u;
   R.tk_n = nn;
@@ -298,17 +298,22 @@ __global__ void __launch_bounds__(256)
 // launch the three merge kernels for a chunk of at most `ub` candidates
 // (the exact count is read on the device from hdr->cand_count)
 inline void launch_merge(const Cand *cands, const StepHdr *hdr, const uint32_t *ids,
-                         uint32_t lmax, QRes *res, const uint32_t *ks, uint32_t *pos, uint32_t nq,
+                         uint32_t lmax, QRes *res, const uint32_t *ks, MergeBufs &mb, uint32_t nq,
                          uint32_t kmax, uint32_t ub, hipStream_t s) {
   if (!ub) return;
   hipLaunchKernelGGL(k_merge_pos, dim3((ub + kMergeWaves - 1) / kMergeWaves),
-                     dim3(64 * kMergeWaves), 0, s, cands, hdr, ids, lmax, res, ks, pos);
+                     dim3(64 * kMergeWaves), 0, s, cands, hdr, ids, lmax, res, ks, mb.pos.p,
+                     mb.list.p, mb.count.p);
   NURI_HIP(hipGetLastError());
+  // blocks per query: enough waves for the items, at most 32 blocks (each
+  // wave then walks several items)
   const uint32_t items = kmax + std::min<uint32_t>(ub, kCandChunk);
-  hipLaunchKernelGGL(k_merge_rank, dim3((items + kMergeWaves - 1) / kMergeWaves, nq),
-                     dim3(64 * kMergeWaves), 0, s, cands, hdr, ids, lmax, res, ks, pos);
+  const uint32_t bx = std::min<uint32_t>((items + kMergeWaves - 1) / kMergeWaves, 32);
+  hipLaunchKernelGGL(k_merge_rank, dim3(bx, nq), dim3(64 * kMergeWaves), 0, s, cands, ids, lmax,
+                     res, ks, mb.pos.p, mb.list.p, mb.count.p);
   NURI_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_merge_finish, dim3(nq), dim3(256), 0, s, cands, hdr, res, ks, pos);
+  hipLaunchKernelGGL(k_merge_finish, dim3((nq + 255) / 256), dim3(256), 0, s, res, ks, mb.count.p,
+                     nq);
   NURI_HIP(hipGetLastError());
 }
 

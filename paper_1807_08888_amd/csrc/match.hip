@@ -701,7 +701,7 @@ struct MatchEngine {
   PoolBuf<QRes> d_res;
   PoolBuf<uint32_t> d_k, d_rootq;
   PoolBuf<Cand> cands, cands2;
-  PoolBuf<uint32_t> mpos;  // merge: position of each candidate among the top-k
+  MergeBufs mbuf;  // top-k merge: candidate positions and survivor lists
   PoolBuf<uint32_t> cand_ids, cand_ids2;
   PoolBuf<CPre> d_pre;
   PinBuf<CPre> h_pre;
@@ -801,7 +801,7 @@ struct MatchEngine {
     cands.alloc(g.pool, cand_cap);
     cand_ids.alloc(g.pool, (u64)cand_cap * QM);
     cands2.alloc(g.pool, cand_cap);
-    mpos.alloc(g.pool, kCandChunk);
+    mbuf.alloc(g.pool, nq, s);
     cand_ids2.alloc(g.pool, (u64)cand_cap * QM);
     d_pre.alloc(g.pool, nq);
     h_pre.alloc(nq);
@@ -966,11 +966,8 @@ struct MatchEngine {
         fail(i, NURI_EBUDGET, "frontier budget exhausted");
         continue;
       }
-      // one step's children take at most an eighth of the query's arena, so
-      // that deeper levels keep room for batches of useful size
       const u64 lim = to_leaves ? std::min<u64>(left_cand, std::max(cand_share, rec))
-                                : std::min<u64>(free_h, std::min<u64>(step_children,
-                                                                      std::max<u64>(Q.hdr_cap / 8, rec)));
+                                : std::min<u64>(free_h, step_children);
       if (lim < rec) continue;
       const uint32_t room = batch_cap - batch_ub;
       if (room == 0) continue;
@@ -1130,7 +1127,7 @@ struct MatchEngine {
       h_ccount.p[0] = std::min<uint32_t>(kCandChunk, ncand - f);
       // the merge kernels read the chunk size through StepHdr::cand_count
       NURI_HIP(hipMemcpyAsync(&dh->cand_count, h_ccount.p, 4, hipMemcpyHostToDevice, s));
-      launch_merge(mc + f, dh, mids + (u64)f * QM, (uint32_t)QM, d_res.p, d_k.p, mpos.p, nq, kmax,
+      launch_merge(mc + f, dh, mids + (u64)f * QM, (uint32_t)QM, d_res.p, d_k.p, mbuf, nq, kmax,
                    h_ccount.p[0], s);
       NURI_HIP(hipStreamSynchronize(s));  // the pinned chunk size is rewritten next round
     }
