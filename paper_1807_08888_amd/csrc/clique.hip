@@ -872,71 +872,75 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
 //      the lower neighbour list N-(c*) of the member with the shortest one
 //      and tested against every other member by binary search in N+(u).
 constexpr int kLeafCap = kMaxLocal + 1;
+// wavefronts per leaf: (a) and the output are done by wave 0, the
+// candidates of (b) are shared out between all of them
+constexpr int kLeafWaves = 8;
 
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64 * kLeafWaves)
     k_leaf_check(GView g, const LRec *leaves, uint32_t first, const u64 *leaf_words,
                  const QRes *res, Cand *cands, unsigned int *cand_count, uint32_t *cand_ids,
                  uint32_t lmax, QCtr *ctr) {
   __shared__ uint32_t s_rank[kLeafCap];
   __shared__ uint32_t s_id[kLeafCap];
   __shared__ uint32_t s_sorted[kLeafCap];
-  const int lane = threadIdx.x;
+  __shared__ int s_ext;  // an extender was found: the leaf is not maximal
+  __shared__ uint32_t s_nc, s_nu, s_cs;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const LRec L = leaves[first + blockIdx.x];
   const uint32_t q = L.qid;
   if (L.score < res[q].theta) return;
   const uint32_t r = L.root;
   const uint32_t d = g.dplus[r];
   const uint32_t W = words_of(d);
-  u64 v = 0;
-  if (d && lane < (int)W) v = leaf_words[L.woff + lane];
-  // member positions -> ranks
-  uint32_t c = __popcll(v);
-  uint32_t off = wave_excl_scan(c, lane);
-  const uint32_t nm = __shfl(off + c, 63, 64);
-  const uint32_t *np = g.oplus + g.ooff[r];
-  {
-    u64 t = v;
-    uint32_t o = off;
-    while (t) {
-      int b = __ffsll((long long)t) - 1;
-      s_rank[o] = np[lane * 64 + b];
-      s_sorted[o++] = lane * 64 + b;  // local positions, for (a)
-      t &= t - 1;
+  if (wv == 0) {
+    u64 v = 0;
+    if (d && lane < (int)W) v = leaf_words[L.woff + lane];
+    // member positions -> ranks
+    const uint32_t c = __popcll(v);
+    const uint32_t off = wave_excl_scan(c, lane);
+    const uint32_t nm = __shfl(off + c, 63, 64);
+    const uint32_t *np = g.oplus + g.ooff[r];
+    {
+      u64 t = v;
+      uint32_t o = off;
+      while (t) {
+        int b = __ffsll((long long)t) - 1;
+        s_rank[o] = np[lane * 64 + b];
+        s_sorted[o++] = lane * 64 + b;  // local positions, for (a)
+        t &= t - 1;
+      }
     }
-  }
-  if (lane == 0) s_rank[nm] = r;
-  wave_sync();
-  const uint32_t nc = nm + 1;  // clique size
-  // (a) local extension: groups of G lanes AND the members' rows, 64/G
-  // members per round (independent loads), then the groups are combined
-  if (d) {
-    const u64 *rows = g.bm + g.bm_off[r];
-    uint32_t G = 1;
-    while (G < W) G <<= 1;
-    const uint32_t per = 64 / G;
-    const int wi = lane & (G - 1);
-    u64 acc = ~0ull;
+    if (lane == 0) s_rank[nm] = r;
+    wave_sync();
+    const uint32_t nc = nm + 1;  // clique size
+    int ext = 0;
+    // (a) local extension: groups of G lanes AND the members' rows, 64/G
+    // members per round (independent loads), then the groups are combined
+    if (d) {
+      const u64 *rows = g.bm + g.bm_off[r];
+      uint32_t G = 1;
+      while (G < W) G <<= 1;
+      const uint32_t per = 64 / G;
+      const int wi = lane & (G - 1);
+      u64 acc = ~0ull;
 #pragma unroll 8
-    for (uint32_t b0 = 0; b0 < nm; b0 += per) {
-      const uint32_t ci = b0 + lane / G;
-      if (ci < nm && wi < (int)W) acc &= rows[(u64)s_sorted[ci] * W + wi];
+      for (uint32_t b0 = 0; b0 < nm; b0 += per) {
+        const uint32_t ci = b0 + lane / G;
+        if (ci < nm && wi < (int)W) acc &= rows[(u64)s_sorted[ci] * W + wi];
+      }
+      for (uint32_t o2 = G; o2 < 64; o2 <<= 1) acc &= __shfl_xor(acc, o2, 64);
+      const u64 x = (lane < (int)W) ? (~v & lt_mask(lane, d) & acc) : 0ull;
+      ext = __ballot(x != 0) != 0;
     }
-    for (uint32_t o2 = G; o2 < 64; o2 <<= 1) acc &= __shfl_xor(acc, o2, 64);
-    const u64 x = (lane < (int)W) ? (~v & lt_mask(lane, d) & acc) : 0ull;
-    if (__ballot(x != 0)) return;
-  }
-  wave_sync();  // s_sorted is rewritten below
-  // (b) extension by a vertex ranked below r
-  {
-    // an extender u has |N+(u)| >= nc; for nc >= kHeavy only the heavy
-    // part of the lower neighbour lists can hold one
+    // (b) set-up: an extender u ranked below r has |N+(u)| >= nc; for
+    // nc >= kHeavy only the heavy part of the lower neighbour lists can
+    // hold one.  Scan the list of the member with the fewest entries.
     const bool heavy = nc >= kHeavy;
-    // member with the fewest (heavy) lower neighbours
     uint32_t bestc = 0xFFFFFFFFu, besti = 0;
     for (uint32_t t = lane; t < nc; t += 64) {
       const uint32_t m = s_rank[t];
-      const uint32_t s = heavy ? (uint32_t)(g.hrow[m + 1] - g.hrow[m]) : g.split[m];
-      if (s < bestc) { bestc = s; besti = t; }
+      const uint32_t sz = heavy ? (uint32_t)(g.hrow[m + 1] - g.hrow[m]) : g.split[m];
+      if (sz < bestc) { bestc = sz; besti = t; }
     }
     for (int o2 = 32; o2 > 0; o2 >>= 1) {
       uint32_t oc = __shfl_xor(bestc, o2, 64), oi = __shfl_xor(besti, o2, 64);
@@ -950,15 +954,30 @@ __global__ void __launch_bounds__(64)
       uint32_t mid = (lo + hi) >> 1;
       if (lo_list[mid] < r) lo = mid + 1; else hi = mid;
     }
-    const uint32_t nu = lo;
-    // u is ranked below every member and adjacent to all nc of them, so
-    // |N+(u)| >= nc: that one load rejects almost every u.  Each remaining
-    // u is then tested by the whole wave, 64 members at a time.
-    for (uint32_t b0 = 0; b0 < nu; b0 += 64) {
+    if (lane == 0) {
+      s_ext = ext;
+      s_nc = nc;
+      s_nu = lo;
+      s_cs = cs;
+    }
+  }
+  __syncthreads();
+  if (s_ext) return;
+  const uint32_t nc = s_nc, nu = s_nu;
+  {
+    const uint32_t cs = s_cs;
+    const bool heavy = nc >= kHeavy;
+    const uint32_t *lo_list = heavy ? g.hcol + g.hrow[cs] : g.rcol + g.rrow[cs];
+    // (b): |N+(u)| >= nc rejects almost every u with one load.  Each
+    // remaining u is tested by a whole wave, 64 members at a time; the
+    // waves take turns over the list and stop once one finds an extender.
+    for (uint32_t b0 = wv * 64; b0 < nu; b0 += 64 * kLeafWaves) {
+      if (*(volatile int *)&s_ext) break;
       const uint32_t t = b0 + lane;
       const uint32_t u = t < nu ? lo_list[t] : 0u;
       u64 cand = __ballot(t < nu && g.dplus[u] >= nc);
-      while (cand) {
+      bool found = false;
+      while (cand && !found) {
         const int src = __ffsll((long long)cand) - 1;
         cand &= cand - 1;
         const uint32_t uu = __shfl(u, src, 64);
@@ -979,10 +998,16 @@ __global__ void __launch_bounds__(64)
           }
           all = __ballot(miss) == 0;
         }
-        if (all) return;
+        found = all;
+      }
+      if (found) {
+        if (lane == 0) s_ext = 1;
+        break;
       }
     }
   }
+  __syncthreads();
+  if (s_ext || wv != 0) return;
   // maximal: emit (score, ascending original ids)
   for (uint32_t t = lane; t < nc; t += 64) s_id[t] = g.orig[s_rank[t]];
   wave_sync();
@@ -1574,7 +1599,7 @@ struct Engine {
     for (uint32_t f = 0; f < nleaf; f += kCandChunk) {
       const uint32_t cnt = std::min<uint32_t>(kCandChunk, nleaf - f);
       NURI_HIP(hipMemsetAsync(&dh->cand_count, 0, sizeof(unsigned int), s));
-      hipLaunchKernelGGL(k_leaf_check, dim3(cnt), dim3(64), 0, s, gv, leaves.p, f, leaf_words.p,
+      hipLaunchKernelGGL(k_leaf_check, dim3(cnt), dim3(64 * kLeafWaves), 0, s, gv, leaves.p, f, leaf_words.p,
                          d_res.p, cands.p, &dh->cand_count, cand_ids.p, lmax, d_ctr.p);
       NURI_HIP(hipGetLastError());
       launch_merge(cands.p, dh, cand_ids.p, lmax, d_res.p, d_k.p, mbuf, nq, kmax, cnt, s);
