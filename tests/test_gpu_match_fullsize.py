@@ -1,0 +1,75 @@
+"""Labelled matching at full size: R-MAT scale 22 (4.2M vertices, 64M edges),
+16 Zipf labels, edge weights 1..1000, 128 random patterns of 3..7 vertices,
+top-50 each, run as one batch exactly as the benchmark runs it.
+
+Every returned match is checked against the graph (labels, edges, score,
+injectivity, order), and the patterns the oracle finishes in seconds at this
+size are compared with it element by element.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+# patterns of the benchmark's recipe whose oracle run takes a few seconds on
+# this graph (the others take tens of seconds each)
+ORACLE_SAMPLE = (1, 2, 3, 7)
+
+
+@pytest.fixture(scope="module")
+def full(request):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_1807_08888_amd import nuri as N
+    N.lib()
+    print("[case] R-MAT scale 22 graph", flush=True)
+    g = synth.rmat(22)
+    synth.add_vertex_weights(g)
+    synth.add_edge_weights(g)
+    synth.add_zipf_labels(g)
+    G = N.Graph.from_synth(g)
+    yield N, g, G
+    G.close()
+
+
+def _check_matches(g, labels, edges, items):
+    rp = g.row_ptr.astype(np.int64)
+    col, ew, lab = g.col, g.edge_weight, g.vertex_label
+    prev = None
+    for score, ids in items:
+        assert len(ids) == len(labels)
+        assert len(set(ids)) == len(ids), "not injective"
+        for i, v in enumerate(ids):
+            assert lab[v] == labels[i], "label mismatch"
+        total = 0
+        for a, b in edges:
+            u, v = ids[a], ids[b]
+            row = col[rp[u]:rp[u + 1]]
+            j = int(np.searchsorted(row, v))
+            assert j < len(row) and row[j] == v, "pattern edge not in the graph"
+            total += int(ew[rp[u] + j])
+        assert total == score, "score is not the sum of matched edge weights"
+        key = (-score, tuple(ids))
+        if prev is not None:
+            assert prev < key, "results not strictly ordered"
+        prev = key
+
+
+def test_full_size_batch_vs_properties_and_oracle(full):
+    N, g, G = full
+    pats = [synth.random_pattern(i) for i in range(128)]
+    qs = [{"kind": "match", "k": 50, "labels": p.labels, "edges": p.edges} for p in pats]
+    print("[case] 128 patterns, top-50, one batch", flush=True)
+    outs = N.topk_batch(G, qs)
+    for i, p in enumerate(pats):
+        _check_matches(g, p.labels, p.edges, outs[i].items)
+        assert len(outs[i].items) <= 50
+    for i in ORACLE_SAMPLE:
+        p = pats[i]
+        print(f"[case] oracle pattern {i}", flush=True)
+        want, _ = oracle.topk_match(g, p.labels, p.edges, 50)
+        assert outs[i].items == want, i
