@@ -266,8 +266,9 @@ __global__ void k_copy_back(const SelSeg *segs, const QCfg *cfg, const CRec *tem
 // ------------------------------------------------------------------
 // Before the search, one wavefront per root (the first `count` roots in
 // bound order) builds a clique greedily: starting from the root's later
-// neighbours it adds the highest remaining position and keeps the
-// positions adjacent to it, until none is left.  The result goes through
+// neighbours it adds the highest remaining position (with vertex weights,
+// also the heaviest remaining candidate, keeping the heavier clique) and
+// keeps the positions adjacent to it, until none is left.  The result goes through
 // the same maximality check and merge as any leaf, so the k-th score
 // starts at the k-th best of these cliques instead of at minus infinity;
 // any k maximal cliques give a valid lower bound of the final k-th score.
@@ -289,18 +290,54 @@ __global__ void __launch_bounds__(256)
   const uint32_t W = words_of(d);
   const int32_t *wl = g.wloc + g.ooff[r];
   const u64 *rows = g.bm + g.bm_off[r];
-  long long score = sg.kind ? (long long)g.vw[r] : 1ll;
-  u64 P = (lane < (int)W) ? lt_mask(lane, d) : 0ull, V = 0;
-  int last = -1;
-  while (__ballot(P != 0)) {
-    const int hb = wave_highest_bit(P);
-    last = hb;
-    score += sg.kind ? (long long)wl[hb] : 1ll;
-    if (lane == (hb >> 6)) {
-      V |= 1ull << (hb & 63);
-      P &= ~(1ull << (hb & 63));
+  // one greedy clique: add the highest remaining position (by_weight:
+  // the heaviest remaining candidate, ties to the highest position)
+  auto dive = [&](bool by_weight, u64 &V, int &last) -> long long {
+    long long score = sg.kind ? (long long)g.vw[r] : 1ll;
+    u64 P = (lane < (int)W) ? lt_mask(lane, d) : 0ull;
+    V = 0;
+    last = -1;
+    while (__ballot(P != 0)) {
+      int hb;
+      if (by_weight) {
+        // (weight, position) maximum: this lane's word, then the wave
+        long long best = -1;
+        for (u64 t = P; t; t &= t - 1) {
+          const int pos = lane * 64 + __ffsll((long long)t) - 1;
+          const long long key = ((long long)wl[pos] << 13) | pos;
+          best = key > best ? key : best;
+        }
+        for (int o2 = 32; o2 > 0; o2 >>= 1) {
+          const long long y = __shfl_xor(best, o2, 64);
+          best = y > best ? y : best;
+        }
+        hb = (int)(best & 8191);
+      } else {
+        hb = wave_highest_bit(P);
+      }
+      last = hb;
+      score += sg.kind ? (long long)wl[hb] : 1ll;
+      if (lane == (hb >> 6)) {
+        V |= 1ull << (hb & 63);
+        P &= ~(1ull << (hb & 63));
+      }
+      if (lane < (int)W) P &= rows[(u64)hb * W + lane];
     }
-    if (lane < (int)W) P &= rows[(u64)hb * W + lane];
+    return score;
+  };
+  u64 V = 0;
+  int last = -1;
+  long long score = dive(false, V, last);
+  if (sg.kind) {
+    // vertex weights: keep the heavier of the two greedy cliques
+    u64 V2 = 0;
+    int last2 = -1;
+    const long long score2 = dive(true, V2, last2);
+    if (score2 > score) {
+      score = score2;
+      V = V2;
+      last = last2;
+    }
   }
   unsigned int slot = 0;
   u64 w0 = 0;
