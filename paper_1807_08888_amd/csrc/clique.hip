@@ -523,6 +523,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     // falls below it), so the only clique of this subtree that can enter
     // the top-k is V + P, and it exists iff P is a clique
     bool whole = false;
+    long long wP = nchild;  // weight of the candidate set
     if (theta != LLONG_MIN) {
       if (!weighted) {
         // each candidate weighs 1: child idx reaches score + nchild - idx
@@ -530,34 +531,40 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         n_eff = R < 0 ? 0u : (uint32_t)(R + 1 < (long long)nchild ? R + 1 : nchild);
         whole = R == 0 && nchild > 0;
       } else {
-        long long lsum = 0;
+        // one word at a time, one lane per bit: coalesced weight loads and
+        // wave reductions instead of a serial walk over each word's bits
+        long long total = 0;
         int32_t lmin = INT32_MAX;
-        for (u64 t = pw; t; t &= t - 1) {
-          const int32_t wt = wl[lane * 64 + __ffsll((long long)t) - 1];
-          lsum += wt;
-          lmin = wt < lmin ? wt : lmin;
+        for (uint32_t w = 0; w < W; ++w) {
+          const u64 word = readlane64(pw, (int)w);
+          const bool set = (word >> lane) & 1ull;
+          const int32_t x = set ? wl[w * 64 + lane] : 0;
+          total += (long long)wave_sum((u64)x);
+          lmin = min((int32_t)wave_min_u32(set ? (uint32_t)x : (uint32_t)INT32_MAX), lmin);
         }
-        for (int o2 = 32; o2 > 0; o2 >>= 1) {
-          const int32_t y = __shfl_xor(lmin, o2, 64);
-          lmin = y < lmin ? y : lmin;
-        }
-        const long long lexcl = wave_excl_scan64(lsum, lane);
-        const long long total = __shfl(lexcl + lsum, 63, 64);
+        wP = total;
         const long long R = total + p.score - theta;
         whole = R >= 0 && R < (long long)lmin && nchild > 0;
+        // first candidate index whose preceding candidates weigh more than R
         uint32_t cut = 0xFFFFFFFFu;
         if (R < 0) {
           cut = 0;
-        } else if (c && lexcl + lsum > R) {
-          long long run = lexcl;
-          uint32_t idx = off;
-          for (u64 t = pw; t; t &= t - 1) {
-            if (run > R) {
-              cut = idx;
+        } else if (total > R) {
+          long long run = 0;
+          uint32_t base = 0;
+          for (uint32_t w = 0; w < W; ++w) {
+            const u64 word = readlane64(pw, (int)w);
+            const bool set = (word >> lane) & 1ull;
+            const long long x = set ? (long long)wl[w * 64 + lane] : 0ll;
+            const long long excl = wave_excl_scan64(x, lane);
+            const u64 hit = __ballot(set && run + excl > R);
+            if (hit) {
+              const int f = __ffsll((long long)hit) - 1;
+              cut = base + (uint32_t)__popcll(word & ((1ull << f) - 1ull));
               break;
             }
-            run += wl[lane * 64 + __ffsll((long long)t) - 1];
-            ++idx;
+            run += (long long)__shfl(excl + x, 63, 64);
+            base += (uint32_t)__popcll(word);
           }
         }
         cut = wave_min_u32(cut);
@@ -575,8 +582,12 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       // above the top of the last class built are dominated.
       const long long need = theta - p.score;
       if (!whole && cf.colour_min && n_eff >= cf.colour_min && need > 0) {
+        // Once the classes built so far plus the weight of everything not
+        // yet coloured fall below need, no child survives: stop there
+        // (most records that reach this point are such dead ends).
         u64 U = pw, Q = 0;
-        long long run = 0;
+        long long run = 0, wU = wP;
+        bool dead = false;
         int cut_pos = -1;  // children at positions <= cut_pos survive
         while (__ballot(U != 0)) {
           Q = U;
@@ -587,13 +598,19 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
             if (top < 0) top = hb;
             const long long wv2 = weighted ? (long long)wl[hb] : 1ll;
             cmax = wv2 > cmax ? wv2 : cmax;
+            wU -= wv2;
             if (lane == (hb >> 6)) {
               const u64 bit = 1ull << (hb & 63);
               U &= ~bit;
               Q &= ~bit;
             }
             if (lane < (int)W) Q &= ~rows[(u64)hb * W + lane];
+            if (run + cmax + wU < need) {
+              dead = true;
+              break;
+            }
           }
+          if (dead) break;
           run += cmax;
           if (run >= need) {
             cut_pos = top;

@@ -41,6 +41,13 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// lane l's 64-bit value, read by every lane (l wave-uniform)
+__device__ inline u64 readlane64(u64 x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  return ((u64)hi << 32) | lo;
+}
+
 // highest set position over a wave's words (lane l holds word l); the
 // caller guarantees that some lane's word is non-zero.  The lane comes from
 // a ballot and the word from a scalar read of that lane, so the result is
