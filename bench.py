@@ -287,8 +287,13 @@ def main() -> int:
         del src, dst
         _log("copy calibration: 1 GiB read + 1 GiB written")
 
+    # step sizes from the autotuner (untimed), then the timed queries use them
+    tuned = nuri.autotune(G, [{"kind": "clique", "k": args.k, "weight_fn": nuri.SCORE_SIZE}],
+                          rounds=1, stream=stream)
+    _log(f"autotuned step sizes: {tuned}")
+
     def one():
-        return nuri.topk_cliques(G, args.k, nuri.SCORE_SIZE, profile=True, stream=stream)
+        return nuri.topk_cliques(G, args.k, nuri.SCORE_SIZE, profile=True, stream=stream, **tuned)
 
     ref = None
     for i in range(args.warmup):
@@ -329,6 +334,7 @@ def main() -> int:
         "config": {"workload": WORKLOAD, "n": g.n, "m": g.m, "k": args.k,
                    "max_clique": results[-1].items[0][0] if results[-1].items else 0,
                    "children_per_query": children // args.steps,
+                   "batch_B": tuned["batch_B"], "root_batch": tuned["root_batch"],
                    "preprocess_ms": info["preprocess_ns"] / 1e6},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),

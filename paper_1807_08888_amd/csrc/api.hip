@@ -180,6 +180,50 @@ int nuri_topk_batch(nuri_graph *g, const nuri_query *qs, uint32_t nq, const nuri
   });
 }
 
+int nuri_autotune(nuri_graph *g, const nuri_query *qs, uint32_t nq, const nuri_opts *o,
+                  uint32_t rounds, nuri_opts *best) {
+  if (!g || !best || !qs || nq == 0 || rounds == 0) {
+    set_error("autotune needs a graph, queries, rounds >= 1 and an output");
+    return NURI_EINVAL;
+  }
+  nuri_opts base{};
+  if (o) base = *o;
+  std::vector<nuri_result *> outs(nq, nullptr);
+  auto run = [&](const nuri_opts &x, uint64_t &ns) -> int {
+    const uint64_t t0 = now_ns();
+    const int rc = nuri_topk_batch(g, qs, nq, &x, outs.data());
+    ns = now_ns() - t0;
+    if (rc == NURI_OK)
+      for (auto *r : outs) nuri_free_result(r);
+    return rc;
+  };
+  uint64_t ns = 0;
+  int rc = run(base, ns);  // warm-up (workspace pool, caches)
+  if (rc != NURI_OK) return rc;
+  static const uint32_t kB[] = {4096, 16384, 65536};
+  static const uint32_t kRoot[] = {2048, 8192};
+  uint64_t best_ns = UINT64_MAX;
+  nuri_opts pick = base;
+  for (uint32_t b : kB)
+    for (uint32_t rb : kRoot) {
+      nuri_opts x = base;
+      x.batch_B = b;
+      x.root_batch = rb;
+      uint64_t t = UINT64_MAX;
+      for (uint32_t i = 0; i < rounds; ++i) {
+        rc = run(x, ns);
+        if (rc != NURI_OK) return rc;
+        t = std::min(t, ns);
+      }
+      if (t < best_ns) {
+        best_ns = t;
+        pick = x;
+      }
+    }
+  *best = pick;
+  return NURI_OK;
+}
+
 int nuri_result_view_get(const nuri_result *r, nuri_result_view *v) {
   if (!r || !v) {
     set_error("NULL argument");

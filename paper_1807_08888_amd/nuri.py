@@ -84,6 +84,9 @@ SIGNATURES = {
                                        ctypes.POINTER(_Opts), ctypes.POINTER(_VP)]),
     "nuri_topk_batch": (ctypes.c_int, [_VP, ctypes.POINTER(_Query), ctypes.c_uint32,
                                        ctypes.POINTER(_Opts), ctypes.POINTER(_VP)]),
+    "nuri_autotune": (ctypes.c_int, [_VP, ctypes.POINTER(_Query), ctypes.c_uint32,
+                                     ctypes.POINTER(_Opts), ctypes.c_uint32,
+                                     ctypes.POINTER(_Opts)]),
     "nuri_result_view_get": (ctypes.c_int, [_VP, ctypes.POINTER(_View)]),
     "nuri_result_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_Stats)]),
     "nuri_free_result": (None, [_VP]),
@@ -257,6 +260,16 @@ def topk_batch(graph: Graph, queries, **opts) -> List[Result]:
     o = _opts(**opts)
     _check(lib().nuri_topk_batch(graph._h, qs, len(queries), ctypes.byref(o), outs))
     return [Result(outs[i]) for i in range(len(queries))]
+
+
+def autotune(graph: Graph, queries, rounds: int = 1, **opts) -> Dict[str, int]:
+    """Fastest (batch_B, root_batch) for these queries (nuri_autotune)."""
+    qs, keep = _queries(queries)
+    o = _opts(**opts)
+    best = _Opts()
+    _check(lib().nuri_autotune(graph._h, qs, len(queries), ctypes.byref(o), rounds,
+                               ctypes.byref(best)))
+    return {"batch_B": int(best.batch_B), "root_batch": int(best.root_batch)}
 
 
 class Server:

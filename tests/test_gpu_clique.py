@@ -285,3 +285,20 @@ def test_result_independent_of_bound(nuri, bound):
                 want, _ = oracle.topk_cliques(g, k, weighted=bool(wf))
                 got = _gpu(nuri, g, k, wf, bound=bound)
                 assert got.items == want, (i, wf, k)
+
+
+def test_autotune_picks_a_candidate_and_keeps_results(nuri):
+    """nuri_autotune returns one of its candidate step sizes; results under it are exact."""
+    g = synth.er_planted(master=7)
+    _case("autotune on the planted-clique workload")
+    G = nuri.Graph.from_synth(g)
+    try:
+        qs = [{"kind": "clique", "k": 10, "weight_fn": 0}]
+        best = nuri.autotune(G, qs, rounds=1)
+        assert best["batch_B"] in (4096, 16384, 65536)
+        assert best["root_batch"] in (2048, 8192)
+        got = nuri.topk_cliques(G, 10, batch_B=best["batch_B"], root_batch=best["root_batch"])
+    finally:
+        G.close()
+    want, _ = oracle.topk_cliques(g, 10)
+    assert got.items == want
