@@ -519,17 +519,19 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     // idx, idx+1, ...); past the first idx where that is below theta every
     // child is dominated
     uint32_t n_eff = nchild;
-    // whole: every candidate is needed to reach theta (dropping any one
-    // falls below it), so the only clique of this subtree that can enter
-    // the top-k is V + P, and it exists iff P is a clique
+    // whole: at most one candidate may be left out and theta still be
+    // reached (with vertex weights: none), so the subtree's only possible
+    // results are V + P and V + P minus one vertex, found directly
     bool whole = false;
+    int wslack = 0;         // whole: how many candidates may be left out (0 or 1)
     long long wP = nchild;  // weight of the candidate set
     if (theta != LLONG_MIN) {
       if (!weighted) {
         // each candidate weighs 1: child idx reaches score + nchild - idx
         const long long R = p.score + (long long)nchild - theta;
         n_eff = R < 0 ? 0u : (uint32_t)(R + 1 < (long long)nchild ? R + 1 : nchild);
-        whole = R == 0 && nchild > 0;
+        whole = (R == 0 || R == 1) && nchild > 0;
+        wslack = (int)R;
       } else {
         // one word at a time, one lane per bit: coalesced weight loads and
         // wave reductions instead of a serial walk over each word's bits
@@ -638,35 +640,68 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     if (nchild) st_expanded += 1;
     st_children += nchild;
     if (whole) {
-      // test every candidate's row against the rest of P at once (the
-      // loads are independent) instead of one chained step per member
-      // also: a vertex of X adjacent to all of P extends V + P, which is
-      // then not maximal
-      bool clique = true;
+      // Every candidate's row at once (the loads are independent): for each
+      // candidate the number of other candidates it is not adjacent to.
+      // With slack 0 the only possible result is V + P (P a clique); with
+      // slack 1 it is V + P or V + P - {x}, and P - {x} is a clique iff
+      // every non-adjacent pair of P contains x.  Also a vertex of X
+      // adjacent to all of P extends V + P, which is then not maximal.
       u64 xacc = (wi < (int)W) ? s_xw[wi] : 0ull;
-      for (uint32_t b0 = 0; b0 < nchild && clique; b0 += 8 * per) {
-        int bad = 0;
+      uint32_t zc = 0, msum = 0, zlo = 0xFFFFFFFFu, zhi = 0, mbest = 0, mpos = 0;
+      for (uint32_t b0 = 0; b0 < nchild; b0 += 8 * per) {
         for (uint32_t u = 0; u < 8; ++u) {
           const uint32_t ci = b0 + u * per + lane / G;
-          if (ci < nchild && wi < (int)W) {
-            const uint32_t j = s_list[ci];
+          const bool valid = ci < nchild;
+          uint32_t miss = 0, j = 0;
+          if (valid && wi < (int)W) {
+            j = s_list[ci];
             const u64 own = (wi == (int)(j >> 6)) ? (1ull << (j & 63)) : 0ull;
             const u64 row = rows[(u64)j * W + wi];
-            bad |= (s_pw[wi] & ~own & ~row) != 0ull;
+            miss = __popcll(s_pw[wi] & ~own & ~row);
             xacc &= row;
           }
+          for (uint32_t o2 = 1; o2 < G; o2 <<= 1) miss += __shfl_xor(miss, o2, 64);
+          if (valid && wi == 0 && miss) {
+            ++zc;
+            msum += miss;
+            zlo = j < zlo ? j : zlo;
+            zhi = j > zhi ? j : zhi;
+            if (miss > mbest) {
+              mbest = miss;
+              mpos = j;
+            }
+          }
         }
-        clique = __ballot(bad) == 0;
+        if (wslack == 0 && __ballot(zc != 0)) break;  // P is not a clique
       }
       st_bytes += 8ull * W * nchild;
+      zc = (uint32_t)wave_sum((u64)zc);
+      msum = (uint32_t)wave_sum((u64)msum);
+      zlo = wave_min_u32(zlo);
+      zhi = (uint32_t)wave_max_u64((u64)zhi);
+      {
+        const u64 key = wave_max_u64(((u64)mbest << 32) | mpos);
+        mbest = (uint32_t)(key >> 32);
+        mpos = (uint32_t)key;
+      }
       // AND the X accumulators of the lane groups holding the same word
       for (uint32_t o2 = G; o2 < 64; o2 <<= 1) xacc &= __shfl_xor(xacc, o2, 64);
-      if (clique && __ballot(wi < (int)W && xacc != 0ull)) clique = false;
-      st_pruned_new += nchild - (clique ? 1 : 0);
+      int drop0 = -2, drop1 = -2;  // dropped position per leaf; -1 none, -2 no leaf
+      if (zc == 0) {
+        if (!__ballot(wi < (int)W && xacc != 0ull)) drop0 = -1;
+      } else if (wslack >= 1 && msum / 2 == mbest) {
+        if (mbest == 1) {
+          drop0 = (int)zlo;
+          drop1 = (int)zhi;
+        } else {
+          drop0 = (int)mpos;
+        }
+      }
+      const uint32_t nl = (drop0 != -2) + (drop1 != -2);
+      st_pruned_new += nchild - (nl ? 1 : 0);
+      st_leaves += nl;
       n_eff = 0;  // no child is built one by one
-      if (clique) {
-        // offer V + P (every candidate added) as a leaf
-        st_leaves += 1;
+      if (nl) {
         long long tot = 0;
         if (weighted) {
           for (u64 t = pw; t; t &= t - 1) tot += wl[lane * 64 + __ffsll((long long)t) - 1];
@@ -677,23 +712,27 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         unsigned int l0 = 0;
         u64 w0 = 0;
         if (lane == 0) {
-          l0 = atomicAdd(&hdr->leaf_count, 1u);
-          w0 = atomicAdd(&hdr->leaf_word_count, (u64)W);
+          l0 = atomicAdd(&hdr->leaf_count, nl);
+          w0 = atomicAdd(&hdr->leaf_word_count, (u64)nl * W);
         }
         l0 = __shfl(l0, 0, 64);
         w0 = __shfl(w0, 0, 64);
-        if (l0 < leaf_cap && w0 + W <= leaf_word_cap) {
-          if (lane < (int)W) leaf_words[w0 + lane] = s_vw[lane] | s_pw[lane];
-          if (lane == 0) {
-            LRec l;
-            l.score = p.score + tot;
-            l.woff = w0;
-            l.root = r;
-            l.last = (int16_t)last;
-            l.qid = (uint16_t)q;
-            leaves[l0] = l;
+        if (l0 + nl <= leaf_cap && w0 + (u64)nl * W <= leaf_word_cap) {
+          for (uint32_t t = 0; t < nl; ++t) {
+            const int dp = t == 0 ? drop0 : drop1;
+            const u64 dbit = (dp >= 0 && lane == (dp >> 6)) ? (1ull << (dp & 63)) : 0ull;
+            if (lane < (int)W) leaf_words[w0 + (u64)t * W + lane] = (s_vw[lane] | s_pw[lane]) & ~dbit;
+            if (lane == 0) {
+              LRec l;
+              l.score = p.score + tot - (dp >= 0 ? (weighted ? (long long)wl[dp] : 1ll) : 0ll);
+              l.woff = w0 + (u64)t * W;
+              l.root = r;
+              l.last = (int16_t)last;
+              l.qid = (uint16_t)q;
+              leaves[l0 + t] = l;
+            }
           }
-          st_bytes += 24 + 8ull * W;
+          st_bytes += (24 + 8ull * W) * nl;
         } else if (lane == 0) {
           atomicAdd(&qs[q].overflow, 1u);
         }
