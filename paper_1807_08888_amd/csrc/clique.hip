@@ -743,6 +743,11 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     // kept children: the first is held back (in s_cv/s_cx) in case it
     // stays the only one; `spilled` once it has been written out
     bool held = false, spilled = false;
+    // the first vertex of X is the witness of most children (X' = X and the
+    // earlier candidates, both adjacent to the child): its row is loaded
+    // once per record, beside the children's rows instead of after them
+    const int xf = n_eff ? wave_lowest_bit((lane < (int)W) ? s_xw[lane] : 0ull) : -1;
+    const u64 rowxf = (xf >= 0 && wi < (int)W) ? rows[(u64)xf * W + wi] : 0ull;
     for (uint32_t base = 0; base < n_eff; base += per) {
       const uint32_t ci = base + lane / G;
       const bool valid = ci < n_eff;
@@ -763,7 +768,8 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       }
       bool covered = false;
       if (x0 != 0x7FFFFFFF) {
-        int miss = (wi < (int)W) ? ((a & ~rows[(u64)x0 * W + wi]) != 0ull) : 0;
+        const u64 rx = x0 == xf ? rowxf : ((wi < (int)W) ? rows[(u64)x0 * W + wi] : 0ull);
+        int miss = (wi < (int)W) ? ((a & ~rx) != 0ull) : 0;
         for (uint32_t o2 = 1; o2 < G; o2 <<= 1) miss |= __shfl_xor(miss, o2, 64);
         covered = miss == 0;
       }

@@ -61,6 +61,14 @@ __device__ inline int wave_highest_bit(u64 x) {
   return l * 64 + 63 - (int)__clzll(w);
 }
 
+// lowest set position over a wave's words (lane l holds word l), or -1
+__device__ inline int wave_lowest_bit(u64 x) {
+  const u64 m = __ballot(x != 0);
+  if (!m) return -1;
+  const int l = __ffsll((long long)m) - 1;
+  return l * 64 + __ffsll((long long)readlane64(x, l)) - 1;
+}
+
 // bits of word w whose position w*64+b is greater than pos (pos may be -1)
 __device__ inline u64 gt_mask(int w, int pos) {
   int lo = w * 64;
