@@ -375,8 +375,13 @@ __global__ void __launch_bounds__(256)
 // processed 64/G at a time, G = the power of two >= W lanes per child,
 // each lane ANDing one word of the parent's bitmaps with one word of the
 // child vertex's local adjacency row.  Group reductions give |P'| (or
-// w(P')); survivors are compacted with a ballot and one atomic per wave
-// and written with coalesced stores.
+// w(P')); survivors of a round are compacted with a ballot, placed with
+// one atomic per wave and written with coalesced stores.
+//
+// Whole records: when at most one candidate may be left out and the k-th
+// score still be reached, the subtree's only possible results are V + P
+// and V + P minus one vertex; one pass over all candidates' rows finds
+// them (see below).
 //
 // Chains: when a record keeps exactly one child, the wave expands that
 // child at once instead of writing it to the frontier and waiting for a

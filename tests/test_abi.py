@@ -74,3 +74,19 @@ def test_errors_are_reported_not_hidden(nuri):
     except nuri.NuriError as e:  # no GPU here: the device error is reported
         assert e.name in ("EDEVICE", "ENOMEM")
         assert nuri.lib().nuri_last_error()
+
+
+def test_bench_traffic_is_null_unless_the_kernel_source_matches(tmp_path, monkeypatch):
+    """bench.py reports counter traffic only for the kernel the counters were taken on."""
+    import bench
+    h = bench.kernel_source_hash()
+    good = tmp_path / "summary.md"
+    good.write_text(f"x\ntraffic_bytes_per_launch: 1234\nkernel_source_sha256: {h}\n")
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(good))
+    assert bench.measured_traffic() == 1234.0
+    stale = tmp_path / "stale.md"
+    stale.write_text("traffic_bytes_per_launch: 1234\nkernel_source_sha256: " + "0" * 64 + "\n")
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(stale))
+    assert bench.measured_traffic() is None
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(tmp_path / "missing.md"))
+    assert bench.measured_traffic() is None
