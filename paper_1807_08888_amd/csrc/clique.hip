@@ -525,10 +525,11 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     // child is dominated
     uint32_t n_eff = nchild;
     // whole: at most one candidate may be left out and theta still be
-    // reached (with vertex weights: none), so the subtree's only possible
-    // results are V + P and V + P minus one vertex, found directly
+    // reached, so the subtree's only possible results are V + P and V + P
+    // minus one vertex, found directly
     bool whole = false;
     int wslack = 0;         // whole: how many candidates may be left out (0 or 1)
+    long long wR = 0;       // whole, vertex weights: a left-out candidate weighs at most wR
     long long wP = nchild;  // weight of the candidate set
     if (theta != LLONG_MIN) {
       if (!weighted) {
@@ -541,17 +542,31 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         // one word at a time, one lane per bit: coalesced weight loads and
         // wave reductions instead of a serial walk over each word's bits
         long long total = 0;
-        int32_t lmin = INT32_MAX;
+        uint32_t m1 = INT32_MAX, m2 = INT32_MAX;  // the two smallest weights
         for (uint32_t w = 0; w < W; ++w) {
           const u64 word = readlane64(pw, (int)w);
           const bool set = (word >> lane) & 1ull;
           const int32_t x = set ? wl[w * 64 + lane] : 0;
           total += (long long)wave_sum((u64)x);
-          lmin = min((int32_t)wave_min_u32(set ? (uint32_t)x : (uint32_t)INT32_MAX), lmin);
+          const uint32_t xv = set ? (uint32_t)x : (uint32_t)INT32_MAX;
+          const uint32_t a = wave_min_u32(xv);
+          const uint32_t b = __popcll(__ballot(set && xv == a)) >= 2
+                                 ? a
+                                 : wave_min_u32(xv == a ? (uint32_t)INT32_MAX : xv);
+          if (a < m1) {
+            m2 = min(m1, b);
+            m1 = a;
+          } else {
+            m2 = min(m2, a);
+          }
         }
         wP = total;
         const long long R = total + p.score - theta;
-        whole = R >= 0 && R < (long long)lmin && nchild > 0;
+        // at most one candidate can be left out when any two weigh more
+        // than the slack R
+        whole = R >= 0 && R < (long long)m1 + (long long)m2 && nchild > 0;
+        wslack = R >= (long long)m1 ? 1 : 0;
+        wR = R;
         // first candidate index whose preceding candidates weigh more than R
         uint32_t cut = 0xFFFFFFFFu;
         if (R < 0) {
@@ -701,19 +716,21 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         } else {
           drop0 = (int)mpos;
         }
+        // with vertex weights a left-out candidate must weigh at most the slack
+        if (weighted) {
+          if (drop1 >= 0 && (long long)wl[drop1] > wR) drop1 = -2;
+          if (drop0 >= 0 && (long long)wl[drop0] > wR) {
+            drop0 = drop1;
+            drop1 = -2;
+          }
+        }
       }
       const uint32_t nl = (drop0 != -2) + (drop1 != -2);
       st_pruned_new += nchild - (nl ? 1 : 0);
       st_leaves += nl;
       n_eff = 0;  // no child is built one by one
       if (nl) {
-        long long tot = 0;
-        if (weighted) {
-          for (u64 t = pw; t; t &= t - 1) tot += wl[lane * 64 + __ffsll((long long)t) - 1];
-          tot = (long long)wave_sum((u64)tot);
-        } else {
-          tot = nchild;
-        }
+        const long long tot = weighted ? wP : (long long)nchild;
         unsigned int l0 = 0;
         u64 w0 = 0;
         if (lane == 0) {
