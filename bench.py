@@ -246,6 +246,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--k", type=int, default=100)
+    ap.add_argument("--batch-B", type=int, default=0,
+                    help="records per step (with --root-batch: skip the autotuner)")
+    ap.add_argument("--root-batch", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -287,10 +290,15 @@ def main() -> int:
         del src, dst
         _log("copy calibration: 1 GiB read + 1 GiB written")
 
-    # step sizes from the autotuner (untimed), then the timed queries use them
-    tuned = nuri.autotune(G, [{"kind": "clique", "k": args.k, "weight_fn": nuri.SCORE_SIZE}],
-                          rounds=1, stream=stream)
-    _log(f"autotuned step sizes: {tuned}")
+    # step sizes from the autotuner (untimed) unless given; the timed
+    # queries use them
+    if args.batch_B and args.root_batch:
+        tuned = {"batch_B": args.batch_B, "root_batch": args.root_batch}
+        _log(f"step sizes given: {tuned}")
+    else:
+        tuned = nuri.autotune(G, [{"kind": "clique", "k": args.k, "weight_fn": nuri.SCORE_SIZE}],
+                              rounds=1, stream=stream)
+        _log(f"autotuned step sizes: {tuned}")
 
     def one():
         return nuri.topk_cliques(G, args.k, nuri.SCORE_SIZE, profile=True, stream=stream, **tuned)
