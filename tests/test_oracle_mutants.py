@@ -1,0 +1,129 @@
+"""Planted mistakes in the oracle, on the CPU (no GPU).
+
+Each mutant below is oracle.c with one plausible mistake (a dropped term, a
+wrong comparison, a missing check).  It is compiled on its own and run
+against a battery of the oracle's pins (brute force over small graphs for
+both clique scores, both bounds, and labelled matching); the battery must
+fail for every mutant and pass for the real oracle, so that a mistake of
+that kind in the oracle would not go unnoticed.
+"""
+import contextlib
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import synth
+from tests import bruteforce
+
+ORACLE_C = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+# (name, text in oracle.c, replacement)
+MUTANTS = [
+    ("pruning at or below the k-th score (not strict)",
+     "return R->n == R->k && bound < R->e[R->k - 1].score;",
+     "return R->n == R->k && bound <= R->e[R->k - 1].score;"),
+    ("bound without the current score",
+     "  int64_t b = s->score;\n  if (bound_kind == 0) {",
+     "  int64_t b = 0;\n  if (bound_kind == 0) {"),
+    ("child candidates not filtered by adjacency",
+     "if (is_adjacent(g, p, s->P[j])) c->P[c->np++] = s->P[j];",
+     "c->P[c->np++] = s->P[j];"),
+    ("earlier candidates left out of X",
+     "else u = s->P[b++];",
+     "else { b++; continue; }"),
+    ("relevant() ignores X (non-maximal results)",
+     "if (s->np == 0 && s->nx == 0) {",
+     "if (s->np == 0) {"),
+    ("ties broken by descending ids",
+     "return lex_cmp(a, na, b, nb);",
+     "return -lex_cmp(a, na, b, nb);"),
+    ("colour class bound takes the lightest vertex",
+     "if (w > cmax[color[i]]) cmax[color[i]] = w;",
+     "if (cmax[color[i]] == 0 || w < cmax[color[i]]) cmax[color[i]] = w;"),
+    ("matching ignores labels",
+     "if (lab[c] != P.label[a]) continue;",
+     "(void)0;"),
+    ("matching not injective",
+     "if (r->mu[b] == c) ok = 0;",
+     "if (0) ok = 0;"),
+    ("matching drops an edge weight from the score",
+     "if (w == 0) ok = 0; else add += w;",
+     "if (w == 0) ok = 0;"),
+    ("matching bound too low for matched edges",
+     "if (matched[a] && matched[c]) ub = edge_weight(g, r->mu[a], r->mu[c]);",
+     "if (matched[a] && matched[c]) ub = 1;"),
+    ("matching bound too low for unmatched edges",
+     "else ub = T->pairmax[P->label[a] * T->nl + P->label[c]];",
+     "else ub = 1;"),
+]
+
+MATCH_PATTERNS = [
+    ([0, 0], [(0, 1)]),
+    ([0, 1, 0], [(0, 1), (1, 2)]),
+    ([0, 0, 0], [(0, 1), (1, 2), (0, 2)]),
+    ([0, 1, 1, 0], [(0, 1), (1, 2), (2, 3), (0, 2)]),
+    ([0, 0, 1, 0, 1], [(0, 1), (1, 2), (2, 3), (3, 4), (0, 2)]),
+]
+
+
+def _battery():
+    """Names of the pins that fail for the oracle currently loaded."""
+    failed = []
+    for n, p, seed in ((8, 0.6, 1), (11, 0.3, 2), (11, 0.6, 3), (13, 0.5, 4), (9, 0.9, 5),
+                       (12, 0.45, 6)):
+        g = synth.gnp(n, p, seed)
+        for w_hi in (3, 100):  # many ties / few ties
+            synth.add_vertex_weights(g, 1, w_hi, master=seed)
+            for k in (1, 2, 5, 1000):
+                want_s = bruteforce.topk_cliques(g, k)
+                want_w = bruteforce.topk_cliques(g, k, weights=g.vertex_weight)
+                for bound in (0, 1):
+                    for xprune in (False, True):
+                        got_s, _ = oracle.topk_cliques(g, k, bound=bound, xprune=xprune)
+                        if got_s != want_s:
+                            failed.append(f"cliques size n={n} k={k} bound={bound}")
+                        for priority in (0, 1):
+                            got_w, _ = oracle.topk_cliques(g, k, weighted=True, bound=bound,
+                                                           priority=priority, xprune=xprune)
+                            if got_w != want_w:
+                                failed.append(f"cliques weight n={n} k={k} bound={bound}")
+    for pi, (labels, edges) in enumerate(MATCH_PATTERNS):
+        for seed, w_hi in ((1, 4), (2, 4), (3, 50)):
+            g = synth.gnp(9, 0.55, 100 * seed + pi)
+            synth.add_zipf_labels(g, n_labels=2, s=0.5, master=100 * seed + pi)
+            synth.add_edge_weights(g, 1, w_hi, master=100 * seed + pi)
+            for k in (1, 2, 5, 10000):
+                want, _ = bruteforce.topk_matches(g, labels, edges, k)
+                got, _ = oracle.topk_match(g, labels, edges, k, n_labels=2)
+                if got != want:
+                    failed.append(f"match pattern {pi} seed {seed} k={k}")
+    return failed
+
+
+@contextlib.contextmanager
+def _oracle_from(so_path):
+    saved = oracle._SO, oracle._lib
+    oracle._SO, oracle._lib = so_path, None
+    try:
+        yield
+    finally:
+        oracle._SO, oracle._lib = saved
+
+
+def test_real_oracle_passes_the_battery():
+    assert _battery() == []
+
+
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_fails_the_battery(tmp_path, name, old, new):
+    src = open(ORACLE_C).read()
+    assert old in src, f"mutation site not found: {old!r}"
+    mut = tmp_path / "oracle_mutant.c"
+    mut.write_text(src.replace(old, new))  # the same mistake wherever the code occurs
+    so = tmp_path / "liboracle_mutant.so"
+    subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", str(so), str(mut)])
+    with _oracle_from(str(so)):
+        failed = _battery()
+    assert failed, f"no pin catches the mutant: {name}"
