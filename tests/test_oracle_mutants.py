@@ -19,7 +19,8 @@ from tests import bruteforce
 
 ORACLE_C = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
-# (name, text in oracle.c, replacement)
+# (name, text in oracle.c, replacement); text and replacement may be tuples
+# of the same length for a mistake made in several places
 MUTANTS = [
     ("pruning at or below the k-th score (not strict)",
      "return R->n == R->k && bound < R->e[R->k - 1].score;",
@@ -48,6 +49,10 @@ MUTANTS = [
     ("matching not injective",
      "if (r->mu[b] == c) ok = 0;",
      "if (0) ok = 0;"),
+    ("matching reports every embedding of an image",
+     ("if (r->depth == q && match_is_canonical(&P, r->mu)) {",
+      "if (!match_may_be_canonical(&P, ch)) { free(ch); continue; }"),
+     ("if (r->depth == q) {", "(void)0;")),
     ("matching drops an edge weight from the score",
      "if (w == 0) ok = 0; else add += w;",
      "if (w == 0) ok = 0;"),
@@ -119,9 +124,12 @@ def test_real_oracle_passes_the_battery():
 @pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_mutant_fails_the_battery(tmp_path, name, old, new):
     src = open(ORACLE_C).read()
-    assert old in src, f"mutation site not found: {old!r}"
+    olds, news = (old, new) if isinstance(old, tuple) else ((old,), (new,))
+    for o, n in zip(olds, news):
+        assert o in src, f"mutation site not found: {o!r}"
+        src = src.replace(o, n)  # the same mistake wherever the code occurs
     mut = tmp_path / "oracle_mutant.c"
-    mut.write_text(src.replace(old, new))  # the same mistake wherever the code occurs
+    mut.write_text(src)
     so = tmp_path / "liboracle_mutant.so"
     subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-o", str(so), str(mut)])
     with _oracle_from(str(so)):
