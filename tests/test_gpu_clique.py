@@ -302,3 +302,18 @@ def test_autotune_picks_a_candidate_and_keeps_results(nuri):
         G.close()
     want, _ = oracle.topk_cliques(g, 10)
     assert got.items == want
+
+
+def test_deadline_fails_loudly_and_leaves_the_graph_usable(nuri):
+    """A query past its deadline returns ETIMEOUT, never a partial top-k."""
+    g = synth.gnp(400, 0.05, 5)
+    _case("deadline")
+    G = nuri.Graph.from_synth(g)
+    try:
+        with pytest.raises(nuri.NuriError) as e:
+            nuri.topk_cliques(G, 20, deadline_ns=1)
+        assert e.value.name == "ETIMEOUT"
+        want, _ = oracle.topk_cliques(g, 20)
+        assert nuri.topk_cliques(G, 20).items == want
+    finally:
+        G.close()

@@ -176,3 +176,15 @@ def test_match_edge_cases(nuri):
             nuri.topk_match(G, [0, 0], [(0, 1)], 0)
     finally:
         G.close()
+
+
+def test_match_deadline_fails_loudly(nuri):
+    g = _rmat14()
+    G = _rmat14_dev(nuri)
+    p = synth.random_pattern(3)
+    _case("match deadline")
+    with pytest.raises(nuri.NuriError) as e:
+        nuri.topk_match(G, p.labels, p.edges, 50, deadline_ns=1)
+    assert e.value.name == "ETIMEOUT"
+    want, _ = oracle.topk_match(g, p.labels, p.edges, 50)
+    assert nuri.topk_match(G, p.labels, p.edges, 50).items == want
