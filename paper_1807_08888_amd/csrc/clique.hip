@@ -1333,7 +1333,8 @@ struct Engine {
     const u64 budget = o.frontier_budget;
     const u64 per_q = budget / nq;
     u64 hdr_per_q = std::max<u64>(1024, per_q / 3 / sizeof(CRec));
-    const u64 word_per_q = std::max<u64>(4096, (per_q - hdr_per_q * sizeof(CRec)) / 8);
+    const u64 hdr_bytes = hdr_per_q * sizeof(CRec);
+    const u64 word_per_q = std::max<u64>(4096, per_q > hdr_bytes ? (per_q - hdr_bytes) / 8 : 0);
     hdr_per_q = std::min<u64>(hdr_per_q, 0x7FFFFFFFull);
     hdr.alloc(g.pool, hdr_per_q * nq);
     words.alloc(g.pool, word_per_q * nq);
@@ -1363,7 +1364,9 @@ struct Engine {
     root_B = o.root_batch ? o.root_batch : 8192;
     step_words = std::max<u64>(1ull << 20, std::min<u64>(budget / 16 / 8, 64ull << 20));
     step_children = std::max<u64>(1ull << 16, std::min<u64>(step_words, 32ull << 20));
-    batch_cap = (uint32_t)std::min<u64>((u64)nq * std::max(B, root_B), 1u << 26);
+    // records per step; k_expand runs 64 threads per record and a launch
+    // must stay below 2^31 threads
+    batch_cap = (uint32_t)std::min<u64>((u64)nq * std::max(B, root_B), 1u << 24);
     batch.alloc(g.pool, batch_cap);
     // leaves of one step: at most one per planned child plus one per unit
     // subgraph, and the reserve that chained expansion draws from

@@ -317,3 +317,27 @@ def test_deadline_fails_loudly_and_leaves_the_graph_usable(nuri):
         assert nuri.topk_cliques(G, 20).items == want
     finally:
         G.close()
+
+
+def test_many_queries_with_the_smallest_arenas(nuri):
+    """4096 vertex-weighted queries share a 64 MiB budget: 16 KiB each, below
+    the smallest arena the engine makes (1024 records, 4096 words), so each
+    gets that minimum.  Results equal the same batch under the default
+    budget, and the oracle on three of them.
+    """
+    g = synth.rmat(12)
+    synth.add_vertex_weights(g)
+    ks = [synth.log_uniform_k(i, 100) for i in range(4096)]
+    qs = [{"kind": "clique", "k": k, "weight_fn": 1} for k in ks]
+    _case("4096 weighted queries, R-MAT scale 12, 64 MiB budget")
+    G = nuri.Graph.from_synth(g)
+    try:
+        full = nuri.topk_batch(G, qs)
+        small = nuri.topk_batch(G, qs, frontier_budget_bytes=64 << 20)
+    finally:
+        G.close()
+    for i in range(len(qs)):
+        assert small[i].items == full[i].items, i
+    for i in (0, 1, 2):
+        want, _ = oracle.topk_cliques(g, ks[i], weighted=True)
+        assert small[i].items == want, i
