@@ -141,7 +141,7 @@ static std::vector<uint32_t> degeneracy_order(const nuri_csr &c) {
 // binary-searches x among N+(r)[i+1..d).  A hit at position j is the edge
 // {u, N+(r)[j]}: bits (i, j) and (j, i) are set.
 __global__ void __launch_bounds__(256) k_build_bitmaps(
-    const uint32_t *__restrict__ roots, uint32_t n_roots, const uint64_t *__restrict__ rrow,
+    const uint32_t *__restrict__ roots, const uint64_t *__restrict__ rrow,
     const uint32_t *__restrict__ rcol, const uint32_t *__restrict__ split,
     const uint32_t *__restrict__ dplus, const uint64_t *__restrict__ bm_off,
     unsigned long long *__restrict__ bm) {
@@ -388,7 +388,7 @@ Graph *load_graph(const nuri_csr *csr, hipStream_t stream) {
     const uint32_t chunk = 1u << 30;
     for (size_t b = 0; b < broots.size(); b += chunk) {
       uint32_t cnt = (uint32_t)std::min<size_t>(chunk, broots.size() - b);
-      hipLaunchKernelGGL(k_build_bitmaps, dim3(cnt), dim3(256), 0, s, d_broots.p + b, cnt,
+      hipLaunchKernelGGL(k_build_bitmaps, dim3(cnt), dim3(256), 0, s, d_broots.p + b,
                          g.rrow.p, g.rcol.p, g.split.p, g.dplus.p, g.bm_off.p,
                          (unsigned long long *)g.bm.p);
       NURI_HIP(hipGetLastError());

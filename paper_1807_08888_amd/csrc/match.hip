@@ -488,7 +488,7 @@ __device__ inline int cbin(long long score, const CPre &c) {
   return b < 0 ? 0 : (b > kBins - 1 ? kBins - 1 : (int)b);
 }
 
-__global__ void k_cand_hist(const Cand *cands, uint32_t ncand, const QRes *res, const CPre *pre,
+__global__ void k_cand_hist(const Cand *cands, uint32_t ncand, const CPre *pre,
                             unsigned int *hist) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < ncand) {
@@ -1103,7 +1103,7 @@ struct MatchEngine {
       }
       NURI_HIP(hipMemcpyAsync(d_pre.p, h_pre.p, nq * sizeof(CPre), hipMemcpyHostToDevice, s));
       hipLaunchKernelGGL(k_cand_hist, dim3((ncand + 255) / 256), dim3(256), 0, s, cands.p, ncand,
-                         d_res.p, d_pre.p, d_chist.p);
+                         d_pre.p, d_chist.p);
       NURI_HIP(hipGetLastError());
       hipLaunchKernelGGL(k_cand_hist_topk, dim3(nq), dim3(256), 0, s, d_res.p, d_pre.p,
                          d_chist.p);
