@@ -966,8 +966,11 @@ struct MatchEngine {
         fail(i, NURI_EBUDGET, "frontier budget exhausted");
         continue;
       }
+      // a step's children take at most three quarters of the query's free
+      // arena, so the (at most q) deeper levels always keep room to go on
       const u64 lim = to_leaves ? std::min<u64>(left_cand, std::max(cand_share, rec))
-                                : std::min<u64>(free_h, step_children);
+                                : std::min<u64>(step_children,
+                                                std::max<u64>(free_h - free_h / 4, rec));
       if (lim < rec) continue;
       const uint32_t room = batch_cap - batch_ub;
       if (room == 0) continue;
