@@ -82,9 +82,12 @@ typedef struct {
  * Validates the CSR, copies it to the device and builds the resident
  * structures every query uses: a degeneracy order and the graph relabelled
  * by it, the oriented adjacency N+(v) (later neighbours), one dense local
- * adjacency bitmap per vertex over N+(v), root orders by bound, and the
- * per-(vertex, label) maximum edge weight table (the 1-hop form of the
- * Section 4.3 index, Listing 3).  `hip_stream` is a hipStream_t or NULL
+ * adjacency bitmap per vertex over N+(v), root orders by bound, for each
+ * vertex the earlier neighbours with at least 32 later neighbours (the
+ * only vertices that can extend a clique of 32 or more members, used by
+ * the maximality check of large results), and the per-(vertex, label)
+ * maximum edge weight table (the 1-hop form of the Section 4.3 index,
+ * Listing 3).  `hip_stream` is a hipStream_t or NULL
  * (the library's own stream); all later work on this graph runs on it.
  * Limit: the degeneracy must be at most 4096 (NURI_EINVAL otherwise).
  */
