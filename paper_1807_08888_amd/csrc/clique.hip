@@ -394,6 +394,11 @@ __global__ void __launch_bounds__(256)
 // five bitmaps of wst words (parent P, parent V, parent X, carried child
 // V+P, carried child X) and a candidate list of lst u16 positions.
 constexpr int kExpandWaves = 4;
+// links one wavefront chains before it writes the held child to the
+// frontier instead: a launch lasts as long as its longest chain, and an
+// unbounded chain (hundreds of links down a near-clique) leaves most of the
+// device idle at the end of every launch
+constexpr uint32_t kMaxLinks = 32;
 
 __device__ inline void put_crec(CRec *hdr, u64 slot, long long score, long long bound, u64 woff,
                                 uint32_t root, int j, uint32_t q) {
@@ -454,6 +459,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   const u64 below = gl ? ((1ull << gl) - 1ull) : 0ull;
   bool carried = false;  // p is a kept child carried over from the previous link
   u64 credit = 0;        // leaf slots reserved for chained links, not yet used (lane 0)
+  uint32_t links = 0;    // chained links expanded by this wave
   // write the held child (s_cv, s_cx, s_c*) to header slot hs, word slot ws
   auto write_held = [&](u64 hs, u64 ws) {
     if (lane < (int)W) {
@@ -912,15 +918,16 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     if (!held || spilled) break;
     // exactly one kept child.  Expand it next, in this wave, if a k-th
     // score is known (without one nothing is cut, and thousands of chains
-    // would each run to full depth unpruned) and the leaf buffer has room
-    // for every leaf it can offer (at most one per candidate); otherwise
-    // write it to the frontier like any other child.
+    // would each run to full depth unpruned), the chain is shorter than
+    // kMaxLinks and the leaf buffer has room for every leaf it can offer
+    // (at most one per candidate); otherwise write it to the frontier like
+    // any other child.
     {
       // leaf slots are reserved in chunks of several links' worth; unused
       // credit is handed back when the chain ends
       const u64 m = s_ccnt[wv];
       int ok = 0;
-      if (lane == 0 && theta != LLONG_MIN) {
+      if (lane == 0 && theta != LLONG_MIN && links < kMaxLinks) {
         if (credit < m) {
           for (u64 want = 8 * m; want >= m && !ok; want = want == m ? 0 : m) {
             const u64 oc = atomicAdd(&hdr->chain_c, want);
@@ -957,6 +964,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     p.bound = s_cbound[wv];
     p.last = (int16_t)s_cj[wv];
     carried = true;
+    ++links;
   }
   if (lane == 0 && credit) atomicSub(&hdr->chain_c, credit);
   // flush per-wave statistics with one atomic each
