@@ -249,9 +249,12 @@ void nuri_free_result(nuri_result *r);
  * free; admitted queries share every expansion launch.
  *   frontier_budget_bytes  total device bytes for all live frontiers
  *   max_slots              queries live at once
- * nuri_server_submit copies the query and returns a ticket at once.
+ * nuri_server_submit copies the query and returns a ticket at once
+ * (NURI_EINVAL for a malformed query, or a matching query on a graph
+ * without vertex labels).
  * nuri_server_poll returns 1 and the result when done (the result then
- * belongs to the caller), 0 while pending, < 0 on error.
+ * belongs to the caller), 0 while pending, < 0 on error: the query's own
+ * error, or NURI_EINVAL for a ticket never issued or already collected.
  * nuri_server_destroy waits for nothing: pending queries are dropped.
  */
 int nuri_server_create(nuri_graph *g, uint64_t frontier_budget_bytes, uint32_t max_slots,

@@ -248,6 +248,11 @@ int nuri_server_submit(nuri_server *srv, const nuri_query *q, uint64_t *ticket) 
     set_error("query kind must be 0 (clique) or 1 (match)");
     return NURI_EINVAL;
   }
+  if (q->kind == 1 && !S.ms) {
+    // no matching engine (and no slot) exists for a graph without labels
+    set_error("labelled matching needs vertex labels");
+    return NURI_EINVAL;
+  }
   {
     std::lock_guard<std::mutex> lk(S.mu);
     if (S.fatal) {
@@ -275,6 +280,11 @@ int nuri_server_poll(nuri_server *srv, uint64_t ticket, nuri_result **out) {
   if (it == S.done.end()) {
     if (ticket == 0 || ticket >= S.next_ticket) {
       set_error("unknown ticket");
+      return NURI_EINVAL;
+    }
+    // a ticket is pending until finish() moves it from submit_t to done
+    if (!S.submit_t.count(ticket)) {
+      set_error("ticket already collected");
       return NURI_EINVAL;
     }
     return 0;

@@ -131,3 +131,28 @@ def test_invalid_query_fails_alone(nuri, workload):
         assert res[good].items == _alone(nuri, G, queries[0])
     finally:
         S.close()
+
+
+def test_ticket_errors(nuri):
+    """A collected ticket cannot be polled again, and a matching query on a
+    graph without vertex labels is refused at submission (there is no
+    matching engine to admit it)."""
+    _case("server: ticket lifecycle, matching without labels")
+    G = nuri.Graph.from_synth(synth.gnp(60, 0.2, 5))
+    S = nuri.Server(G, frontier_budget_bytes=1 << 30, max_slots=2)
+    try:
+        t = S.submit({"kind": "clique", "k": 3, "weight_fn": 0})
+        res = _wait(nuri, S, [t])
+        assert res[t].items == nuri.topk_cliques(G, 3).items
+        with pytest.raises(nuri.NuriError) as e:
+            S.poll(t)
+        assert e.value.name == "EINVAL"
+        with pytest.raises(nuri.NuriError) as e:
+            S.poll(t + 100)
+        assert e.value.name == "EINVAL"
+        with pytest.raises(nuri.NuriError) as e:
+            S.submit({"kind": "match", "k": 5, "labels": [0, 0], "edges": [(0, 1)]})
+        assert e.value.name == "EINVAL"
+    finally:
+        S.close()
+        G.close()
