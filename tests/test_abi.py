@@ -90,3 +90,38 @@ def test_bench_traffic_is_null_unless_the_kernel_source_matches(tmp_path, monkey
     assert bench.measured_traffic() is None
     monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", str(tmp_path / "missing.md"))
     assert bench.measured_traffic() is None
+
+
+# ctypes mirror of each struct in include/nuri.h
+_STRUCTS = {"nuri_csr": "_CSR", "nuri_graph_info": "_GraphInfo", "nuri_pattern": "_Pattern",
+            "nuri_opts": "_Opts", "nuri_query": "_Query", "nuri_result_view": "_View",
+            "nuri_stats": "_Stats"}
+
+
+def test_binding_structs_match_the_header(nuri, tmp_path):
+    """sizeof and every field offset of the ctypes structures equal what a C
+    compiler makes of include/nuri.h, and the status and score constants
+    agree (a mismatch would corrupt arguments silently)."""
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "nuri.h"', "int main(void) {"]
+    want = []
+    for cname, pyname in _STRUCTS.items():
+        py = getattr(nuri, pyname)
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        want.append(ctypes.sizeof(py))
+        for f, _ in py._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {f}));')
+            want.append(getattr(py, f).offset)
+    for code, name in nuri.ERRORS.items():
+        lines.append(f'  printf("%d\\n", (int)NURI_{name});')
+        want.append(code)
+    lines.append('  printf("%d\\n%d\\n", (int)NURI_SCORE_SIZE, (int)NURI_SCORE_VERTEX_WEIGHT);')
+    want += [nuri.SCORE_SIZE, nuri.SCORE_VERTEX_WEIGHT]
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.check_call(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER),
+                           "-o", str(exe), str(src)])
+    got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert got == want
