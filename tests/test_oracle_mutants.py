@@ -1,7 +1,7 @@
 """Planted mistakes in the oracle, on the CPU (no GPU).
 
 Each mutant below is oracle.c with one plausible mistake (a dropped term, a
-wrong comparison, a missing check).  It is compiled on its own and run
+wrong comparison, a missing check, a wrong index).  It is compiled on its own and run
 against a battery of the oracle's pins (brute force over small graphs for
 both clique scores, both bounds, and labelled matching); the battery must
 fail for every mutant and pass for the real oracle, so that a mistake of
@@ -62,6 +62,23 @@ MUTANTS = [
     ("matching bound too low for unmatched edges",
      "else ub = T->pairmax[P->label[a] * T->nl + P->label[c]];",
      "else ub = 1;"),
+    ("result set keeps the worse of a new result and the k-th",
+     "if (rank_cmp(score, ids, len, kth->score, kth->ids, kth->len) >= 0) return 0;",
+     "if (rank_cmp(score, ids, len, kth->score, kth->ids, kth->len) < 0) return 0;"),
+    ("greedy colouring ignores adjacency (one colour class)",
+     "if (is_adjacent(g, s->P[i], s->P[j])) used[color[j]] = 1;",
+     "(void)0;"),
+    ("pattern automorphisms ignore labels",
+     "if (P->label[perm[a]] != P->label[a]) ok = 0;",
+     "(void)0;"),
+    ("matching represents an image by its largest tuple",
+     ("if (x < mu[i]) return 0;\n      if (x > mu[i]) break;",
+      "if (x < r->mu[i]) return 0;\n      if (x > r->mu[i]) break;"),
+     ("if (x > mu[i]) return 0;\n      if (x < mu[i]) break;",
+      "if (x > r->mu[i]) return 0;\n      if (x < r->mu[i]) break;")),
+    ("one-endpoint matching bound looks up the matched vertex's own label",
+     "else if (matched[a]) ub = T->best[(uint64_t)r->mu[a] * T->nl + P->label[c]];",
+     "else if (matched[a]) ub = T->best[(uint64_t)r->mu[a] * T->nl + P->label[a]];"),
 ]
 
 MATCH_PATTERNS = [
