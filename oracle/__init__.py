@@ -232,3 +232,60 @@ def topk_cliques_min_size(g, k: int, min_size: int, weighted: bool = False, **kw
     res, st = topk_cliques(sub, k, weighted=weighted, **kw)
     out = [(s, tuple(int(old[i]) for i in ids)) for s, ids in res if len(ids) >= min_size]
     return out, st
+
+
+def large_clique_kernel(g, min_size: int, max_vertices: int = 8192):
+    """Exact reduction for the maximal cliques of g with >= min_size vertices.
+
+    Returns (residual graph, residual -> original id array, common ids):
+    the maximal cliques of g with s >= min_size vertices are exactly
+    common + C for the maximal cliques C of the residual with
+    s - len(common) vertices.  Steps, each exact for such cliques:
+      1. keep the (min_size-1)-core (every member has min_size-1 neighbours
+         inside the clique);
+      2. repeatedly drop edges with fewer than min_size-2 common neighbours
+         and then vertices with fewer than min_size-1 neighbours (every edge
+         of the clique has min_size-2 common neighbours inside it, so
+         nothing of the clique is ever dropped);
+      3. take out the vertices adjacent to all others that are left: every
+         maximal clique of what is left contains them.
+    A vertex extending such a clique in g forms a larger one, which the
+    same steps keep, so maximality is unchanged by the reduction.  Ids stay
+    in increasing original order, so the ranking order is unchanged too
+    (the common ids are shared by every result).
+    """
+    core = core_numbers(g)
+    sub, old = induced_subgraph(g, core >= max(0, min_size - 1))
+    n = sub.n
+    if n > max_vertices:
+        raise ValueError(f"core of {n} vertices is larger than {max_vertices}")
+    A = np.zeros((n, n), np.float32)  # counts below 2^24 are exact in float32
+    rp = sub.row_ptr.astype(np.int64)
+    A[np.repeat(np.arange(n), np.diff(rp)), sub.col.astype(np.int64)] = 1.0
+    alive = np.ones(n, bool)
+    while True:
+        support = A @ A  # common neighbours of every pair
+        weak = (A > 0) & (support < min_size - 2)
+        A[weak] = 0.0
+        low = alive & (A.sum(axis=1) < min_size - 1)
+        A[low, :] = 0.0
+        A[:, low] = 0.0
+        alive &= ~low
+        if not weak.any() and not low.any():
+            break
+    idx = np.flatnonzero(alive)
+    B = A[np.ix_(idx, idx)]
+    universal = B.sum(axis=1) == len(idx) - 1
+    common = old[idx[universal]]
+    rest = idx[~universal]
+    keep = np.zeros(n, bool)
+    keep[rest] = True
+    # the residual keeps only the edges that survived the peeling
+    C = A[np.ix_(rest, rest)]
+    import synth
+    m = len(rest)
+    src, dst = np.nonzero(C)
+    row = np.zeros(m + 1, np.uint64)
+    np.add.at(row, src + 1, 1)
+    resid = synth.Graph(m, np.cumsum(row).astype(np.uint64), dst.astype(np.uint32))
+    return resid, old[rest], [int(v) for v in common]

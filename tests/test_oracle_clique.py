@@ -238,3 +238,34 @@ def test_degeneracy_order_is_a_permutation_with_small_out_degree():
     outdeg = [sum(1 for e in range(int(g.row_ptr[u]), int(g.row_ptr[u + 1]))
                   if pi[int(g.col[e])] > pi[u]) for u in range(g.n)]
     assert max(outdeg) == degeneracy
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_large_clique_kernel_is_exact(seed):
+    """The oracle on the reduced graph (core and truss peeling, common
+    vertices taken out) gives the same maximal cliques of at least s
+    vertices as brute force on the whole graph."""
+    g = synth.gnp(13, 0.45 + 0.04 * (seed % 6), seed)
+    want_all = bruteforce.topk_cliques(g, 100000)
+    for s in (3, 4, 5, 6, 8):
+        want = [x for x in want_all if x[0] >= s]
+        resid, rid, common = oracle.large_clique_kernel(g, s)
+        if resid.n:
+            res, _ = oracle.topk_cliques(resid, 100000)
+            cand = [common + [int(rid[i]) for i in ids] for _, ids in res]
+        else:
+            cand = [common] if common else []
+        got = sorted(((len(c), tuple(sorted(c))) for c in cand if len(c) >= s),
+                     key=lambda t: (-t[0], t[1]))
+        assert got == want, (seed, s)
+
+
+def test_large_clique_kernel_on_planted_workload():
+    g = synth.er_planted()
+    want, _ = oracle.topk_cliques(g, 10)
+    s = min(size for size, _ in want)
+    resid, rid, common = oracle.large_clique_kernel(g, s)
+    res, _ = oracle.topk_cliques(resid, 10)
+    got = sorted(((len(common) + len(ids), tuple(sorted(common + [int(rid[i]) for i in ids])))
+                  for _, ids in res), key=lambda t: (-t[0], t[1]))
+    assert got == want
