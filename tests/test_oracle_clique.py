@@ -269,3 +269,31 @@ def test_large_clique_kernel_on_planted_workload():
     got = sorted(((len(common) + len(ids), tuple(sorted(common + [int(rid[i]) for i in ids])))
                   for _, ids in res), key=lambda t: (-t[0], t[1]))
     assert got == want
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_core_numbers_match_networkx(seed):
+    g = synth.gnp(150, 0.05 * seed, seed)
+    G = nx.Graph()
+    G.add_nodes_from(range(g.n))
+    for u in range(g.n):
+        for e in range(int(g.row_ptr[u]), int(g.row_ptr[u + 1])):
+            G.add_edge(u, int(g.col[e]))
+    want = nx.core_number(G)
+    got = oracle.core_numbers(g)
+    assert [int(got[v]) for v in range(g.n)] == [want[v] for v in range(g.n)]
+
+
+def test_induced_subgraph_keeps_edges_weights_and_id_order():
+    g = synth.gnp(60, 0.2, 7)
+    synth.add_vertex_weights(g, 1, 50, master=7)
+    keep = np.zeros(g.n, bool)
+    keep[np.random.default_rng(7).choice(g.n, 35, replace=False)] = True
+    sub, old = oracle.induced_subgraph(g, keep)
+    assert list(old) == sorted(np.flatnonzero(keep).tolist())
+    edges = {(int(old[u]), int(old[sub.col[e]])) for u in range(sub.n)
+             for e in range(int(sub.row_ptr[u]), int(sub.row_ptr[u + 1]))}
+    want = {(u, int(g.col[e])) for u in range(g.n) if keep[u]
+            for e in range(int(g.row_ptr[u]), int(g.row_ptr[u + 1])) if keep[g.col[e]]}
+    assert edges == want
+    assert list(sub.vertex_weight) == [int(g.vertex_weight[v]) for v in old]
