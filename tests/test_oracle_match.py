@@ -171,3 +171,40 @@ def test_absent_label_gives_empty_result():
     g = _labelled(20, 0.3, 2, n_labels=2, w_hi=3)
     got, _ = oracle.topk_match(g, [5, 0], [(0, 1)], 5, n_labels=16)
     assert got == []
+
+
+@pytest.mark.parametrize("pi", [2, 4, 5, 6, 7])
+def test_topk_equals_networkx_monomorphisms(pi):
+    """The whole ranked list, rebuilt from networkx's monomorphism
+    enumeration: embeddings grouped by image (the set of data edges the
+    pattern edges land on), each image scored by its edge weights and
+    represented by its smallest embedding tuple, ranked by score descending
+    then tuple ascending.  On graphs larger than brute force reaches."""
+    labels, edges = PATTERNS[pi]
+    g = _labelled(45, 0.22, 60 + pi, n_labels=2, w_hi=7)
+    G = _nx(g)
+    for v in range(g.n):
+        G.nodes[v]["l"] = int(g.vertex_label[v])
+    wmap = {}
+    for u in range(g.n):
+        for e in range(int(g.row_ptr[u]), int(g.row_ptr[u + 1])):
+            wmap[(u, int(g.col[e]))] = int(g.edge_weight[e])
+    P = nx.Graph()
+    for a, la in enumerate(labels):
+        P.add_node(a, l=la)
+    P.add_edges_from(edges)
+    gm = nx.algorithms.isomorphism.GraphMatcher(G, P, node_match=lambda x, y: x["l"] == y["l"])
+    best = {}
+    for m in gm.subgraph_monomorphisms_iter():  # data vertex -> pattern vertex
+        mu = [0] * len(labels)
+        for v, a in m.items():
+            mu[a] = v
+        mu = tuple(mu)
+        image = frozenset(frozenset((mu[a], mu[b])) for a, b in edges)
+        if image not in best or mu < best[image]:
+            best[image] = mu
+    ranked = sorted(((sum(wmap[(mu[a], mu[b])] for a, b in edges), mu) for mu in best.values()),
+                    key=lambda t: (-t[0], t[1]))
+    for k in (1, 7, 50, len(ranked) + 1):
+        got, _ = oracle.topk_match(g, labels, edges, k, n_labels=2)
+        assert got == ranked[:k], k
