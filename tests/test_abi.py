@@ -125,3 +125,13 @@ def test_binding_structs_match_the_header(nuri, tmp_path):
                            "-o", str(exe), str(src)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
     assert got == want
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU and says so for --gpus N > 1 (no GPU needed)."""
+    import subprocess
+    import sys
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert p.returncode != 0
+    assert "one GPU" in p.stdout + p.stderr
