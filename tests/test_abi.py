@@ -135,3 +135,26 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=300)
     assert p.returncode != 0
     assert "one GPU" in p.stdout + p.stderr
+
+
+def test_binding_marshals_queries_and_options(nuri):
+    """Query dicts and keyword options reach the C structs unchanged (no GPU)."""
+    qs, keep = nuri._queries([
+        {"kind": "clique", "k": 7, "weight_fn": 1},
+        {"kind": "match", "k": 11, "labels": [3, 0, 3], "edges": [(0, 1), (1, 2)]},
+        {"kind": "clique", "k": 1},
+    ])
+    assert (qs[0].kind, qs[0].k, qs[0].wf, bool(qs[0].p)) == (0, 7, 1, False)
+    assert (qs[2].kind, qs[2].k, qs[2].wf) == (0, 1, nuri.SCORE_SIZE)
+    assert (qs[1].kind, qs[1].k) == (1, 11)
+    p = qs[1].p.contents
+    assert (p.q, p.n_edges) == (3, 2)
+    assert list(ctypes.cast(p.label, ctypes.POINTER(ctypes.c_uint8))[:3]) == [3, 0, 3]
+    assert list(ctypes.cast(p.edges, ctypes.POINTER(ctypes.c_uint32))[:4]) == [0, 1, 1, 2]
+    o = nuri._opts(frontier_budget_bytes=1 << 30, batch_B=4096, root_batch=512, bound=2,
+                   deadline_ns=5, profile=True, stream=1234)
+    assert (o.frontier_budget_bytes, o.batch_B, o.root_batch, o.bound, o.deadline_ns,
+            o.profile, o.hip_stream) == (1 << 30, 4096, 512, 2, 5, 1, 1234)
+    d = nuri._opts()
+    assert (d.frontier_budget_bytes, d.batch_B, d.root_batch, d.bound, d.deadline_ns,
+            d.profile, d.hip_stream) == (0, 0, 0, 0, 0, 0, None)
