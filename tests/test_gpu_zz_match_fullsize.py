@@ -3,8 +3,12 @@
 top-50 each, run as one batch exactly as the benchmark runs it.
 
 Every returned match is checked against the graph (labels, edges, score,
-injectivity, order), and the patterns the oracle finishes in seconds at this
-size are compared with it element by element.
+injectivity, order); the patterns the oracle finishes in seconds at this
+size are compared with it element by element here, and every list the oracle
+finished is compared with the oracle's stored result for its pattern
+(length, best score and the SHA-256 of the whole list; tests/golden/
+rmat22_match_top50.txt, written by the script beside it).  Collected last
+among the GPU tests: it is the longest.
 """
 import numpy as np
 import pytest
@@ -73,3 +77,10 @@ def test_full_size_batch_vs_properties_and_oracle(full):
         print(f"[case] oracle pattern {i}", flush=True)
         want, _ = oracle.topk_match(g, p.labels, p.edges, 50)
         assert outs[i].items == want, i
+    from tests.golden_lists import result_sha256, rmat22_match_top50, workload_sha256
+    sha, rows = rmat22_match_top50()
+    assert workload_sha256(g) == sha, "the generator made a different workload"
+    differ = [i for i in sorted(rows)
+              if (len(outs[i].items), outs[i].items[0][0] if outs[i].items else 0,
+                  result_sha256(outs[i].items)) != rows[i]]
+    assert not differ, f"patterns whose top-50 differs from the oracle's: {differ}"
