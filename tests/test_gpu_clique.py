@@ -1,7 +1,7 @@
 """GPU parity for top-k maximal cliques: the HIP engine against the CPU oracle.
 
 Every comparison is bit-exact on (score, ascending id list) under the total
-order (score descending, ids ascending).  Runs only on a GPU machine.
+order (score descending, ids ascending).  Runs only where a GPU is present.
 """
 import os
 

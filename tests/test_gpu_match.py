@@ -1,7 +1,7 @@
 """GPU parity for top-k labelled subgraph matching: HIP engine vs CPU oracle.
 
 Bit-exact on (score, mu(0..q-1)) under (score descending, tuple ascending).
-Runs only on a GPU machine.
+Runs only where a GPU is present.
 """
 from math import comb
 
