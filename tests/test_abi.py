@@ -158,3 +158,28 @@ def test_binding_marshals_queries_and_options(nuri):
     d = nuri._opts()
     assert (d.frontier_budget_bytes, d.batch_B, d.root_batch, d.bound, d.deadline_ns,
             d.profile, d.hip_stream) == (0, 0, 0, 0, 0, 0, None)
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
+    """No CPU fallback: a missing libnuri.so is an error, not a silent detour."""
+    from paper_1807_08888_amd import nuri as N
+    monkeypatch.setattr(N, "_lib", None)
+    monkeypatch.setattr(N, "LIB_PATH", str(tmp_path / "libnuri.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        N.lib()
+
+
+def test_product_package_never_reaches_the_oracle():
+    """The HIP path and the oracle share no code: nothing under the package
+    imports, loads or names the oracle module or its library."""
+    pkg = os.path.join(ROOT, "paper_1807_08888_amd")
+    offenders = []
+    for dirpath, _, files in os.walk(pkg):
+        if "_build" in dirpath or "__pycache__" in dirpath:
+            continue
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".hpp", ".cpp", ".c")):
+                text = open(os.path.join(dirpath, f), errors="replace").read()
+                if re.search(r"\boracle\b|liboracle", text):
+                    offenders.append(os.path.join(dirpath, f))
+    assert offenders == []
