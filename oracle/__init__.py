@@ -214,26 +214,6 @@ def induced_subgraph(g, keep: np.ndarray):
     return sub, old
 
 
-def topk_cliques_min_size(g, k: int, min_size: int, weighted: bool = False, **kw):
-    """Top-k maximal cliques among those with at least min_size vertices.
-
-    Every clique with s >= min_size vertices lies in the (min_size-1)-core,
-    and any vertex that extends it is adjacent to s >= min_size clique
-    members, so it lies there too: maximality inside the core equals
-    maximality in g.  The oracle therefore runs on the core alone; results
-    are mapped back to original ids (the renumbering keeps id order).
-    Valid as the top-k of g whenever at least k maximal cliques of g have
-    min_size or more vertices (and, for weighted scores, when every result
-    of g's top-k has that many vertices).
-    """
-    core = core_numbers(g)
-    keep = core >= max(0, min_size - 1)
-    sub, old = induced_subgraph(g, keep)
-    res, st = topk_cliques(sub, k, weighted=weighted, **kw)
-    out = [(s, tuple(int(old[i]) for i in ids)) for s, ids in res if len(ids) >= min_size]
-    return out, st
-
-
 def large_clique_kernel(g, min_size: int, max_vertices: int = 8192):
     """Exact reduction for the maximal cliques of g with >= min_size vertices.
 

@@ -11,8 +11,11 @@ difference.  The oracle takes from a few seconds to about a minute per
 pattern on this graph; the patterns are shared out over worker processes.
 
 Run from anywhere: python tests/golden/make_rmat22_match_top50.py [workers]
-[deadline seconds].  With a deadline, patterns the oracle has not finished
-by then are written as "unfinished" and the tests skip them.
+[deadline seconds] [--resume].  With a deadline, patterns the oracle has not
+finished by then are written as "unfinished" and the tests skip them.  With
+--resume, the rows already in the file are kept and only the unfinished
+patterns are run.  The file is rewritten after every finished pattern, so an
+interrupted run keeps what it finished.
 """
 import hashlib
 import multiprocessing as mp
@@ -52,29 +55,21 @@ def _one(i):
     return i, len(res), (res[0][0] if res else 0), result_sha256(res), time.time() - t
 
 
-def main():
-    workers = int(sys.argv[1]) if len(sys.argv) > 1 else 8
-    deadline = float(sys.argv[2]) if len(sys.argv) > 2 else None
-    t0 = time.time()
-    sha = workload_sha256(workload())
+def _read_rows():
     rows = {}
-    # spawn, not fork: the generator runs threads, and a forked copy of a
-    # threaded process can deadlock in them
-    pool = mp.get_context("spawn").Pool(workers)
-    it = pool.imap_unordered(_one, range(N_PATTERNS))
-    try:
-        while len(rows) < N_PATTERNS:
-            left = None if deadline is None else max(1.0, deadline - (time.time() - t0))
-            try:
-                i, n, top, h, dt = it.next(timeout=left)
-            except mp.TimeoutError:
-                break
-            rows[i] = (n, top, h)
-            print(f"pattern {i}: {n} results, best {top}, {dt:.1f} s "
-                  f"({len(rows)}/{N_PATTERNS}, {time.time() - t0:.0f} s)", flush=True)
-    finally:
-        pool.terminate()
-    with open(OUT, "w") as f:
+    if not os.path.exists(OUT):
+        return rows
+    with open(OUT) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) == 5 and parts[0] == "pattern":
+                rows[int(parts[1])] = (int(parts[2]), int(parts[3]), parts[4])
+    return rows
+
+
+def _write(sha, rows):
+    tmp = OUT + ".tmp"
+    with open(tmp, "w") as f:
         f.write("# Top-50 labelled matches of the 128 patterns of the R-MAT scale-22\n"
                 "# matching workload, from the CPU oracle; written by\n"
                 "# make_rmat22_match_top50.py.  pattern <i> <count> <best score> <sha256>\n")
@@ -85,6 +80,36 @@ def main():
                 f.write(f"pattern {i} {n} {top} {h}\n")
             else:
                 f.write(f"pattern {i} unfinished\n")
+    os.replace(tmp, OUT)
+
+
+def main():
+    args = [a for a in sys.argv[1:] if not a.startswith("--")]
+    resume = "--resume" in sys.argv[1:]
+    workers = int(args[0]) if args else 8
+    deadline = float(args[1]) if len(args) > 1 else None
+    t0 = time.time()
+    sha = workload_sha256(workload())
+    rows = _read_rows() if resume else {}
+    todo = [i for i in range(N_PATTERNS) if i not in rows]
+    # spawn, not fork: the generator runs threads, and a forked copy of a
+    # threaded process can deadlock in them
+    pool = mp.get_context("spawn").Pool(workers)
+    it = pool.imap_unordered(_one, todo)
+    try:
+        for _ in range(len(todo)):
+            left = None if deadline is None else max(1.0, deadline - (time.time() - t0))
+            try:
+                i, n, top, h, dt = it.next(timeout=left)
+            except mp.TimeoutError:
+                break
+            rows[i] = (n, top, h)
+            _write(sha, rows)
+            print(f"pattern {i}: {n} results, best {top}, {dt:.1f} s "
+                  f"({len(rows)}/{N_PATTERNS}, {time.time() - t0:.0f} s)", flush=True)
+    finally:
+        pool.terminate()
+    _write(sha, rows)
     print(f"wrote {OUT} ({time.time() - t0:.0f} s)")
 
 

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import synth
-from tests import bruteforce
+from tests import bruteforce, closed_forms
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -297,3 +297,61 @@ def test_induced_subgraph_keeps_edges_weights_and_id_order():
             for e in range(int(g.row_ptr[u]), int(g.row_ptr[u + 1])) if keep[g.col[e]]}
     assert edges == want
     assert list(sub.vertex_weight) == [int(g.vertex_weight[v]) for v in old]
+
+
+@pytest.mark.parametrize("shape", [
+    # (singleton parts, multi-vertex parts, decoy parts, background vertices, seed)
+    (290, [2] * 6 + [3] * 4, 148, 3000, 11),
+    (400, [2] * 30 + [3] * 20, 224, 3000, 12),
+])
+def test_large_clique_kernel_on_dense_cores_in_a_sparse_graph(shape):
+    """The reduction at the shape it is used on: a dense core of 300-520
+    vertices (a complete multipartite graph whose one-vertex parts are
+    adjacent to everything else in it) inside a sparse power-law graph,
+    next to a decoy core whose vertices pass the degree test but whose
+    edges fail the common-neighbour test.  The maximal cliques with s =
+    (number of parts) vertices are exactly the singletons plus a transversal
+    of the other parts, so the kernel must return the singletons as common
+    vertices and, as residual, exactly the other parts with the edges
+    between different parts."""
+    singletons, multi, decoy_parts, n_bg, seed = shape
+    g, s, single, parts, decoys = closed_forms.dense_core_in_background(
+        singletons, multi, decoy_parts, n_bg, seed)
+    core = oracle.core_numbers(g)
+    # the decoys survive core peeling: only the common-neighbour test removes them
+    assert all(int(core[v]) >= s - 1 for v in decoys)
+    resid, rid, common = oracle.large_clique_kernel(g, s)
+    assert common == single
+    members = sorted(v for pt in parts for v in pt)
+    assert sorted(int(x) for x in rid) == members
+    part_of = {v: i for i, pt in enumerate(parts) for v in pt}
+    got_edges = {(int(rid[u]), int(rid[resid.col[e]])) for u in range(resid.n)
+                 for e in range(int(resid.row_ptr[u]), int(resid.row_ptr[u + 1]))}
+    want_edges = {(u, v) for u in members for v in members if part_of[u] != part_of[v]}
+    assert got_edges == want_edges
+    if len(parts) <= 12:
+        # the search on the residual, lifted back, ranks the transversals
+        k = 40
+        res, _ = oracle.topk_cliques(resid, k)
+        got = [(len(common) + len(ids), tuple(sorted(common + [int(rid[i]) for i in ids])))
+               for _, ids in res]
+        full = [tuple(sorted(single + list(t))) for t in closed_forms.transversals(parts)]
+        assert got == closed_forms.ranked(full)[:k]
+        assert all(size == s for size, _ in got)
+
+
+def test_work_limit_stops_the_search_and_resets():
+    """A capped search stops once it has created the cap's children and
+    returns no result; with the cap removed the same query is exact."""
+    g = synth.er_planted()
+    want, st_full = oracle.topk_cliques(g, 10)
+    cap = st_full["children"] // 4
+    oracle.set_work_limit(cap)
+    try:
+        res, st = oracle.topk_cliques(g, 10)
+    finally:
+        oracle.set_work_limit(0)
+    assert res is None
+    assert cap <= st["children"] < st_full["children"]
+    again, st2 = oracle.topk_cliques(g, 10)
+    assert again == want and st2["children"] == st_full["children"]

@@ -107,7 +107,7 @@ def test_uniform_triangle_count():
         assert mu[0] < mu[1] < mu[2]
 
 
-@pytest.mark.parametrize("r", [2, 3])
+@pytest.mark.parametrize("r", [2, 3, 7])
 def test_uniform_star_count(r):
     g = synth.gnp(40, 0.15, 13)
     g.vertex_label = np.zeros(g.n, np.uint8)
@@ -208,3 +208,46 @@ def test_topk_equals_networkx_monomorphisms(pi):
     for k in (1, 7, 50, len(ranked) + 1):
         got, _ = oracle.topk_match(g, labels, edges, k, n_labels=2)
         assert got == ranked[:k], k
+
+
+# eight-vertex patterns (the largest size a query may have): a cycle, a star,
+# a labelled path and a cube-like graph with many automorphisms
+PATTERNS8 = [
+    ([0] * 8, [(i, (i + 1) % 8) for i in range(8)]),
+    ([0] + [0] * 7, [(0, i) for i in range(1, 8)]),
+    ([0, 1, 0, 1, 0, 1, 0, 1], [(i, i + 1) for i in range(7)]),
+    ([0, 0, 0, 0, 1, 1, 1, 1], [(0, 1), (1, 2), (2, 3), (3, 0), (4, 5), (5, 6), (6, 7), (7, 4),
+                                (0, 4), (1, 5), (2, 6), (3, 7)]),
+]
+
+
+@pytest.mark.parametrize("pi", range(len(PATTERNS8)))
+def test_eight_vertex_patterns_match_brute_force(pi):
+    labels, edges = PATTERNS8[pi]
+    n_labels = max(labels) + 1
+    g = _labelled(9, 0.92, 800 + pi, n_labels=n_labels, w_hi=6)
+    # every pattern label on at least four data vertices
+    g.vertex_label = np.array([i % n_labels for i in range(9)], np.uint8)[
+        np.random.default_rng(pi).permutation(9)]
+    want, n_img = bruteforce.topk_matches(g, labels, edges, 10 ** 6)
+    assert n_img > 0
+    got, st = oracle.topk_match(g, labels, edges, 10 ** 6, n_labels=n_labels)
+    assert got == want and len(got) == n_img
+    assert st["automorphisms"] == bruteforce.automorphism_count(labels, edges)
+    for k in (1, 5):
+        top, _ = oracle.topk_match(g, labels, edges, k, n_labels=n_labels)
+        assert top == want[:k]
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_random_eight_vertex_patterns_match_brute_force(idx):
+    pat = synth.random_pattern(900 + idx, q_lo=8, q_hi=8, n_labels=2, s=0.3)
+    assert len(pat.labels) == 8
+    g = _labelled(10, 0.85, 900 + idx, n_labels=2, w_hi=9)
+    # the pattern's own labels plus one vertex of each label, shuffled
+    g.vertex_label = np.array(list(pat.labels) + [0, 1], np.uint8)[
+        np.random.default_rng(idx).permutation(10)]
+    want, n_img = bruteforce.topk_matches(g, pat.labels, pat.edges, 10 ** 6)
+    assert n_img > 0
+    got, _ = oracle.topk_match(g, pat.labels, pat.edges, 10 ** 6, n_labels=2)
+    assert got == want
