@@ -144,6 +144,9 @@ typedef struct {
  *   profile                1: time every expansion launch with HIP events
  *                          (reported in nuri_stats)
  *   hip_stream             hipStream_t to run on (NULL = the graph's stream)
+ *   priority               order in which partial subgraphs are expanded
+ *                          (priority() of Table 1); one of NURI_PRIORITY_*.
+ *                          Results never depend on it, only the work does.
  */
 typedef struct {
   uint64_t frontier_budget_bytes;
@@ -153,7 +156,31 @@ typedef struct {
   uint64_t deadline_ns;
   uint32_t profile;
   void *hip_stream;
+  uint32_t priority;
 } nuri_opts;
+
+/*
+ * Expansion orders (Section 3.2, prioritized expansion; Section 6.1).  A
+ * step expands a batch of records, so each order is followed batch by
+ * batch: within a step every record taken ranks at least as high as every
+ * record left behind of the same level.
+ *   DEPTH  (default) the partial subgraphs with the most vertices first,
+ *          highest bound first among them: the paper's (|V|, |P|) for
+ *          clique sizes and (matched edges, bound) for matching
+ *   BOUND  highest bound first, whatever the size (best-first)
+ *   PAPER  the paper's clique priority (|V|, |P|) also for vertex weights
+ *          (most vertices first, then the largest candidate set); for
+ *          matching the same as DEPTH
+ *   NONE   no prioritization and no pruning, as the paper's Nuri-NP
+ *          variant: only targeted expansion, so every maximal clique (every
+ *          match) is reached and the result set keeps the k best
+ */
+enum {
+  NURI_PRIORITY_DEPTH = 0,
+  NURI_PRIORITY_BOUND = 1,
+  NURI_PRIORITY_PAPER = 2,
+  NURI_PRIORITY_NONE = 3
+};
 
 /*
  * Top-k maximal cliques (Algorithm 1 with the clique user functions of
@@ -239,9 +266,13 @@ typedef struct {
   uint64_t expand_launches;    /* expansion kernel launches */
   uint64_t expand_ns;          /* summed expansion kernel time (profile = 1) */
   uint64_t wall_ns;            /* wall time of the call */
+  uint64_t ties_at_k;          /* results returned whose score equals the k-th's (0 when
+                                  fewer than k); Algorithm 1 would keep every further
+                                  result tied with the k-th too, this engine returns k */
 } nuri_stats;
-int nuri_result_get_stats(const nuri_result *r, nuri_stats *s);
+int nuri_result_stats(const nuri_result *r, nuri_stats *s);
 void nuri_free_result(nuri_result *r);
+
 
 /*
  * Continuous-batching server on one resident graph.  Queries submitted

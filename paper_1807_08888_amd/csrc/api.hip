@@ -35,6 +35,8 @@ QueryOpts resolve_opts(const Graph &g, const nuri_opts *o) {
   q.bound = o->bound;
   q.deadline_ns = o->deadline_ns;
   q.profile = o->profile != 0;
+  if (o->priority > NURI_PRIORITY_NONE) throw Error{NURI_EINVAL, "priority must be 0..3"};
+  q.priority = o->priority;
   if (o->hip_stream) q.stream = (hipStream_t)o->hip_stream;
   if (q.frontier_budget < (64ull << 20))
     throw Error{NURI_EINVAL, "frontier_budget_bytes must be at least 64 MiB"};
@@ -236,7 +238,7 @@ int nuri_result_view_get(const nuri_result *r, nuri_result_view *v) {
   return NURI_OK;
 }
 
-int nuri_result_get_stats(const nuri_result *r, nuri_stats *s) {
+int nuri_result_stats(const nuri_result *r, nuri_stats *s) {
   if (!r || !s) {
     set_error("NULL argument");
     return NURI_EINVAL;

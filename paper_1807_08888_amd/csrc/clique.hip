@@ -49,12 +49,18 @@ namespace {
 struct CRec {
   long long score;
   long long bound;
-  u64 woff;       // word offset of the bitmap in the query's word arena
+  u64 woff;       // low 48 bits: word offset of the bitmap in the query's word
+                  // arena; high 16 bits: |P|, the number of candidates
   uint32_t root;  // rank of the root vertex
   int16_t last;   // local position of the last added vertex; -1 for a unit subgraph
   uint16_t qid;
 };
 static_assert(sizeof(CRec) == 32, "frontier record must stay 32 bytes");
+
+constexpr uint32_t kWoffBits = 48;
+constexpr u64 kWoffMask = (1ull << kWoffBits) - 1;
+__device__ inline u64 pack_woff(u64 woff, uint32_t np) { return woff | ((u64)np << kWoffBits); }
+__device__ inline uint32_t rec_np(const CRec &c) { return (uint32_t)(c.woff >> kWoffBits); }
 
 struct LRec {  // a child with an empty candidate set, awaiting the maximality check
   long long score;
@@ -75,8 +81,20 @@ struct QCfg {  // per query, written by the host each step
   uint32_t k;
   uint32_t colour_min;  // colour cutoff for records with at least this many live
                         // children after the size cutoff (0 = never)
-  uint32_t pad;
+  uint32_t prio;        // NURI_PRIORITY_*: the selection key, and no pruning for NONE
 };
+
+// the k-th score the search prunes against: none without prioritization
+// and pruning (the Nuri-NP order), where only the result set keeps the k best
+__device__ inline long long prune_theta(const QCfg &c, const QRes &r) {
+  return c.prio == NURI_PRIORITY_NONE ? LLONG_MIN : r.theta;
+}
+
+// selection key inside a level: the bound, or |P| for the paper's
+// (|V|, |P|) clique priority
+__device__ inline long long sel_key(const QCfg &c, const CRec &r) {
+  return c.prio == NURI_PRIORITY_PAPER ? (long long)rec_np(r) : r.bound;
+}
 
 struct QStep {  // per query, this step's counters (zeroed by the step upload)
   unsigned int n_out, pad;
@@ -125,7 +143,7 @@ __global__ void k_make_roots(GView g, const RootSeg *segs, CRec *batch, StepHdr 
     CRec c;
     c.score = sg.kind ? (long long)g.vw[r] : 1;
     c.bound = sg.kind ? c.score + g.wplus[r] : 1 + (long long)g.dplus[r];
-    c.woff = 0;
+    c.woff = pack_woff(0, g.dplus[r]);
     c.root = r;
     c.last = -1;
     c.qid = (uint16_t)sg.qid;
@@ -156,13 +174,14 @@ __global__ void __launch_bounds__(256)
     s_c[b] = 0;
   }
   __syncthreads();
-  const long long theta = res[sg.qid].theta;
-  const CRec *h = cfg[sg.qid].hdr + sg.begin;
+  const QCfg cf = cfg[sg.qid];
+  const long long theta = prune_theta(cf, res[sg.qid]);
+  const CRec *h = cf.hdr + sg.begin;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sg.count;
        i += gridDim.x * blockDim.x) {
     const CRec c = h[i];
     if (c.bound < theta) continue;
-    int b = bin_of(c.bound, sg.top, sg.shift);
+    int b = bin_of(sel_key(cf, c), sg.top, sg.shift);
     atomicAdd(&s_h[b], 1u);
     atomicAdd(&s_c[b], rec_children(g, c));
   }
@@ -174,47 +193,24 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-// one thread per segment: scan bins from the top until a limit is reached,
-// then clear the bins for the next step
-__global__ void k_sel_thresh(const SelSeg *segs, uint32_t nseg, unsigned int *hist, u64 *hchild,
-                             int *thr, unsigned int *quota) {
+// threshold bin and quota of each segment (block_select_threshold), then
+// the bins are cleared for the next step.  grid: (segment), 256 threads
+__global__ void __launch_bounds__(kSelThreads)
+    k_sel_thresh(const SelSeg *segs, uint32_t nseg, unsigned int *hist, u64 *hchild, int *thr,
+                 unsigned int *quota) {
   const uint32_t s = blockIdx.x;
   if (s >= nseg) return;
   const SelSeg sg = segs[s];
-  if (threadIdx.x == 0 && !sg.take_all) {
-    u64 n = 0, c = 0;
-    int t = -1;
-    unsigned int q = 0;
-    for (int b = kBins - 1; b >= 0; --b) {
-      size_t o = (size_t)s * kBins + b;
-      u64 hn = hist[o];
-      if (!hn) continue;
-      u64 hc = hchild[o];
-      if (n + hn <= sg.max_records && c + hc <= sg.max_children &&
-          (c + hc) * sg.wpc <= sg.max_words) {
-        n += hn;
-        c += hc;
-        continue;
-      }
-      u64 qa = sg.max_records - n;
-      u64 mc = sg.maxcc ? (sg.max_children - c) / sg.maxcc : qa;
-      u64 mw = sg.maxcc ? (sg.max_words - c * sg.wpc) / (sg.maxcc * sg.wpc) : qa;
-      qa = qa < mc ? qa : mc;
-      qa = qa < mw ? qa : mw;
-      if (qa == 0 && n == 0) qa = 1;  // the host guarantees one record always fits
-      t = b;
-      q = (unsigned int)(qa < hn ? qa : hn);
-      break;
-    }
-    thr[s] = t;
-    quota[s] = q;
-  }
+  if (sg.take_all) return;
+  unsigned int *h = hist + (size_t)s * kBins;
+  u64 *hc = hchild + (size_t)s * kBins;
+  const SelLimits lim{sg.max_records, sg.max_children, sg.max_words, sg.wpc, sg.maxcc};
+  block_select_threshold(h, hc, lim, &thr[s], &quota[s]);
   __syncthreads();
-  if (!sg.take_all)
-    for (int b = threadIdx.x; b < kBins; b += blockDim.x) {
-      hist[(size_t)s * kBins + b] = 0;
-      hchild[(size_t)s * kBins + b] = 0;
-    }
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) {
+    h[b] = 0;
+    hc[b] = 0;
+  }
 }
 
 __global__ void k_sel_part(const SelSeg *segs, const QCfg *cfg, const QRes *res, const int *thr,
@@ -222,8 +218,9 @@ __global__ void k_sel_part(const SelSeg *segs, const QCfg *cfg, const QRes *res,
                            StepHdr *hdr, CRec *temp, unsigned int *temp_count, QCtr *ctr) {
   const uint32_t s = blockIdx.y;
   const SelSeg sg = segs[s];
-  const long long theta = res[sg.qid].theta;
-  const CRec *h = cfg[sg.qid].hdr + sg.begin;
+  const QCfg cf = cfg[sg.qid];
+  const long long theta = prune_theta(cf, res[sg.qid]);
+  const CRec *h = cf.hdr + sg.begin;
   const int t = sg.take_all ? -1 : thr[s];
   const unsigned int qt = sg.take_all ? 0 : quota[s];
   unsigned int pruned = 0;
@@ -236,7 +233,7 @@ __global__ void k_sel_part(const SelSeg *segs, const QCfg *cfg, const QRes *res,
     } else if (sg.take_all) {
       where = 1;
     } else {
-      int b = bin_of(c.bound, sg.top, sg.shift);
+      int b = bin_of(sel_key(cf, c), sg.top, sg.shift);
       if (b > t) where = 1;
       else if (b < t) where = 2;
       else where = atomicAdd(&taken[s], 1u) < qt ? 1 : 2;
@@ -401,11 +398,11 @@ constexpr int kExpandWaves = 4;
 constexpr uint32_t kMaxLinks = 32;
 
 __device__ inline void put_crec(CRec *hdr, u64 slot, long long score, long long bound, u64 woff,
-                                uint32_t root, int j, uint32_t q) {
+                                uint32_t np, uint32_t root, int j, uint32_t q) {
   CRec ch;
   ch.score = score;
   ch.bound = bound;
-  ch.woff = woff;
+  ch.woff = pack_woff(woff, np);
   ch.root = root;
   ch.last = (int16_t)j;
   ch.qid = (uint16_t)q;
@@ -434,7 +431,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   CRec p = batch[rec];
   const uint32_t q = p.qid;
   const QCfg cf = cfg[q];
-  const long long theta = res[q].theta;
+  const long long theta = prune_theta(cf, res[q]);
   const bool weighted = cf.weighted != 0;
   // wave-uniform counters; the per-child ones of written children are
   // gathered in LDS by the lanes that write them
@@ -468,7 +465,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     }
     if (lane == 0) {
       const int jc = s_cj[wv];
-      put_crec(cf.hdr, hs, s_cscore[wv], s_cbound[wv], ws, r, jc, q);
+      put_crec(cf.hdr, hs, s_cscore[wv], s_cbound[wv], ws, s_ccnt[wv], r, jc, q);
       const u64 cc = (u64)(d - jc - 1);
       atomicAdd(&s_cost[wv], cc);
       atomicMax(&s_maxcc[wv], cc);
@@ -509,8 +506,9 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         word = s_cv[lane];
         xword = s_cx[lane];
       } else {
-        word = last < 0 ? lt_mask(lane, d) : cf.words[p.woff + lane];
-        xword = last < 0 ? 0ull : cf.words[p.woff + W + lane];
+        const u64 wo = p.woff & kWoffMask;
+        word = last < 0 ? lt_mask(lane, d) : cf.words[wo + lane];
+        xword = last < 0 ? 0ull : cf.words[wo + W + lane];
       }
     }
     const u64 pw = word & gt_mask(lane, last);
@@ -870,7 +868,8 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
                 cf.words[slot_w + W + wi] = xc;
               }
               if (wi == 0) {
-                put_crec(cf.hdr, (u64)cf.out_hdr + h0 + rk, score2, bound2, slot_w, r, (int)j, q);
+                put_crec(cf.hdr, (u64)cf.out_hdr + h0 + rk, score2, bound2, slot_w, cnt, r, (int)j,
+                         q);
                 const u64 cc = (u64)(d - j - 1);
                 atomicAdd(&s_cost[wv], cc);
                 atomicMax(&s_maxcc[wv], cc);
@@ -1278,10 +1277,19 @@ struct Engine {
   std::unique_ptr<StepLayout> L;
   bool trace = false;  // NURI_TRACE=1: one line per step on stderr
   uint32_t rr = 0;     // round-robin start of the per-step planning
+  std::vector<int> level_order;  // scratch of plan()
 
-  Engine(Graph &g_, const QueryOpts &o_) : g(g_), o(o_), s(o_.stream ? o_.stream : g_.stream) {
+  // device memory of every buffer: the graph's pool, or a fixed region
+  // (the allocation-free entry point), from which nothing is allocated
+  MemPool *mp;
+  uint64_t fixed_topk_bytes = 0;  // fixed region: bytes kept for the top-k buffers
+
+  Engine(Graph &g_, const QueryOpts &o_, MemPool *pool = nullptr)
+      : g(g_), o(o_), s(o_.stream ? o_.stream : g_.stream), mp(pool ? pool : &g_.pool) {
     const char *t = getenv("NURI_TRACE");
     trace = t && t[0] == '1';
+    const bool pinned = mp->fixed_base == nullptr;
+    h_seed.pinned = h_step.pinned = h_res.pinned = h_ctr.pinned = h_k.pinned = pinned;
   }
   ~Engine() {
     if (ev0) (void)hipEventDestroy(ev0);
@@ -1338,14 +1346,49 @@ struct Engine {
     seg_cap = std::min<uint32_t>(nq * kSegPerQuery, std::max<uint32_t>(nq, 1024));
     L.reset(new StepLayout(nq, seg_cap));
     seg_level.assign(seg_cap, 0);
-    const u64 budget = o.frontier_budget;
+    const bool fixed = mp->fixed_base != nullptr;
+    B = o.batch_B ? o.batch_B : 16384;
+    root_B = o.root_batch ? o.root_batch : 8192;
+    // LDS of k_expand: five bitmaps of the widest local row and a candidate
+    // list as long as the largest out-degree, per wave
+    ex_wst = std::max<uint32_t>(1, (g.degeneracy + 63) / 64);
+    ex_lst = (g.degeneracy + 8) & ~7u;
+    u64 budget = o.frontier_budget;
+    if (fixed) {
+      // a fixed region: small steps, and the frontier gets what is left
+      // after every other buffer (temp, which holds a level being
+      // selected from, is sized with the headers)
+      B = std::min<uint32_t>(B, 4096);
+      root_B = std::min<uint32_t>(root_B, 4096);
+      step_words = 1ull << 17;
+      step_children = 1ull << 16;
+      batch_cap = nq * std::max(B, root_B);
+      leaf_cap = (uint32_t)(2 * step_children + batch_cap);
+      leaf_word_cap = 2 * step_words;
+      const u64 other = MemPool::align_up(batch_cap * sizeof(CRec)) +
+                        MemPool::align_up((u64)leaf_cap * sizeof(LRec)) +
+                        MemPool::align_up(leaf_word_cap * 8) +
+                        MemPool::align_up(kCandChunk * sizeof(Cand)) +
+                        MemPool::align_up((u64)kCandChunk * lmax * 4) +
+                        MemPool::align_up((u64)seg_cap * kBins * 4) +
+                        MemPool::align_up((u64)seg_cap * kBins * 8) +
+                        MemPool::align_up(L->total) + 16 * 4096 + fixed_topk_bytes +
+                        (u64)nq * (kCandChunk * 4 + 1024);
+      const u64 have = mp->fixed_size - MemPool::align_up(mp->fixed_used);
+      if (have < other + (4ull << 20))
+        throw Error{NURI_EINVAL, "query too large for the fixed scratch region: needs more than " +
+                                     std::to_string(other + (4ull << 20)) + " of " +
+                                     std::to_string(have) + " bytes"};
+      budget = have - other;
+    }
     const u64 per_q = budget / nq;
-    u64 hdr_per_q = std::max<u64>(1024, per_q / 3 / sizeof(CRec));
-    const u64 hdr_bytes = hdr_per_q * sizeof(CRec);
+    // fixed region: a quarter headers, a quarter their selection copy, half words
+    u64 hdr_per_q = std::max<u64>(1024, per_q / (fixed ? 4 : 3) / sizeof(CRec));
+    const u64 hdr_bytes = hdr_per_q * sizeof(CRec) * (fixed ? 2 : 1);
     const u64 word_per_q = std::max<u64>(4096, per_q > hdr_bytes ? (per_q - hdr_bytes) / 8 : 0);
     hdr_per_q = std::min<u64>(hdr_per_q, 0x7FFFFFFFull);
-    hdr.alloc(g.pool, hdr_per_q * nq);
-    words.alloc(g.pool, word_per_q * nq);
+    hdr.alloc(*mp, hdr_per_q * nq);
+    words.alloc(*mp, word_per_q * nq);
     h_res.alloc(nq);
     h_ctr.alloc(nq);
     h_k.alloc(nq);
@@ -1362,41 +1405,38 @@ struct Engine {
       R.theta = LLONG_MIN;
       h_k.p[i] = 1;
     }
-    d_ctr.alloc(g.pool, nq);
-    d_res.alloc(g.pool, nq);
-    d_k.alloc(g.pool, nq);
+    d_ctr.alloc(*mp, nq);
+    d_res.alloc(*mp, nq);
+    d_k.alloc(*mp, nq);
     NURI_HIP(hipMemcpyAsync(d_res.p, h_res.p, nq * sizeof(QRes), hipMemcpyHostToDevice, s));
     NURI_HIP(hipMemcpyAsync(d_k.p, h_k.p, nq * sizeof(uint32_t), hipMemcpyHostToDevice, s));
     NURI_HIP(hipMemsetAsync(d_ctr.p, 0, nq * sizeof(QCtr), s));
-    B = o.batch_B ? o.batch_B : 16384;
-    root_B = o.root_batch ? o.root_batch : 8192;
-    step_words = std::max<u64>(1ull << 20, std::min<u64>(budget / 16 / 8, 64ull << 20));
-    step_children = std::max<u64>(1ull << 16, std::min<u64>(step_words, 32ull << 20));
-    // records per step; k_expand runs 64 threads per record and a launch
-    // must stay below 2^31 threads
-    batch_cap = (uint32_t)std::min<u64>((u64)nq * std::max(B, root_B), 1u << 24);
-    batch.alloc(g.pool, batch_cap);
-    // leaves of one step: at most one per planned child plus one per unit
-    // subgraph, and the reserve that chained expansion draws from
-    leaf_cap = (uint32_t)(2 * step_children + batch_cap);
-    leaf_word_cap = 2 * step_words;
-    // LDS of k_expand: five bitmaps of the widest local row and a candidate
-    // list as long as the largest out-degree, per wave
-    ex_wst = std::max<uint32_t>(1, (g.degeneracy + 63) / 64);
-    ex_lst = (g.degeneracy + 8) & ~7u;
+    if (!fixed) {
+      step_words = std::max<u64>(1ull << 20, std::min<u64>(budget / 16 / 8, 64ull << 20));
+      step_children = std::max<u64>(1ull << 16, std::min<u64>(step_words, 32ull << 20));
+      // records per step; k_expand runs 64 threads per record and a launch
+      // must stay below 2^31 threads
+      batch_cap = (uint32_t)std::min<u64>((u64)nq * std::max(B, root_B), 1u << 24);
+      // leaves of one step: at most one per planned child plus one per unit
+      // subgraph, and the reserve that chained expansion draws from
+      leaf_cap = (uint32_t)(2 * step_children + batch_cap);
+      leaf_word_cap = 2 * step_words;
+    }
+    batch.alloc(*mp, batch_cap);
+    if (fixed) temp.alloc(*mp, hdr_per_q * nq);  // every level fits; never grown
     expand_lds = (size_t)kExpandWaves * (5ull * 8 * ex_wst + 2ull * ex_lst);
-    leaves.alloc(g.pool, leaf_cap);
-    leaf_words.alloc(g.pool, leaf_word_cap);
-    cands.alloc(g.pool, kCandChunk);
-    mbuf.alloc(g.pool, nq, s);
+    leaves.alloc(*mp, leaf_cap);
+    leaf_words.alloc(*mp, leaf_word_cap);
+    cands.alloc(*mp, kCandChunk);
+    mbuf.alloc(*mp, nq, s);
     h_seed.alloc(nq);
-    d_seed.alloc(g.pool, nq);
-    cand_ids.alloc(g.pool, (u64)kCandChunk * lmax);
-    d_hist.alloc(g.pool, (u64)seg_cap * kBins);
-    d_hchild.alloc(g.pool, (u64)seg_cap * kBins);
+    d_seed.alloc(*mp, nq);
+    cand_ids.alloc(*mp, (u64)kCandChunk * lmax);
+    d_hist.alloc(*mp, (u64)seg_cap * kBins);
+    d_hchild.alloc(*mp, (u64)seg_cap * kBins);
     NURI_HIP(hipMemsetAsync(d_hist.p, 0, d_hist.bytes(), s));
     NURI_HIP(hipMemsetAsync(d_hchild.p, 0, d_hchild.bytes(), s));
-    d_step.alloc(g.pool, L->total);
+    d_step.alloc(*mp, L->total);
     h_step.alloc(L->total);
     if (o.profile) {
       NURI_HIP(hipEventCreate(&ev0));
@@ -1421,11 +1461,11 @@ struct Engine {
     // automatic: colour classes unless the densest region is a near-clique
     const bool colour = o.bound == 2 || (o.bound == 0 && g.core_density < 0.9);
     c.colour_min = colour ? 1u : 0u;
-    c.pad = 0;
+    c.prio = o.priority;
     SlotTopk &T = *tk[i];
-    T.score.alloc(g.pool, 2ull * k);
-    T.len.alloc(g.pool, 2ull * k);
-    T.ids.alloc(g.pool, 2ull * k * lmax);
+    T.score.alloc(*mp, 2ull * k);
+    T.len.alloc(*mp, 2ull * k);
+    T.ids.alloc(*mp, 2ull * k * lmax);
     QRes &R = h_res.p[i];
     R.theta = LLONG_MIN;
     R.tk_n = 0;
@@ -1490,21 +1530,31 @@ struct Engine {
       }
       while (!Q.stack.empty() && Q.stack.back().count == 0) Q.stack.pop_back();
       const u64 cap_c = std::min(left_c, share_c), cap_w = std::min(left_w, share_w);
-      if (Q.stack.empty()) {
-        // unit subgraphs: the next roots in bound order with bound >= theta
-        const auto &rb = g.h_root_bound[Q.kind];
-        const auto &ro = g.h_root_order[Q.kind];
-        u64 end = g.n;
-        if (Q.theta != LLONG_MIN)
-          end = std::lower_bound(rb.begin(), rb.end(), Q.theta,
-                                 [](long long a, long long t) { return a >= t; }) -
-                rb.begin();
+      const bool prune = o.priority != NURI_PRIORITY_NONE;
+      // unit subgraphs left: the next roots in bound order with bound >= theta
+      const auto &rb = g.h_root_bound[Q.kind];
+      const auto &ro = g.h_root_order[Q.kind];
+      u64 end = g.n;
+      if (Q.theta != LLONG_MIN && prune)
+        end = std::lower_bound(rb.begin(), rb.end(), Q.theta,
+                               [](long long a, long long t) { return a >= t; }) -
+              rb.begin();
+      // best-first: unit subgraphs come before records of lower bound
+      long long level_best = LLONG_MIN;
+      for (const Level &Lv : Q.stack)
+        if (Lv.count) level_best = std::max(level_best, Lv.max_bound);
+      const bool roots_first = o.priority == NURI_PRIORITY_BOUND && !Q.stack.empty() &&
+                               Q.cursor < end && rb[Q.cursor] > level_best;
+      if (Q.stack.empty() || roots_first) {
         if (Q.cursor >= end) {
           Q.done = true;
           continue;
         }
+        const u64 new_h = Q.stack.empty() ? 0 : (u64)Q.stack.back().begin + Q.stack.back().count;
+        const u64 new_w = Q.stack.empty() ? 0 : Q.stack.back().wend;
         u64 cc = 0, cw = 0, cnt = 0;
-        const u64 lim_c = std::min<u64>(cap_c, Q.hdr_cap), lim_w = std::min<u64>(cap_w, Q.word_cap);
+        const u64 lim_c = std::min<u64>(cap_c, Q.hdr_cap - new_h),
+                  lim_w = std::min<u64>(cap_w, Q.word_cap - new_w);
         while (Q.cursor + cnt < end && cnt < root_B && batch_ub + cnt < batch_cap) {
           const uint32_t r = ro[Q.cursor + cnt];
           const u64 d = g.h_dplus[r];
@@ -1514,7 +1564,7 @@ struct Engine {
           cw += w;
           ++cnt;
         }
-        if (cc > Q.hdr_cap || cw > Q.word_cap) {
+        if (cc > Q.hdr_cap - new_h || cw > Q.word_cap - new_w) {
           fail(i, NURI_EBUDGET, "frontier budget too small for one unit subgraph");
           continue;
         }
@@ -1527,8 +1577,8 @@ struct Engine {
         max_rseg_count = std::max(max_rseg_count, rs.count);
         Q.cursor += cnt;
         Q.plan = 1;
-        Q.new_begin = 0;
-        Q.new_wbegin = 0;
+        Q.new_begin = (uint32_t)new_h;
+        Q.new_wbegin = new_w;
         batch_ub += (uint32_t)cnt;
         left_c -= std::min(left_c, cc);
         left_w -= std::min(left_w, cw);
@@ -1553,7 +1603,16 @@ struct Engine {
       Q.seg0 = nseg;
       Q.nsegs = 0;
       u64 rec_left = B;
-      for (int li = (int)Q.stack.size() - 1; li >= 0; --li) {
+      // levels in priority order: the deepest first, or the highest bound
+      // first (ties: the deeper)
+      std::vector<int> &lorder = level_order;
+      lorder.resize(Q.stack.size());
+      for (size_t t2 = 0; t2 < lorder.size(); ++t2) lorder[t2] = (int)(lorder.size() - 1 - t2);
+      if (o.priority == NURI_PRIORITY_BOUND)
+        std::stable_sort(lorder.begin(), lorder.end(), [&](int a, int b) {
+          return Q.stack[a].max_bound > Q.stack[b].max_bound;
+        });
+      for (int li : lorder) {
         if (nseg >= L->nseg_cap || Q.nsegs >= kSegPerQuery || rec_left == 0) break;
         const Level &Lv = Q.stack[li];
         if (Lv.count == 0) continue;
@@ -1574,8 +1633,13 @@ struct Engine {
         sg.top = Lv.max_bound;
         sg.maxcc = Lv.maxcc;
         sg.wpc = 2ull * Lv.maxw;
-        const long long floor_b = Q.theta == LLONG_MIN ? 0 : Q.theta;
-        const long long span = Lv.max_bound - floor_b;
+        long long floor_b = Q.theta == LLONG_MIN || !prune ? 0 : Q.theta;
+        if (o.priority == NURI_PRIORITY_PAPER) {
+          // key |P| <= the largest out-neighbourhood
+          sg.top = g.degeneracy;
+          floor_b = 0;
+        }
+        const long long span = sg.top - floor_b;
         uint32_t shift = 0;
         while (span > 0 && (span >> shift) >= kBins - 1) ++shift;
         sg.shift = shift;
@@ -1637,7 +1701,7 @@ struct Engine {
     if (nseg) {
       bool any_sel = false;
       for (uint32_t i = 0; i < nseg; ++i) any_sel |= !sseg()[i].take_all;
-      if (temp_need && temp.n < temp_need) temp.alloc(g.pool, temp_need * 2);
+      if (temp_need && temp.n < temp_need) temp.alloc(*mp, temp_need * 2);
       const uint32_t bx = std::max(1u, std::min<uint32_t>((max_seg_count + 255) / 256, 2048));
       if (any_sel) {
         hipLaunchKernelGGL(k_sel_hist, dim3(std::min(bx, 512u), nseg), dim3(256), 0, s, gv, dseg,
@@ -1749,6 +1813,10 @@ struct Engine {
     for (uint32_t i = 0; i < nq; ++i) {
       QHost &Q = qh[i];
       if (!Q.active || Q.done || Q.seeded) continue;
+      if (o.priority == NURI_PRIORITY_NONE) {
+        Q.seeded = true;  // no pruning: an early k-th score would not be used
+        continue;
+      }
       const u64 want = std::min<u64>(g.n, std::max<u64>(2ull * Q.k, 512));
       const u64 room = std::min<u64>(leaf_cap, leaf_word_cap / ex_wst);
       if (total + want > room) break;  // the rest seed at the next step
@@ -1843,6 +1911,7 @@ struct Engine {
     st.expand_launches = Q.launches;
     st.expand_ns = Q.expand_ns;
     st.wall_ns = now_ns() - Q.t_admit;
+    st.ties_at_k = ties_at_k(res.score, Q.k);
     Q.active = false;
     Q.stack.clear();
     tk[i]->score.release();
@@ -1872,6 +1941,30 @@ void run_cliques(Graph &g, const std::vector<uint32_t> &ks, const std::vector<in
   }
   out.resize(ks.size());
   for (uint32_t i = 0; i < ks.size(); ++i) e.harvest(i, out[i]);
+}
+
+// One clique query whose device buffers all come from the caller's fixed
+// region [base, base + bytes): nothing is allocated on the device and no
+// host memory is page-locked.  The region's previous contents are never
+// read: every buffer that must start at zero is cleared by the query.
+void run_clique_fixed(Graph &g, uint32_t k, int kind, const QueryOpts &o, void *base, size_t bytes,
+                      Result &out) {
+  check_clique_query(g, k, kind);
+  MemPool region;
+  region.fixed_base = static_cast<unsigned char *>(base);
+  region.fixed_size = bytes;
+  QueryOpts q = o;
+  q.profile = false;  // no HIP events either
+  Engine e(g, q, &region);
+  const u64 lmax = g.degeneracy + 1;
+  e.fixed_topk_bytes = MemPool::align_up(2ull * k * 8) + MemPool::align_up(2ull * k * 4) +
+                       MemPool::align_up(2ull * k * lmax * 4);
+  e.setup(1);
+  e.admit(0, k, kind);
+  while (e.step_all()) {
+  }
+  e.harvest(0, out);
+  if (out.error) throw Error{out.error, out.errmsg};
 }
 
 // ------------------------------------------------------------------

@@ -142,6 +142,94 @@ __device__ inline int bin_of(long long bound, long long top, uint32_t shift) {
 }
 
 // ------------------------------------------------------------------
+// selection threshold over a bound histogram (one 256-thread block per
+// segment).  Bins are taken from the top while the records, the children
+// they may create and those children's bitmap words all stay within the
+// step's limits; the first bin (from the top) that would break a limit is
+// the threshold bin t, of which only `quota` records are taken.  Running
+// totals from the top are a suffix scan over the bins: each thread owns 8
+// consecutive bins, the block scans the per-thread totals, and every thread
+// tests its own bins.  A bin can only break a limit if it holds records
+// (an empty bin adds nothing to the totals), so t is never empty.
+// ------------------------------------------------------------------
+constexpr int kSelThreads = 256;
+constexpr int kBinsPerThread = kBins / kSelThreads;
+static_assert(kBins % kSelThreads == 0, "bins are shared evenly by the threads");
+
+struct SelLimits {
+  u64 max_records, max_children, max_words;
+  u64 wpc;    // bitmap words per child (0: no word limit)
+  u64 maxcc;  // most children one record of the level can create
+};
+
+// hist/hchild: this segment's kBins counters (records, children) per bin.
+// Writes (t, quota) from thread 0; every thread must call it.
+__device__ inline void block_select_threshold(const unsigned int *hist, const u64 *hchild,
+                                              const SelLimits lim, int *t_out,
+                                              unsigned int *q_out) {
+  __shared__ u64 s_n[kSelThreads], s_c[kSelThreads];
+  __shared__ int s_t;
+  const int tid = threadIdx.x;
+  // this thread's bins: b0 .. b0 + 7; thread 0 holds the top bins
+  const int b0 = kBins - (tid + 1) * kBinsPerThread;
+  u64 hn[kBinsPerThread], hc[kBinsPerThread];
+  u64 tn = 0, tc = 0;
+  for (int i = 0; i < kBinsPerThread; ++i) {
+    hn[i] = hist[b0 + i];
+    hc[i] = hchild[b0 + i];
+    tn += hn[i];
+    tc += hc[i];
+  }
+  s_n[tid] = tn;
+  s_c[tid] = tc;
+  if (tid == 0) s_t = -1;
+  __syncthreads();
+  // inclusive scan over threads (Hillis-Steele in LDS)
+  for (int off = 1; off < kSelThreads; off <<= 1) {
+    const u64 an = tid >= off ? s_n[tid - off] : 0, ac = tid >= off ? s_c[tid - off] : 0;
+    __syncthreads();
+    s_n[tid] += an;
+    s_c[tid] += ac;
+    __syncthreads();
+  }
+  // totals of the bins above this thread's bins
+  u64 n = s_n[tid] - tn, c = s_c[tid] - tc;
+  auto fits = [&](u64 nn, u64 cc) {
+    return nn <= lim.max_records && cc <= lim.max_children &&
+           (lim.wpc == 0 || cc * lim.wpc <= lim.max_words);
+  };
+  int mine = -1;  // highest bin of this thread that breaks a limit
+  u64 n_at = 0, c_at = 0;
+  for (int i = kBinsPerThread - 1; i >= 0; --i) {
+    if (hn[i] && !fits(n + hn[i], c + hc[i])) {
+      mine = b0 + i;
+      n_at = n;
+      c_at = c;
+      break;
+    }
+    n += hn[i];
+    c += hc[i];
+  }
+  if (mine >= 0) atomicMax(&s_t, mine);
+  __syncthreads();
+  if (mine >= 0 && mine == s_t) {
+    u64 qa = lim.max_records - n_at;
+    const u64 mc = lim.maxcc ? (lim.max_children - c_at) / lim.maxcc : qa;
+    const u64 mw = (lim.maxcc && lim.wpc) ? (lim.max_words - c_at * lim.wpc) / (lim.maxcc * lim.wpc)
+                                          : qa;
+    qa = qa < mc ? qa : mc;
+    qa = qa < mw ? qa : mw;
+    if (qa == 0 && n_at == 0) qa = 1;  // the host guarantees one record always fits
+    const u64 h = hist[mine];
+    *t_out = mine;
+    *q_out = (unsigned int)(qa < h ? qa : h);
+  } else if (tid == 0 && s_t < 0) {
+    *t_out = -1;
+    *q_out = 0;
+  }
+}
+
+// ------------------------------------------------------------------
 // top-k merge (Algorithm 1, lines 6-10) under the total order
 // (score descending, then ascending id list lexicographically)
 // ------------------------------------------------------------------
@@ -332,21 +420,28 @@ inline void launch_merge(const Cand *cands, const StepHdr *hdr, const uint32_t *
   NURI_HIP(hipGetLastError());
 }
 
-// page-locked host staging buffer
+// host staging buffer: page-locked, or (pinned = false, for the
+// allocation-free entry point) ordinary pageable host memory
 template <class T>
 struct PinBuf {
   T *p = nullptr;
   size_t n = 0;
+  bool pinned = true;
   PinBuf() = default;
   PinBuf(const PinBuf &) = delete;
   PinBuf &operator=(const PinBuf &) = delete;
-  ~PinBuf() {
-    if (p) (void)hipHostFree(p);
+  ~PinBuf() { release(); }
+  void release() {
+    if (p) {
+      if (pinned) (void)hipHostFree(p);
+      else ::operator delete(p);
+    }
+    p = nullptr;
   }
   void alloc(size_t count) {
-    if (p) (void)hipHostFree(p);
-    p = nullptr;
-    NURI_HIP(hipHostMalloc((void **)&p, count * sizeof(T), 0));
+    release();
+    if (pinned) NURI_HIP(hipHostMalloc((void **)&p, count * sizeof(T), 0));
+    else p = static_cast<T *>(::operator new(count * sizeof(T)));
     n = count;
   }
 };

@@ -67,7 +67,13 @@ struct MView {
 struct MCfg {  // per query, per step
   MRec *hdr;
   uint32_t out_hdr, hdr_cap;
+  uint32_t prio, pad;  // NURI_PRIORITY_*: no pruning for NONE
 };
+
+// the k-th score the search prunes against (none in the Nuri-NP order)
+__device__ inline long long mprune_theta(const MCfg &c, const QRes &r) {
+  return c.prio == NURI_PRIORITY_NONE ? LLONG_MIN : r.theta;
+}
 
 struct MStep {  // per query, this step's counters
   unsigned int n_out, n_kept, overflow, cand_n;
@@ -186,7 +192,7 @@ __global__ void __launch_bounds__(256)
     s_c[b] = 0;
   }
   __syncthreads();
-  const long long theta = res[sg.qid].theta;
+  const long long theta = mprune_theta(cfg[sg.qid], res[sg.qid]);
   const MRec *h = cfg[sg.qid].hdr + sg.begin;
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sg.count;
        i += gridDim.x * blockDim.x) {
@@ -204,42 +210,22 @@ __global__ void __launch_bounds__(256)
     }
 }
 
-__global__ void k_msel_thresh(const MSeg *segs, uint32_t nseg, unsigned int *hist, u64 *hcost,
-                              int *thr, unsigned int *quota) {
+__global__ void __launch_bounds__(kSelThreads)
+    k_msel_thresh(const MSeg *segs, uint32_t nseg, unsigned int *hist, u64 *hcost, int *thr,
+                  unsigned int *quota) {
   const uint32_t s = blockIdx.x;
   if (s >= nseg) return;
   const MSeg sg = segs[s];
-  if (threadIdx.x == 0 && !sg.take_all) {
-    u64 n = 0, c = 0;
-    int t = -1;
-    unsigned int q = 0;
-    for (int b = kBins - 1; b >= 0; --b) {
-      size_t o = (size_t)s * kBins + b;
-      u64 hn = hist[o];
-      if (!hn) continue;
-      u64 hc = hcost[o];
-      if (n + hn <= sg.max_records && c + hc <= sg.max_children) {
-        n += hn;
-        c += hc;
-        continue;
-      }
-      u64 qa = sg.max_records - n;
-      u64 mc = sg.maxcost ? (sg.max_children - c) / sg.maxcost : qa;
-      qa = qa < mc ? qa : mc;
-      if (qa == 0 && n == 0) qa = 1;  // the host guarantees one record always fits
-      t = b;
-      q = (unsigned int)(qa < hn ? qa : hn);
-      break;
-    }
-    thr[s] = t;
-    quota[s] = q;
-  }
+  if (sg.take_all) return;
+  unsigned int *h = hist + (size_t)s * kBins;
+  u64 *hc = hcost + (size_t)s * kBins;
+  const SelLimits lim{sg.max_records, sg.max_children, ~0ull, 0, sg.maxcost};
+  block_select_threshold(h, hc, lim, &thr[s], &quota[s]);
   __syncthreads();
-  if (!sg.take_all)
-    for (int b = threadIdx.x; b < kBins; b += blockDim.x) {
-      hist[(size_t)s * kBins + b] = 0;
-      hcost[(size_t)s * kBins + b] = 0;
-    }
+  for (int b = threadIdx.x; b < kBins; b += blockDim.x) {
+    h[b] = 0;
+    hc[b] = 0;
+  }
 }
 
 __global__ void k_msel_part(const MSeg *segs, const MCfg *cfg, const QRes *res, const int *thr,
@@ -247,7 +233,7 @@ __global__ void k_msel_part(const MSeg *segs, const MCfg *cfg, const QRes *res, 
                             StepHdr *hdr, MRec *temp, unsigned int *temp_count, MCtr *ctr) {
   const uint32_t s = blockIdx.y;
   const MSeg sg = segs[s];
-  const long long theta = res[sg.qid].theta;
+  const long long theta = mprune_theta(cfg[sg.qid], res[sg.qid]);
   const MRec *h = cfg[sg.qid].hdr + sg.begin;
   const int t = sg.take_all ? -1 : thr[s];
   const unsigned int qt = sg.take_all ? 0 : quota[s];
@@ -307,7 +293,7 @@ __global__ void __launch_bounds__(64 * kMatchWaves)
   const uint32_t q = p.qid;
   const MPlan &P = plans[q];
   const MCfg cf = cfg[q];
-  const long long theta = res[q].theta;
+  const long long theta = mprune_theta(cf, res[q]);
   u64 st_children = 0, st_pruned_new = 0, st_leaves = 0, st_offered = 0, st_bytes = 0,
       st_cost = 0, st_maxcost = 0;
   long long st_maxb = LLONG_MIN;
@@ -635,6 +621,7 @@ void plan_pattern(const Graph &g, const nuri_pattern &pt, uint32_t k, MPlan &P) 
 // ------------------------------------------------------------------
 struct MLevel {
   uint32_t begin = 0, count = 0;
+  uint32_t depth = 1;  // matched pattern vertices of its records
   u64 cost = 0, maxcost = 0;
   long long max_bound = LLONG_MIN;
 };
@@ -654,6 +641,7 @@ struct MQHost {
   int plan = 0;
   uint32_t new_begin = 0;
   int seg = -1;
+  int lvl = -1;  // stack index of the level this step takes from
 };
 
 struct MSlotTopk {
@@ -769,6 +757,8 @@ struct MatchEngine {
       cfg[i].hdr = hdr.p + (u64)i * hdr_per_q;
       cfg[i].hdr_cap = (uint32_t)hdr_per_q;
       cfg[i].out_hdr = 0;
+      cfg[i].prio = o.priority;
+      cfg[i].pad = 0;
     }
     d_plans.alloc(g.pool, nq);
     h_plan.alloc(1);
@@ -911,6 +901,7 @@ struct MatchEngine {
       if (c.n_out) {
         MLevel Lv;
         Lv.begin = 0;
+        Lv.depth = 1;
         Lv.count = c.n_out;
         Lv.cost = c.out_cost;
         Lv.maxcost = c.out_max_cost;
@@ -957,10 +948,16 @@ struct MatchEngine {
         Q.done = true;
         continue;
       }
-      MLevel &Lv = Q.stack.back();
-      const u64 free_h = Q.hdr_cap - (u64)(Lv.begin + Lv.count);
-      const uint32_t depth = (uint32_t)Q.stack.size();  // records at this level match `depth` vertices
-      const bool to_leaves = depth + 1 == plans[i].q;   // children are complete matches
+      // the level to take from: the deepest, or (best-first) the one with the
+      // highest bound (ties: the deeper)
+      int li = (int)Q.stack.size() - 1;
+      if (o.priority == NURI_PRIORITY_BOUND)
+        for (int t2 = li - 1; t2 >= 0; --t2)
+          if (Q.stack[t2].count && Q.stack[t2].max_bound > Q.stack[li].max_bound) li = t2;
+      MLevel &Lv = Q.stack[li];
+      const MLevel &Top = Q.stack.back();
+      const u64 free_h = Q.hdr_cap - (u64)(Top.begin + Top.count);
+      const bool to_leaves = Lv.depth + 1 == plans[i].q;  // children are complete matches
       const u64 rec = std::max<u64>(1, Lv.maxcost);
       if ((to_leaves ? cand_cap : free_h) < rec) {
         fail(i, NURI_EBUDGET, "frontier budget exhausted");
@@ -984,7 +981,8 @@ struct MatchEngine {
       sg.maxcost = Lv.maxcost;
       sg.take_all = Lv.count <= sg.max_records && Lv.cost <= lim;
       sg.top = Lv.max_bound;
-      const long long floor_b = Q.theta == LLONG_MIN ? 0 : Q.theta;
+      const long long floor_b =
+          Q.theta == LLONG_MIN || o.priority == NURI_PRIORITY_NONE ? 0 : Q.theta;
       const long long span = Lv.max_bound - floor_b;
       uint32_t shift = 0;
       while (span > 0 && (span >> shift) >= kBins - 1) ++shift;
@@ -996,8 +994,9 @@ struct MatchEngine {
       }
       max_count = std::max(max_count, Lv.count);
       Q.seg = (int)nseg++;
+      Q.lvl = li;
       Q.plan = 1;
-      Q.new_begin = Lv.begin + Lv.count;
+      Q.new_begin = Top.begin + Top.count;
       batch_ub += (uint32_t)(sg.take_all ? Lv.count : sg.max_records);
       const u64 used = sg.take_all ? Lv.cost : lim;
       if (to_leaves) left_cand -= std::min(left_cand, used);
@@ -1060,10 +1059,11 @@ struct MatchEngine {
         fail(i, NURI_EBUDGET, "frontier overflow (internal accounting error)");
         continue;
       }
-      MLevel &Lv = Q.stack.back();
+      MLevel &Lv = Q.stack[Q.lvl];
       Lv.count = sseg()[Q.seg].take_all ? 0 : c.n_kept;
       if (c.n_out) {
         MLevel N;
+        N.depth = Lv.depth + 1;
         N.begin = Q.new_begin;
         N.count = c.n_out;
         N.cost = c.out_cost;
@@ -1190,6 +1190,7 @@ struct MatchEngine {
     st.expand_launches = Q.launches;
     st.expand_ns = Q.expand_ns;
     st.wall_ns = now_ns() - Q.t_admit;
+    st.ties_at_k = ties_at_k(res.score, Q.k);
     Q.active = false;
     Q.stack.clear();
     tk[i]->score.release();

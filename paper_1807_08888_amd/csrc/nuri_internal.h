@@ -64,11 +64,27 @@ struct DevBuf {
 // Device memory kept for reuse by later queries on the same graph: query
 // workspaces (frontier arenas, buffers) are taken from here and returned,
 // so repeated queries do not pay for hipMalloc/hipFree of large blocks.
+//
+// Fixed-region mode (fixed_base set): blocks are carved in order from the
+// caller's region [fixed_base, fixed_base + fixed_size), never returned one
+// by one, and no device memory is ever allocated; a request past the end
+// of the region fails with NURI_EBUDGET.
 struct MemPool {
   std::mutex mu;
   std::multimap<size_t, void *> free_blocks;  // size -> block
+  unsigned char *fixed_base = nullptr;
+  size_t fixed_size = 0, fixed_used = 0;
   ~MemPool() { trim(); }
+  static size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
   void *get(size_t bytes) {
+    if (fixed_base) {
+      const size_t at = align_up(fixed_used);
+      if (at + bytes > fixed_size)
+        throw Error{NURI_EBUDGET, "query needs more than the fixed scratch region (" +
+                                      std::to_string(fixed_size) + " bytes)"};
+      fixed_used = at + bytes;
+      return fixed_base + at;
+    }
     {
       std::lock_guard<std::mutex> lk(mu);
       auto it = free_blocks.lower_bound(bytes);
@@ -91,6 +107,7 @@ struct MemPool {
     return p;
   }
   void put(void *p, size_t bytes) {
+    if (fixed_base) return;
     std::lock_guard<std::mutex> lk(mu);
     free_blocks.emplace(bytes, p);
   }
@@ -221,11 +238,20 @@ struct Result {
   nuri_stats stats{};
 };
 
+// results of a full top-k whose score equals the k-th's; 0 when fewer than k
+inline uint64_t ties_at_k(const std::vector<int64_t> &score, uint32_t k) {
+  if (k == 0 || score.size() < k) return 0;
+  uint64_t t = 0;
+  for (size_t i = score.size(); i-- > 0 && score[i] == score[k - 1];) ++t;
+  return t;
+}
+
 struct QueryOpts {
   uint64_t frontier_budget = 8ull << 30;
   uint32_t batch_B = 0;
   uint32_t root_batch = 0;
   uint32_t bound = 0;  // 0 auto, 1 Carraghan-Pardalos only, 2 colour classes always
+  uint32_t priority = NURI_PRIORITY_DEPTH;
   uint64_t deadline_ns = 0;
   bool profile = false;
   hipStream_t stream = nullptr;
@@ -238,6 +264,10 @@ uint64_t now_ns();
 // together; results in the same order
 void run_cliques(Graph &g, const std::vector<uint32_t> &ks, const std::vector<int> &wfs,
                  const QueryOpts &o, std::vector<Result> &out);
+
+// one clique query with every device buffer carved from [base, base + bytes)
+void run_clique_fixed(Graph &g, uint32_t k, int kind, const QueryOpts &o, void *base, size_t bytes,
+                      Result &out);
 
 // Query slots for continuous batching: queries are admitted into free
 // slots between steps, every step serves all live slots, and finished

@@ -18,6 +18,7 @@ NURI_OK = 0
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EBUDGET", -4: "EDEVICE", -5: "ETIMEOUT"}
 SCORE_SIZE = 0
 SCORE_VERTEX_WEIGHT = 1
+PRIORITY_DEPTH, PRIORITY_BOUND, PRIORITY_PAPER, PRIORITY_NONE = 0, 1, 2, 3
 
 
 class NuriError(RuntimeError):
@@ -49,7 +50,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("frontier_budget_bytes", ctypes.c_uint64), ("batch_B", ctypes.c_uint32),
                 ("root_batch", ctypes.c_uint32), ("bound", ctypes.c_uint32),
                 ("deadline_ns", ctypes.c_uint64), ("profile", ctypes.c_uint32),
-                ("hip_stream", ctypes.c_void_p)]
+                ("hip_stream", ctypes.c_void_p), ("priority", ctypes.c_uint32)]
 
 
 class _Query(ctypes.Structure):
@@ -65,7 +66,7 @@ class _View(ctypes.Structure):
 
 STAT_FIELDS = ("steps", "popped", "expanded", "children", "pruned_at_pop", "pruned_at_creation",
                "leaves", "offered", "frontier_peak_bytes", "logical_bytes", "expand_launches",
-               "expand_ns", "wall_ns")
+               "expand_ns", "wall_ns", "ties_at_k")
 
 
 class _Stats(ctypes.Structure):
@@ -88,7 +89,7 @@ SIGNATURES = {
                                      ctypes.POINTER(_Opts), ctypes.c_uint32,
                                      ctypes.POINTER(_Opts)]),
     "nuri_result_view_get": (ctypes.c_int, [_VP, ctypes.POINTER(_View)]),
-    "nuri_result_get_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_Stats)]),
+    "nuri_result_stats": (ctypes.c_int, [_VP, ctypes.POINTER(_Stats)]),
     "nuri_free_result": (None, [_VP]),
     "nuri_server_create": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_uint32,
                                           ctypes.POINTER(_VP)]),
@@ -134,9 +135,9 @@ def _stream_handle(stream) -> Optional[int]:
 
 
 def _opts(frontier_budget_bytes=0, batch_B=0, root_batch=0, bound=0, deadline_ns=0,
-          profile=False, stream=None) -> _Opts:
+          profile=False, stream=None, priority=PRIORITY_DEPTH) -> _Opts:
     return _Opts(frontier_budget_bytes, batch_B, root_batch, bound, deadline_ns,
-                 int(bool(profile)), _stream_handle(stream))
+                 int(bool(profile)), _stream_handle(stream), priority)
 
 
 class Result:
@@ -154,7 +155,7 @@ class Result:
         self.items: List[Tuple[int, Tuple[int, ...]]] = [
             (scores[i], tuple(int(x) for x in ids[off[i]:off[i + 1]])) for i in range(n)]
         st = _Stats()
-        _check(lib().nuri_result_get_stats(handle, ctypes.byref(st)))
+        _check(lib().nuri_result_stats(handle, ctypes.byref(st)))
         self.stats: Dict[str, int] = {f: int(getattr(st, f)) for f in STAT_FIELDS}
         lib().nuri_free_result(handle)
         self._h = None

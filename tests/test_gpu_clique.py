@@ -177,16 +177,46 @@ def test_prefix_property(nuri):
         G.close()
 
 
-def test_small_budget_is_exact_or_fails_loudly(nuri):
+def test_smallest_budget_is_exact(nuri):
+    """The smallest budget the library accepts (64 MiB) holds this search's
+    frontier (its peak is reported and stays below it), so the result must be
+    exact, not EBUDGET."""
     g = synth.gnp(400, 0.05, 5)
-    _case("small frontier budget")
+    _case("smallest frontier budget")
     want, _ = oracle.topk_cliques(g, 20)
-    try:
-        got = _gpu(nuri, g, 20, frontier_budget_bytes=64 << 20)
-    except nuri.NuriError as e:
-        assert e.name == "EBUDGET"
-    else:
-        assert got.items == want
+    got = _gpu(nuri, g, 20, frontier_budget_bytes=64 << 20)
+    assert got.items == want
+    assert 0 < got.stats["frontier_peak_bytes"] <= 64 << 20
+
+
+def _ties(items, k):
+    return sum(1 for s, _ in items if s == items[-1][0]) if len(items) == k else 0
+
+
+@pytest.mark.parametrize("priority", [0, 1, 2, 3])
+def test_result_independent_of_priority(nuri, priority):
+    """Depth-first, best-first, the paper's (|V|, |P|) and no prioritization
+    or pruning at all (the paper's Nuri-NP) reach the same top-k, with the
+    same count of results tied with the k-th; without pruning the search
+    creates at least as many children as with it."""
+    _case(f"priority={priority}")
+    cases = [synth.gnp(40, 0.6, 3), synth.gnp(300, 0.06, 4),
+             synth.er_planted(n=600, avg_degree=12.0, n_cliques=6, lo=6, hi=10, master=8)]
+    for i, g in enumerate(cases):
+        synth.add_vertex_weights(g, 1, 9, master=i)
+        G = nuri.Graph.from_synth(g)
+        try:
+            for wf in (0, 1):
+                for k in (1, 25):
+                    want, _ = oracle.topk_cliques(g, k, weighted=bool(wf))
+                    got = nuri.topk_cliques(G, k, wf, priority=priority)
+                    assert got.items == want, (i, wf, k)
+                    assert got.stats["ties_at_k"] == _ties(want, k), (i, wf, k)
+                    if priority == 3:
+                        ref = nuri.topk_cliques(G, k, wf)
+                        assert got.stats["children"] >= ref.stats["children"]
+        finally:
+            G.close()
 
 
 def test_invalid_arguments(nuri):

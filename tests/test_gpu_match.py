@@ -188,3 +188,76 @@ def test_match_deadline_fails_loudly(nuri):
     assert e.value.name == "ETIMEOUT"
     want, _ = oracle.topk_match(g, p.labels, p.edges, 50)
     assert nuri.topk_match(G, p.labels, p.edges, 50).items == want
+
+
+# eight-vertex patterns (the largest query size; every bit of the pattern
+# masks and all eight matched slots of a record are used): a cycle, a star,
+# a labelled path, a cube-like graph, and two joined stars
+PATTERNS8 = [
+    ([0] * 8, [(i, (i + 1) % 8) for i in range(8)]),
+    ([0] * 8, [(0, i) for i in range(1, 8)]),
+    ([0, 1, 0, 1, 0, 1, 0, 1], [(i, i + 1) for i in range(7)]),
+    ([0, 0, 0, 0, 1, 1, 1, 1], [(0, 1), (1, 2), (2, 3), (3, 0), (4, 5), (5, 6), (6, 7), (7, 4),
+                                (0, 4), (1, 5), (2, 6), (3, 7)]),
+    ([1, 0, 0, 0, 1, 0, 0, 0], [(0, 1), (0, 2), (0, 3), (0, 4), (4, 5), (4, 6), (4, 7)]),
+]
+
+
+@pytest.mark.parametrize("pi", range(len(PATTERNS8)))
+def test_eight_vertex_patterns_vs_brute_force(nuri, pi):
+    labels, edges = PATTERNS8[pi]
+    n_labels = max(labels) + 1
+    g = _labelled(9, 0.92, 800 + pi, n_labels, 6)
+    # the pattern's own labels plus one more vertex, shuffled
+    g.vertex_label = np.array(list(labels) + [0], np.uint8)[
+        np.random.default_rng(pi).permutation(9)]
+    want, n_img = bruteforce.topk_matches(g, labels, edges, 10 ** 6)
+    assert n_img > 0
+    _case(f"eight-vertex pattern {pi}: {n_img} images")
+    G = nuri.Graph.from_synth(g)
+    try:
+        for k in (1, 5, 10 ** 6):
+            assert nuri.topk_match(G, labels, edges, k).items == want[:k], k
+    finally:
+        G.close()
+
+
+@pytest.mark.parametrize("idx", list(range(6)) + ["cycle", "double_star"])
+def test_eight_vertex_rmat_patterns_vs_oracle(nuri, idx):
+    """Eight-vertex patterns of the served mix's recipe (q = 8), plus two
+    with non-trivial automorphism groups (16 and 72), on R-MAT scale 14."""
+    if idx == "cycle":
+        labels, edges = PATTERNS8[0]
+    elif idx == "double_star":
+        labels = [2, 0, 0, 0, 2, 0, 0, 0]
+        edges = PATTERNS8[4][1]
+    else:
+        p = synth.random_pattern(2000 + idx, q_lo=8, q_hi=8)
+        labels, edges = p.labels, p.edges
+    g = _rmat14()
+    _case(f"rmat14 eight-vertex pattern {idx}: labels={labels}")
+    want, _ = oracle.topk_match(g, labels, edges, 50)
+    got = nuri.topk_match(_rmat14_dev(nuri), labels, edges, 50)
+    assert got.items == want
+
+
+@pytest.mark.parametrize("priority", [0, 1, 2, 3])
+def test_match_result_independent_of_priority(nuri, priority):
+    """Depth-first, best-first, the paper's order and no pruning (Nuri-NP)
+    give the same top-k; without pruning at least as many children."""
+    g = _labelled(300, 0.04, 77, 3, 50)
+    _case(f"matching priority={priority}")
+    G = nuri.Graph.from_synth(g)
+    try:
+        for labels, edges in PATTERNS[2:] + [([0, 1, 2, 0], [(0, 1), (1, 2), (2, 3), (3, 1)])]:
+            for k in (1, 20):
+                want, _ = oracle.topk_match(g, labels, edges, k, n_labels=3)
+                got = nuri.topk_match(G, labels, edges, k, priority=priority)
+                assert got.items == want, (labels, edges, k)
+                ties = sum(1 for s, _ in want if s == want[-1][0]) if len(want) == k else 0
+                assert got.stats["ties_at_k"] == ties
+                if priority == 3:
+                    ref = nuri.topk_match(G, labels, edges, k)
+                    assert got.stats["children"] >= ref.stats["children"]
+    finally:
+        G.close()
