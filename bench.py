@@ -249,6 +249,8 @@ def main() -> int:
     ap.add_argument("--batch-B", type=int, default=0,
                     help="records per step (with --root-batch: skip the autotuner)")
     ap.add_argument("--root-batch", type=int, default=0)
+    ap.add_argument("--chain-links", type=int, default=0,
+                    help="chained links per wavefront and launch (0 = the engine's default)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -300,6 +302,9 @@ def main() -> int:
                               rounds=1, stream=stream)
         _log(f"autotuned step sizes: {tuned}")
 
+    if args.chain_links:
+        tuned["chain_links"] = args.chain_links
+
     def one():
         return nuri.topk_cliques(G, args.k, nuri.SCORE_SIZE, profile=True, stream=stream, **tuned)
 
@@ -343,6 +348,7 @@ def main() -> int:
                    "max_clique": results[-1].items[0][0] if results[-1].items else 0,
                    "children_per_query": children // args.steps,
                    "batch_B": tuned["batch_B"], "root_batch": tuned["root_batch"],
+                   "chain_links": tuned.get("chain_links", 0),
                    "preprocess_ms": info["preprocess_ns"] / 1e6},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),

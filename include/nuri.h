@@ -147,6 +147,9 @@ typedef struct {
  *   priority               order in which partial subgraphs are expanded
  *                          (priority() of Table 1); one of NURI_PRIORITY_*.
  *                          Results never depend on it, only the work does.
+ *   chain_links            cliques: when an expanded record keeps a single
+ *                          child, the same wavefront expands that child at
+ *                          once, up to this many links per launch (0 = 32)
  */
 typedef struct {
   uint64_t frontier_budget_bytes;
@@ -157,6 +160,7 @@ typedef struct {
   uint32_t profile;
   void *hip_stream;
   uint32_t priority;
+  uint32_t chain_links;
 } nuri_opts;
 
 /*

@@ -37,6 +37,7 @@ QueryOpts resolve_opts(const Graph &g, const nuri_opts *o) {
   q.profile = o->profile != 0;
   if (o->priority > NURI_PRIORITY_NONE) throw Error{NURI_EINVAL, "priority must be 0..3"};
   q.priority = o->priority;
+  q.chain_links = o->chain_links;
   if (o->hip_stream) q.stream = (hipStream_t)o->hip_stream;
   if (q.frontier_budget < (64ull << 20))
     throw Error{NURI_EINVAL, "frontier_budget_bytes must be at least 64 MiB"};

@@ -391,10 +391,10 @@ __global__ void __launch_bounds__(256)
 // five bitmaps of wst words (parent P, parent V, parent X, carried child
 // V+P, carried child X) and a candidate list of lst u16 positions.
 constexpr int kExpandWaves = 4;
-// links one wavefront chains before it writes the held child to the
-// frontier instead: a launch lasts as long as its longest chain, and an
-// unbounded chain (hundreds of links down a near-clique) leaves most of the
-// device idle at the end of every launch
+// links one wavefront chains (by default) before it writes the held child
+// to the frontier instead: a launch lasts as long as its longest chain, and
+// an unbounded chain (hundreds of links down a near-clique) leaves most of
+// the device idle at the end of every launch
 constexpr uint32_t kMaxLinks = 32;
 
 __device__ inline void put_crec(CRec *hdr, u64 slot, long long score, long long bound, u64 woff,
@@ -412,7 +412,8 @@ __device__ inline void put_crec(CRec *hdr, u64 slot, long long score, long long 
 __global__ void __launch_bounds__(64 * kExpandWaves)
     k_expand(GView g, const CRec *__restrict__ batch, StepHdr *hdr, const QCfg *__restrict__ cfg,
              QStep *qs, QCtr *ctr, const QRes *__restrict__ res, LRec *leaves, u64 *leaf_words,
-             uint32_t leaf_cap, u64 leaf_word_cap, uint32_t wst, uint32_t lst, u64 chain_cap) {
+             uint32_t leaf_cap, u64 leaf_word_cap, uint32_t wst, uint32_t lst, u64 chain_cap,
+             uint32_t max_links) {
   extern __shared__ u64 s_dyn[];
   __shared__ long long s_cscore[kExpandWaves], s_cbound[kExpandWaves];
   __shared__ int s_cj[kExpandWaves];
@@ -918,7 +919,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     // exactly one kept child.  Expand it next, in this wave, if a k-th
     // score is known (without one nothing is cut, and thousands of chains
     // would each run to full depth unpruned), the chain is shorter than
-    // kMaxLinks and the leaf buffer has room for every leaf it can offer
+    // max_links and the leaf buffer has room for every leaf it can offer
     // (at most one per candidate); otherwise write it to the frontier like
     // any other child.
     {
@@ -926,7 +927,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       // credit is handed back when the chain ends
       const u64 m = s_ccnt[wv];
       int ok = 0;
-      if (lane == 0 && theta != LLONG_MIN && links < kMaxLinks) {
+      if (lane == 0 && theta != LLONG_MIN && links < max_links) {
         if (credit < m) {
           for (u64 want = 8 * m; want >= m && !ok; want = want == m ? 0 : m) {
             const u64 oc = atomicAdd(&hdr->chain_c, want);
@@ -1730,7 +1731,8 @@ struct Engine {
                          batch.p, dh, dcfg, dqs, d_ctr.p, d_res.p, leaves.p, leaf_words.p,
                          leaf_cap, leaf_word_cap, ex_wst, ex_lst,
                          std::min<u64>((u64)leaf_cap - plan_c - batch_ub,
-                                       (leaf_word_cap - plan_w) / ex_wst));
+                                       (leaf_word_cap - plan_w) / ex_wst),
+                         o.chain_links ? o.chain_links : kMaxLinks);
       NURI_HIP(hipGetLastError());
       if (o.profile) NURI_HIP(hipEventRecord(ev1, s));
     }

@@ -19,9 +19,11 @@ struct Cand {  // a result offered to the result set (its ids are stored apart)
 };
 
 struct StepHdr {  // global counters of one step (zeroed by the step upload)
-  unsigned int batch_count, leaf_count, cand_count, pad;
+  unsigned int batch_count, leaf_count, cand_count, big_next;
   u64 leaf_word_count;
-  u64 chain_c;  // leaf slots reserved by chained expansion (each with the widest row)
+  u64 chain_c;     // leaf slots reserved by chained expansion (each with the widest row)
+  u64 big_packed;  // matching: records with long candidate lists (high 32 bits) and
+                   // their extra chunks (low 32 bits)
 };
 
 struct QRes {  // per query result state

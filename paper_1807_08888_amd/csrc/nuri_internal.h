@@ -252,6 +252,7 @@ struct QueryOpts {
   uint32_t root_batch = 0;
   uint32_t bound = 0;  // 0 auto, 1 Carraghan-Pardalos only, 2 colour classes always
   uint32_t priority = NURI_PRIORITY_DEPTH;
+  uint32_t chain_links = 0;  // 0: the engine's default
   uint64_t deadline_ns = 0;
   bool profile = false;
   hipStream_t stream = nullptr;

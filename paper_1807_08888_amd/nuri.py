@@ -50,7 +50,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("frontier_budget_bytes", ctypes.c_uint64), ("batch_B", ctypes.c_uint32),
                 ("root_batch", ctypes.c_uint32), ("bound", ctypes.c_uint32),
                 ("deadline_ns", ctypes.c_uint64), ("profile", ctypes.c_uint32),
-                ("hip_stream", ctypes.c_void_p), ("priority", ctypes.c_uint32)]
+                ("hip_stream", ctypes.c_void_p), ("priority", ctypes.c_uint32),
+                ("chain_links", ctypes.c_uint32)]
 
 
 class _Query(ctypes.Structure):
@@ -135,9 +136,9 @@ def _stream_handle(stream) -> Optional[int]:
 
 
 def _opts(frontier_budget_bytes=0, batch_B=0, root_batch=0, bound=0, deadline_ns=0,
-          profile=False, stream=None, priority=PRIORITY_DEPTH) -> _Opts:
+          profile=False, stream=None, priority=PRIORITY_DEPTH, chain_links=0) -> _Opts:
     return _Opts(frontier_budget_bytes, batch_B, root_batch, bound, deadline_ns,
-                 int(bool(profile)), _stream_handle(stream), priority)
+                 int(bool(profile)), _stream_handle(stream), priority, chain_links)
 
 
 class Result:
