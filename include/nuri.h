@@ -277,6 +277,38 @@ typedef struct {
 int nuri_result_stats(const nuri_result *r, nuri_stats *s);
 void nuri_free_result(nuri_result *r);
 
+/*
+ * Allocation-free variant of nuri_topk_cliques, for callers that cannot
+ * allocate device memory: code under HIP stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same query and the same result
+ * as nuri_topk_cliques(g, k, wf, o), but the call allocates no device or
+ * page-locked host memory: every device buffer is carved from one static
+ * device array of NURI_NOALLOC_SCRATCH_BYTES that each GPU holds from the
+ * library's load until the process ends.  Outputs go to caller-owned host
+ * arrays:
+ *   score_out  [k]               scores, best first
+ *   len_out    [k]               number of vertices of each clique
+ *   ids_out    [k * ids_stride]  clique i's ascending vertex ids at
+ *                                ids_out[i * ids_stride ...]
+ *   ids_stride                   >= the graph's degeneracy + 1 (the largest
+ *                                possible clique)
+ *   count_out                    number of results written (min(k, #results))
+ *   stats_out                    work counters, or NULL
+ * Options as nuri_topk_cliques, except that profile is ignored and the
+ * frontier gets what the array has left after the other buffers (the
+ * frontier_budget_bytes option is not used).  Errors: NURI_EINVAL for k = 0,
+ * k > NURI_NOALLOC_MAX_K, a short ids_stride, or a graph whose fixed
+ * buffers (candidate ids and top-k, which grow with k and the degeneracy)
+ * leave less than 4 MiB of the array for the frontier; NURI_EBUDGET when
+ * the search needs more frontier than the array holds.  Calls on one GPU
+ * share its array and are serialised inside the process; calls from several
+ * processes on one GPU race.
+ */
+#define NURI_NOALLOC_SCRATCH_BYTES (128ull << 20)
+#define NURI_NOALLOC_MAX_K 1000u
+int nuri_topk_cliques_noalloc(nuri_graph *g, uint32_t k, nuri_weight_fn wf, const nuri_opts *o,
+                              int64_t *score_out, uint32_t *len_out, uint32_t *ids_out,
+                              uint32_t ids_stride, uint32_t *count_out, nuri_stats *stats_out);
 
 /*
  * Continuous-batching server on one resident graph.  Queries submitted

@@ -98,6 +98,10 @@ SIGNATURES = {
                                           ctypes.POINTER(ctypes.c_uint64)]),
     "nuri_server_poll": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(_VP)]),
     "nuri_server_destroy": (None, [_VP]),
+    "nuri_topk_cliques_noalloc": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_int,
+                                                 ctypes.POINTER(_Opts), _VP, _VP, _VP,
+                                                 ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                                 ctypes.POINTER(_Stats)]),
     "nuri_last_error": (ctypes.c_char_p, []),
 }
 
@@ -222,6 +226,24 @@ def topk_cliques(graph: Graph, k: int, weight_fn: int = SCORE_SIZE, **opts) -> R
     o = _opts(**opts)
     _check(lib().nuri_topk_cliques(graph._h, k, weight_fn, ctypes.byref(o), ctypes.byref(out)))
     return Result(out)
+
+
+def topk_cliques_noalloc(graph: Graph, k: int, weight_fn: int = SCORE_SIZE, **opts):
+    """Top-k maximal cliques through the allocation-free entry point
+    (nuri_topk_cliques_noalloc); returns (items, stats) like Result."""
+    stride = int(graph.info()["degeneracy"]) + 1
+    score = np.zeros(max(k, 1), np.int64)
+    lens = np.zeros(max(k, 1), np.uint32)
+    ids = np.zeros(max(k, 1) * stride, np.uint32)
+    count = ctypes.c_uint32(0)
+    st = _Stats()
+    o = _opts(**opts)
+    _check(lib().nuri_topk_cliques_noalloc(graph._h, k, weight_fn, ctypes.byref(o),
+                                           score.ctypes.data, lens.ctypes.data, ids.ctypes.data,
+                                           stride, ctypes.byref(count), ctypes.byref(st)))
+    items = [(int(score[i]), tuple(int(x) for x in ids[i * stride:i * stride + int(lens[i])]))
+             for i in range(count.value)]
+    return items, {f: int(getattr(st, f)) for f in STAT_FIELDS}
 
 
 def _pattern(labels: Sequence[int], edges: Sequence[Tuple[int, int]]):
