@@ -128,10 +128,16 @@ typedef struct {
 /*
  * Tuning and limits; pass NULL for defaults.  None of these changes a
  * result, only speed, memory and whether the call may fail.
- *   frontier_budget_bytes  device bytes for the frontier of partial
- *                          subgraphs (0 = 40% of the free device memory,
- *                          at most 64 GiB); NURI_EBUDGET if the search
- *                          cannot proceed within it
+ *   frontier_budget_bytes  device bytes for the frontiers of partial
+ *                          subgraphs of all live queries (0 = 40% of the
+ *                          free device memory, at most 64 GiB); a batch
+ *                          runs only as many queries at once as have an
+ *                          arena of a useful size (64 KiB or more, and
+ *                          room for the children of any one record) and
+ *                          starts the others as those finish; the step
+ *                          buffers (selected records, leaves, candidates)
+ *                          come on top.  NURI_EBUDGET if a search cannot
+ *                          proceed within its arena
  *   batch_B                records expanded per step (0 = automatic)
  *   root_batch             unit subgraphs expanded per step (0 = automatic)
  *   bound                  clique bound used to skip children before they
@@ -266,13 +272,20 @@ typedef struct {
   uint64_t leaves;             /* children with nothing left to add */
   uint64_t offered;            /* results offered to the result set */
   uint64_t frontier_peak_bytes;
-  uint64_t logical_bytes;      /* algorithmic bytes read + written by expansion */
+  uint64_t logical_bytes;      /* algorithmic bytes of the frontier read + written by
+                                  expansion: records taken and written, leaves (and,
+                                  for matching, the graph's candidate lists) */
   uint64_t expand_launches;    /* expansion kernel launches */
   uint64_t expand_ns;          /* summed expansion kernel time (profile = 1) */
   uint64_t wall_ns;            /* wall time of the call */
   uint64_t ties_at_k;          /* results returned whose score equals the k-th's (0 when
                                   fewer than k); Algorithm 1 would keep every further
                                   result tied with the k-th too, this engine returns k */
+  uint64_t restarts;           /* served queries: times the query outgrew its frontier
+                                  arena and was started again with a larger one */
+  uint64_t onchip_bytes;       /* cliques: local adjacency rows read by expansion (a
+                                  working set that stays in the L2 caches), kept apart
+                                  from logical_bytes */
 } nuri_stats;
 int nuri_result_stats(const nuri_result *r, nuri_stats *s);
 void nuri_free_result(nuri_result *r);
@@ -312,10 +325,16 @@ int nuri_topk_cliques_noalloc(nuri_graph *g, uint32_t k, nuri_weight_fn wf, cons
 
 /*
  * Continuous-batching server on one resident graph.  Queries submitted
- * while others run are admitted when a slot and frontier memory are
- * free; admitted queries share every expansion launch.
+ * while others run are admitted, in arrival order, when a slot of their
+ * kind is free and their frontier arena fits in what the budget has left
+ * (a query waiting for memory is not overtaken); admitted queries share
+ * every expansion launch.  A query starts with frontier_budget_bytes / (2 *
+ * max_slots) bytes of arena (at least what one record's children need); one
+ * that outgrows it is restarted with twice the arena, up to the whole
+ * budget, and only then fails with NURI_EBUDGET.
  *   frontier_budget_bytes  total device bytes for all live frontiers
- *   max_slots              queries live at once
+ *                          (0 = the default of nuri_opts)
+ *   max_slots              queries of each kind live at once
  * nuri_server_submit copies the query and returns a ticket at once
  * (NURI_EINVAL for a malformed query, or a matching query on a graph
  * without vertex labels).

@@ -106,6 +106,7 @@ struct QStep {  // per query, this step's counters (zeroed by the step upload)
 
 struct QCtr {  // per query, cumulative counters
   u64 popped, expanded, children, pruned_pop, pruned_new, leaves, offered, logical_bytes;
+  u64 onchip_bytes;  // adjacency rows read (cache-resident), apart from logical_bytes
 };
 
 struct GView {
@@ -420,6 +421,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   __shared__ uint32_t s_ccnt[kExpandWaves];
   __shared__ u64 s_cost[kExpandWaves], s_maxcc[kExpandWaves];
   __shared__ long long s_maxb[kExpandWaves];
+  __shared__ u64 s_st[kExpandWaves][8];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   u64 *s_pw = s_dyn + (u64)wv * 5 * wst;
   u64 *s_vw = s_pw + wst;
@@ -434,11 +436,22 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   const QCfg cf = cfg[q];
   const long long theta = prune_theta(cf, res[q]);
   const bool weighted = cf.weighted != 0;
-  // wave-uniform counters; the per-child ones of written children are
-  // gathered in LDS by the lanes that write them
-  u64 st_popped = 0, st_pruned_pop = 0, st_expanded = 0, st_children = 0, st_pruned_new = 0,
-      st_leaves = 0, st_bytes = 0;
+  // wave-uniform work counters, kept in LDS by lane 0 rather than in
+  // registers (they live across the whole kernel, and every register counts
+  // against occupancy); the per-child ones of written children are gathered
+  // in LDS by the lanes that write them
+  enum {
+    ST_POPPED, ST_PRUNED_POP, ST_EXPANDED, ST_CHILDREN, ST_PRUNED_NEW, ST_LEAVES,
+    ST_BYTES,   // frontier records and leaves read and written
+    ST_ONCHIP,  // local adjacency rows read (L2-resident)
+    ST_N
+  };
+  u64 *st = s_st[wv];
+  auto stat = [&](int i, u64 v) {
+    if (lane == 0) st[i] += v;
+  };
   if (lane == 0) {
+    for (int i = 0; i < ST_N; ++i) st[i] = 0;
     s_cost[wv] = 0;
     s_maxcc[wv] = 0;
     s_maxb[wv] = LLONG_MIN;
@@ -472,18 +485,18 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       atomicMax(&s_maxcc[wv], cc);
       atomicMax(&s_maxb[wv], s_cbound[wv]);
     }
-    st_bytes += 32 + 16ull * W;
+    stat(ST_BYTES, 32 + 16ull * W);
   };
 
   for (;;) {
-    ++st_popped;
+    stat(ST_POPPED, 1);
     if (p.bound < theta) {
-      st_pruned_pop = 1;
+      stat(ST_PRUNED_POP, 1);
       break;
     }
     if (d == 0) {
       // a unit subgraph with no later neighbour: itself a leaf
-      st_leaves = 1;
+      stat(ST_LEAVES, 1);
       if (p.score >= theta && lane == 0) {
         unsigned int slot = atomicAdd(&hdr->leaf_count, 1u);
         if (slot < leaf_cap) {
@@ -661,9 +674,9 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         s_list[o++] = (uint16_t)(lane * 64 + __ffsll((long long)t) - 1);
     }
     wave_sync();
-    if (last >= 0) st_bytes += 32 + 16ull * W;  // the parent record
-    if (nchild) st_expanded += 1;
-    st_children += nchild;
+    if (last >= 0) stat(ST_BYTES, 32 + 16ull * W);  // the parent record
+    if (nchild) stat(ST_EXPANDED, 1);
+    stat(ST_CHILDREN, nchild);
     if (whole) {
       // Every candidate's row at once (the loads are independent): for each
       // candidate the number of other candidates it is not adjacent to.
@@ -673,6 +686,35 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       // adjacent to all of P extends V + P, which is then not maximal.
       u64 xacc = (wi < (int)W) ? s_xw[wi] : 0ull;
       uint32_t zc = 0, msum = 0, zlo = 0xFFFFFFFFu, zhi = 0, mbest = 0, mpos = 0;
+      if (W >= 2) {
+        // one candidate per lane, its W words in sequence (independent
+        // loads): 64 candidates per round and no group reductions
+        for (uint32_t b0 = 0; b0 < nchild; b0 += 64) {
+          const uint32_t ci = b0 + lane;
+          if (ci < nchild) {
+            const uint32_t j = s_list[ci];
+            const uint32_t jw = j >> 6;
+            const u64 jb = 1ull << (j & 63);
+            const u64 *rj = rows + (u64)j * W;
+            uint32_t miss = 0;
+#pragma unroll 4
+            for (uint32_t w = 0; w < W; ++w)
+              miss += __popcll(s_pw[w] & ~(w == jw ? jb : 0ull) & ~rj[w]);
+            if (miss) {
+              ++zc;
+              msum += miss;
+              zlo = j < zlo ? j : zlo;
+              zhi = j > zhi ? j : zhi;
+              if (miss > mbest) {
+                mbest = miss;
+                mpos = j;
+              }
+            }
+          }
+          if (wslack == 0 && __ballot(zc != 0)) break;  // P is not a clique
+        }
+        xacc = 0;  // X is tested below, only if P is a clique
+      } else
       for (uint32_t b0 = 0; b0 < nchild; b0 += 8 * per) {
         for (uint32_t u = 0; u < 8; ++u) {
           const uint32_t ci = b0 + u * per + lane / G;
@@ -699,7 +741,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         }
         if (wslack == 0 && __ballot(zc != 0)) break;  // P is not a clique
       }
-      st_bytes += 8ull * W * nchild;
+      stat(ST_ONCHIP, 8ull * W * nchild);
       zc = (uint32_t)wave_sum((u64)zc);
       msum = (uint32_t)wave_sum((u64)msum);
       zlo = wave_min_u32(zlo);
@@ -712,7 +754,35 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       // AND the X accumulators of the lane groups holding the same word
       for (uint32_t o2 = G; o2 < 64; o2 <<= 1) xacc &= __shfl_xor(xacc, o2, 64);
       int drop0 = -2, drop1 = -2;  // dropped position per leaf; -1 none, -2 no leaf
-      if (zc == 0) {
+      if (zc == 0 && W >= 2) {
+        // P is a clique: V + P is maximal unless a vertex of X is adjacent
+        // to all of P.  X's positions go to the candidate list (no longer
+        // needed), one per lane, each tested against P word by word.
+        wave_sync();
+        const u64 xw = (lane < (int)W) ? s_xw[lane] : 0ull;
+        const uint32_t xc = __popcll(xw);
+        const uint32_t xo = wave_excl_scan(xc, lane);
+        const uint32_t nx = __shfl(xo + xc, 63, 64);
+        {
+          uint32_t o = xo;
+          for (u64 t = xw; t; t &= t - 1) s_list[o++] = (uint16_t)(lane * 64 + __ffsll((long long)t) - 1);
+        }
+        wave_sync();
+        bool ext = false;
+        for (uint32_t b0 = 0; b0 < nx && !ext; b0 += 64) {
+          bool all = false;
+          if (b0 + lane < nx) {
+            const u64 *rx = rows + (u64)s_list[b0 + lane] * W;
+            u64 out = 0;
+#pragma unroll 4
+            for (uint32_t w = 0; w < W; ++w) out |= s_pw[w] & ~rx[w];
+            all = out == 0;
+          }
+          ext = __ballot(all) != 0;
+        }
+        stat(ST_ONCHIP, 8ull * W * nx);
+        if (!ext) drop0 = -1;
+      } else if (zc == 0) {
         if (!__ballot(wi < (int)W && xacc != 0ull)) drop0 = -1;
       } else if (wslack >= 1 && msum / 2 == mbest) {
         if (mbest == 1) {
@@ -731,8 +801,8 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         }
       }
       const uint32_t nl = (drop0 != -2) + (drop1 != -2);
-      st_pruned_new += nchild - (nl ? 1 : 0);
-      st_leaves += nl;
+      stat(ST_PRUNED_NEW, nchild - (nl ? 1 : 0));
+      stat(ST_LEAVES, nl);
       n_eff = 0;  // no child is built one by one
       if (nl) {
         const long long tot = weighted ? wP : (long long)nchild;
@@ -759,13 +829,73 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
               leaves[l0 + t] = l;
             }
           }
-          st_bytes += (24 + 8ull * W) * nl;
+          stat(ST_BYTES, (24 + 8ull * W) * nl);
         } else if (lane == 0) {
           atomicAdd(&qs[q].overflow, 1u);
         }
       }
     } else {
-      st_pruned_new += nchild - n_eff;
+      stat(ST_PRUNED_NEW, nchild - n_eff);
+    }
+    // Screening, for records with more children than one round of lane
+    // groups builds: one child per lane, its W words in sequence
+    // (independent loads, 64 children per round, no group reductions),
+    // gives |P'| -- with vertex weights an upper bound of w(P'): the bits
+    // of each word times the heaviest candidate in that word -- and the
+    // first vertex of X' with the test whether it is adjacent to all of P'.
+    // Children that this bound or the witness rule out are counted as
+    // pruned here; the others, in order, replace the list and are built by
+    // the lane groups below, which repeat the exact test.
+    if (!whole && n_eff > per && W >= 2) {
+      int32_t wmx = 0;  // lane w: heaviest candidate of word w
+      if (weighted)
+        for (uint32_t w = 0; w < W; ++w) {
+          const u64 word = readlane64(pw, (int)w);
+          const uint32_t x = ((word >> lane) & 1ull) ? (uint32_t)wl[w * 64 + lane] : 0u;
+          const uint32_t m = (uint32_t)wave_max_u64((u64)x);
+          if (lane == (int)w) wmx = (int32_t)m;
+        }
+      uint32_t kept = 0;
+      for (uint32_t b0 = 0; b0 < n_eff; b0 += 64) {
+        const uint32_t ci = b0 + lane;
+        const bool valid = ci < n_eff;
+        const uint32_t j = valid ? s_list[ci] : 0;
+        const u64 *rj = rows + (u64)j * W;
+        uint32_t cnt = 0;
+        long long wub = 0;
+        int x0 = -1;
+        if (valid) {
+#pragma unroll 1
+          for (uint32_t w = 0; w < W; ++w) {
+            const u64 row = rj[w];
+            const u64 pv = s_pw[w];
+            const u64 a = pv & row & gt_mask((int)w, (int)j);
+            const uint32_t c = __popcll(a);
+            cnt += c;
+            if (weighted) wub += (long long)c * __builtin_amdgcn_readlane(wmx, (int)w);
+            const u64 xc = (s_xw[w] | (pv & ~gt_mask((int)w, (int)j - 1))) & row;
+            if (x0 < 0 && xc) x0 = (int)w * 64 + __ffsll((long long)xc) - 1;
+          }
+        }
+        const long long score2 = p.score + (weighted ? (long long)wl[j] : 1ll);
+        bool pass = valid && score2 + (weighted ? wub : (long long)cnt) >= theta;
+        if (pass && x0 >= 0) {
+          const u64 *rx = rows + (u64)x0 * W;
+          u64 out = 0;
+#pragma unroll 1
+          for (uint32_t w = 0; w < W; ++w)
+            out |= s_pw[w] & rj[w] & gt_mask((int)w, (int)j) & ~rx[w];
+          pass = out != 0;  // covered when x0 is adjacent to all of P'
+        }
+        const u64 pm = __ballot(pass);
+        stat(ST_PRUNED_NEW, __popcll(__ballot(valid && !pass)));
+        stat(ST_ONCHIP, 8ull * W * (__popcll(__ballot(valid)) + __popcll(__ballot(valid && x0 >= 0))));
+        wave_sync();  // every lane has read its entry before the list is rewritten
+        if (pass) s_list[kept + __popcll(pm & ((1ull << lane) - 1ull))] = (uint16_t)j;
+        kept += __popcll(pm);
+        wave_sync();
+      }
+      n_eff = kept;
     }
     // kept children: the first is held back (in s_cv/s_cx) in case it
     // stays the only one; `spilled` once it has been written out
@@ -818,10 +948,10 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       const u64 lm = __ballot(leader);
       const u64 km = __ballot(leader && keep);
       const u64 fm = __ballot(leader && offer);
-      st_pruned_new += __popcll(__ballot(leader && prune));
-      st_leaves += __popcll(__ballot(leader && leaf));
-      st_bytes += 8ull * W * __popcll(lm);  // adjacency rows read
-      st_bytes += 8ull * W * __popcll(__ballot(wi == 0 && valid && x0 != 0x7FFFFFFF));  // witness
+      stat(ST_PRUNED_NEW, __popcll(__ballot(leader && prune)));
+      stat(ST_LEAVES, __popcll(__ballot(leader && leaf)));
+      stat(ST_ONCHIP, 8ull * W * __popcll(lm));  // adjacency rows read
+      stat(ST_ONCHIP, 8ull * W * __popcll(__ballot(wi == 0 && valid && x0 != 0x7FFFFFFF)));  // witness
       const u64 jbit = (wi == (int)(j >> 6)) ? (1ull << (j & 63)) : 0ull;
       if (km) {
         if (!held && __popcll(km) == 1) {
@@ -877,7 +1007,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
                 atomicMax(&s_maxb[wv], bound2);
               }
             }
-            st_bytes += (32 + 16ull * W) * __popcll(km);
+            stat(ST_BYTES, (32 + 16ull * W) * __popcll(km));
           }
           held = true;
           spilled = true;
@@ -885,7 +1015,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       }
       if (fm) {
         const uint32_t nf = __popcll(fm);
-        st_bytes += (24 + 8ull * W) * nf;
+        stat(ST_BYTES, (24 + 8ull * W) * nf);
         unsigned int l0 = 0;
         u64 w0 = 0;
         if (lane == 0) {
@@ -971,13 +1101,14 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   wave_sync();
   if (lane == 0) {
     QCtr &C = ctr[q];
-    atomicAdd(&C.popped, st_popped);
-    if (st_pruned_pop) atomicAdd(&C.pruned_pop, st_pruned_pop);
-    if (st_expanded) atomicAdd(&C.expanded, st_expanded);
-    if (st_children) atomicAdd(&C.children, st_children);
-    if (st_pruned_new) atomicAdd(&C.pruned_new, st_pruned_new);
-    if (st_leaves) atomicAdd(&C.leaves, st_leaves);
-    if (st_bytes) atomicAdd(&C.logical_bytes, st_bytes);
+    atomicAdd(&C.popped, st[ST_POPPED]);
+    if (st[ST_PRUNED_POP]) atomicAdd(&C.pruned_pop, st[ST_PRUNED_POP]);
+    if (st[ST_EXPANDED]) atomicAdd(&C.expanded, st[ST_EXPANDED]);
+    if (st[ST_CHILDREN]) atomicAdd(&C.children, st[ST_CHILDREN]);
+    if (st[ST_PRUNED_NEW]) atomicAdd(&C.pruned_new, st[ST_PRUNED_NEW]);
+    if (st[ST_LEAVES]) atomicAdd(&C.leaves, st[ST_LEAVES]);
+    if (st[ST_BYTES]) atomicAdd(&C.logical_bytes, st[ST_BYTES]);
+    if (st[ST_ONCHIP]) atomicAdd(&C.onchip_bytes, st[ST_ONCHIP]);
     QStep &S = qs[q];
     const u64 cost = s_cost[wv];
     if (cost) {
@@ -1193,10 +1324,14 @@ struct QHost {
   uint32_t seg0 = 0, nsegs = 0;  // this step's segments: seg0 .. seg0 + nsegs - 1
 };
 
-// per-slot top-k buffers (two of each, switched by every merge)
+// per-slot top-k buffers (two of each, switched by every merge) and the
+// slot's frontier arena (record headers and bitmap words), all taken when a
+// query is admitted and returned when it is harvested
 struct SlotTopk {
   PoolBuf<long long> score;
   PoolBuf<unsigned int> len, ids;
+  PoolBuf<CRec> hdr;
+  PoolBuf<u64> words;
 };
 
 // Layout of the per-step block that one host-to-device copy uploads and
@@ -1243,8 +1378,7 @@ struct Engine {
   std::vector<QCfg> cfg;
   std::vector<std::unique_ptr<SlotTopk>> tk;
 
-  PoolBuf<CRec> hdr;
-  PoolBuf<u64> words;
+  u64 arena_bytes = 0;  // frontier arena of a slot unless admit() is given one
   PoolBuf<QCtr> d_ctr;
   PoolBuf<QRes> d_res;
   PoolBuf<uint32_t> d_k;
@@ -1382,25 +1516,11 @@ struct Engine {
                                      std::to_string(have) + " bytes"};
       budget = have - other;
     }
-    const u64 per_q = budget / nq;
-    // fixed region: a quarter headers, a quarter their selection copy, half words
-    u64 hdr_per_q = std::max<u64>(1024, per_q / (fixed ? 4 : 3) / sizeof(CRec));
-    const u64 hdr_bytes = hdr_per_q * sizeof(CRec) * (fixed ? 2 : 1);
-    const u64 word_per_q = std::max<u64>(4096, per_q > hdr_bytes ? (per_q - hdr_bytes) / 8 : 0);
-    hdr_per_q = std::min<u64>(hdr_per_q, 0x7FFFFFFFull);
-    hdr.alloc(*mp, hdr_per_q * nq);
-    words.alloc(*mp, word_per_q * nq);
+    arena_bytes = budget / nq;
     h_res.alloc(nq);
     h_ctr.alloc(nq);
     h_k.alloc(nq);
     for (uint32_t i = 0; i < nq; ++i) {
-      qh[i].hdr_cap = (uint32_t)hdr_per_q;
-      qh[i].word_cap = word_per_q;
-      QCfg &c = cfg[i];
-      c.hdr = hdr.p + (u64)i * hdr_per_q;
-      c.words = words.p + (u64)i * word_per_q;
-      c.word_cap = word_per_q;
-      c.hdr_cap = (uint32_t)hdr_per_q;
       QRes &R = h_res.p[i];
       memset(&R, 0, sizeof(R));
       R.theta = LLONG_MIN;
@@ -1424,7 +1544,7 @@ struct Engine {
       leaf_word_cap = 2 * step_words;
     }
     batch.alloc(*mp, batch_cap);
-    if (fixed) temp.alloc(*mp, hdr_per_q * nq);  // every level fits; never grown
+    if (fixed) temp.alloc(*mp, arena_caps(arena_bytes).first);  // every level fits
     expand_lds = (size_t)kExpandWaves * (5ull * 8 * ex_wst + 2ull * ex_lst);
     leaves.alloc(*mp, leaf_cap);
     leaf_words.alloc(*mp, leaf_word_cap);
@@ -1445,18 +1565,44 @@ struct Engine {
     }
   }
 
-  // start query (k, score kind) in a free slot
-  void admit(uint32_t i, uint32_t k, int kind) {
+  // (headers, words) of an arena of `bytes`: a third headers, the rest
+  // words; in a fixed region a quarter headers, a quarter their selection
+  // copy (temp) and half words
+  std::pair<u64, u64> arena_caps(u64 bytes) const {
+    const bool fixed = mp->fixed_base != nullptr;
+    u64 h = std::max<u64>(1024, bytes / (fixed ? 4 : 3) / sizeof(CRec));
+    h = std::min<u64>(h, 0x7FFFFFFFull);
+    const u64 hb = h * sizeof(CRec) * (fixed ? 2 : 1);
+    const u64 w = std::max<u64>(4096, bytes > hb ? (bytes - hb) / 8 : 0);
+    return {h, w};
+  }
+  // bytes of the smallest arena that holds the children of any one record
+  u64 min_arena_bytes() const {
+    const u64 W = (g.degeneracy + 63) / 64;
+    return std::max<u64>(64ull << 10, 4ull * g.degeneracy * (sizeof(CRec) + 16 * W));
+  }
+
+  // start query (k, score kind) in a free slot with a frontier arena of
+  // `bytes` (0: the slot default)
+  void admit(uint32_t i, uint32_t k, int kind, u64 bytes = 0) {
     QHost &Q = qh[i];
     Q = QHost{};
     Q.active = true;
     Q.done = false;
     Q.k = k;
     Q.kind = kind;
-    Q.hdr_cap = cfg[i].hdr_cap;
-    Q.word_cap = cfg[i].word_cap;
+    const auto caps = arena_caps(bytes ? bytes : arena_bytes);
+    SlotTopk &A = *tk[i];
+    A.hdr.alloc(*mp, caps.first);
+    A.words.alloc(*mp, caps.second);
+    Q.hdr_cap = (uint32_t)caps.first;
+    Q.word_cap = caps.second;
     Q.t_admit = now_ns();
     QCfg &c = cfg[i];
+    c.hdr = A.hdr.p;
+    c.words = A.words.p;
+    c.hdr_cap = (uint32_t)caps.first;
+    c.word_cap = caps.second;
     c.weighted = kind;
     c.k = k;
     // automatic: colour classes unless the densest region is a near-clique
@@ -1510,10 +1656,7 @@ struct Engine {
     // and at most an eighth of its own arena: a step that fills the arena
     // leaves the deeper levels so little room that the search then crawls
     // forward a few records per step
-    const u64 share_c = std::max<u64>(std::min<u64>(step_children / live, cfg[0].hdr_cap / 8),
-                                      max_rec_children());
-    const u64 share_w = std::max<u64>(std::min<u64>(step_words / live, cfg[0].word_cap / 8),
-                                      max_rec_words());
+    const u64 step_share_c = step_children / live, step_share_w = step_words / live;
     u64 left_c = step_children, left_w = step_words;
     bool any = false;
     for (uint32_t i = 0; i < nq; ++i) {
@@ -1530,6 +1673,10 @@ struct Engine {
         continue;
       }
       while (!Q.stack.empty() && Q.stack.back().count == 0) Q.stack.pop_back();
+      const u64 share_c =
+          std::max<u64>(std::min<u64>(step_share_c, Q.hdr_cap / 8), max_rec_children());
+      const u64 share_w =
+          std::max<u64>(std::min<u64>(step_share_w, Q.word_cap / 8), max_rec_words());
       const u64 cap_c = std::min(left_c, share_c), cap_w = std::min(left_w, share_w);
       const bool prune = o.priority != NURI_PRIORITY_NONE;
       // unit subgraphs left: the next roots in bound order with bound >= theta
@@ -1910,6 +2057,7 @@ struct Engine {
     st.offered = c.offered;
     st.frontier_peak_bytes = Q.peak_bytes;
     st.logical_bytes = c.logical_bytes;
+    st.onchip_bytes = c.onchip_bytes;
     st.expand_launches = Q.launches;
     st.expand_ns = Q.expand_ns;
     st.wall_ns = now_ns() - Q.t_admit;
@@ -1919,6 +2067,10 @@ struct Engine {
     tk[i]->score.release();
     tk[i]->len.release();
     tk[i]->ids.release();
+    tk[i]->hdr.release();
+    tk[i]->words.release();
+    cfg[i].hdr = nullptr;
+    cfg[i].words = nullptr;
   }
 };
 
@@ -1936,13 +2088,38 @@ void run_cliques(Graph &g, const std::vector<uint32_t> &ks, const std::vector<in
   if (ks.empty()) return;
   if (ks.size() > 65535) throw Error{NURI_EINVAL, "at most 65535 queries per batch"};
   for (size_t i = 0; i < ks.size(); ++i) check_clique_query(g, ks[i], kinds[i]);
+  // as many queries live at once as the frontier budget holds arenas of at
+  // least the smallest useful size; the others wait for a slot and run
+  // when one is harvested
+  const uint32_t nq = (uint32_t)ks.size();
   Engine e(g, o);
-  e.setup((uint32_t)ks.size());
-  for (uint32_t i = 0; i < ks.size(); ++i) e.admit(i, ks[i], kinds[i]);
-  while (e.step_all()) {
+  const u64 per = std::max<u64>(e.min_arena_bytes(), o.frontier_budget / nq);
+  const uint32_t slots = (uint32_t)std::max<u64>(1, std::min<u64>(nq, o.frontier_budget / per));
+  e.setup(slots);
+  e.arena_bytes = o.frontier_budget / slots;
+  std::vector<uint32_t> slot_query(slots, UINT32_MAX);
+  uint32_t next = 0;
+  out.resize(nq);
+  auto fill = [&] {
+    for (uint32_t s = 0; s < slots && next < nq; ++s)
+      if (e.slot_free(s)) {
+        e.admit(s, ks[next], kinds[next]);
+        slot_query[s] = next++;
+      }
+  };
+  fill();
+  for (;;) {
+    const bool more = e.step_all();
+    bool freed = false;
+    for (uint32_t s = 0; s < slots; ++s)
+      if (e.finished(s)) {
+        e.harvest(s, out[slot_query[s]]);
+        slot_query[s] = UINT32_MAX;
+        freed = true;
+      }
+    if (freed) fill();
+    if (!more && !e.any_live() && next >= nq) break;
   }
-  out.resize(ks.size());
-  for (uint32_t i = 0; i < ks.size(); ++i) e.harvest(i, out[i]);
 }
 
 // One clique query whose device buffers all come from the caller's fixed
@@ -1986,10 +2163,11 @@ uint32_t CliqueSlots::slots() const { return impl->e.nq; }
 bool CliqueSlots::free(uint32_t i) const { return impl->e.slot_free(i); }
 bool CliqueSlots::finished(uint32_t i) const { return impl->e.finished(i); }
 bool CliqueSlots::live() const { return impl->e.any_live(); }
-void CliqueSlots::admit(uint32_t i, uint32_t k, int kind) {
+void CliqueSlots::admit(uint32_t i, uint32_t k, int kind, uint64_t bytes) {
   check_clique_query(impl->e.g, k, kind);
-  impl->e.admit(i, k, kind);
+  impl->e.admit(i, k, kind, bytes);
 }
+uint64_t CliqueSlots::min_arena_bytes() const { return impl->e.min_arena_bytes(); }
 bool CliqueSlots::step() { return impl->e.step_all(); }
 void CliqueSlots::harvest(uint32_t i, Result &r) { impl->e.harvest(i, r); }
 

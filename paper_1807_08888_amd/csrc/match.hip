@@ -280,12 +280,202 @@ __global__ void k_mcopy_back(const MSeg *segs, const MCfg *cfg, const MRec *temp
 // label segment among the matched neighbours of the next pattern vertex a
 // (coalesced reads of ids and weights), and test each candidate against
 // the other matched neighbours by binary search in their label-a segments.
+//
+// A hub's label segment can hold tens of thousands of ids, and one
+// wavefront walking it alone would keep a launch running long after the
+// rest of the device is idle.  So a wavefront walks at most kMatchChunk
+// candidates of its record; the rest of a longer segment is cut into
+// chunks of kMatchChunk that k_match_expand_big shares out between all its
+// wavefronts.
 constexpr int kMatchWaves = 4;
+constexpr uint32_t kMatchChunk = 2048;
+constexpr uint32_t kBigBlocks = 1024;
+
+// what a wavefront needs to walk candidates of one record
+struct MWork {
+  uint32_t a, la, anchor, alen;
+  u64 base;          // first entry of the anchor's label-la segment
+  long long bound0;  // record bound without the terms the candidate replaces
+  bool last;         // children are complete matches
+};
+
+__device__ inline MWork match_work(const MView &m, const MPlan &P, const MRec &p) {
+  MWork w;
+  w.a = P.order[p.depth];
+  w.la = P.label[w.a];
+  // anchor: the matched neighbour of a with the shortest label-la segment
+  w.anchor = QM;
+  w.alen = 0xFFFFFFFFu;
+  for (uint32_t i = 0; i < p.depth; ++i) {
+    const uint32_t b = P.order[i];
+    if (P.nbr[w.a] >> b & 1) {
+      uint32_t s = seg_len(m, p.mu[b], w.la);
+      if (s < w.alen) {
+        w.alen = s;
+        w.anchor = b;
+      }
+    }
+  }
+  if (w.anchor == QM) w.alen = 0;  // cannot happen for a connected pattern
+  const uint32_t av = w.anchor == QM ? 0 : p.mu[w.anchor];
+  w.base = m.orow[av] + m.loff[(u64)av * 17 + w.la];
+  w.last = p.depth + 1 == P.q;
+  // the anchor's own bound term is replaced by the candidate's weight
+  w.bound0 = p.bound;
+  for (uint32_t i = 0; i < p.depth; ++i) {
+    const uint32_t b = P.order[i];
+    if (P.nbr[w.a] >> b & 1) w.bound0 -= m.best[(u64)p.mu[b] * NURI_MAX_LABELS + w.la];
+  }
+  for (uint32_t u = 0; u < P.q; ++u)
+    if ((P.nbr[w.a] >> u & 1) && P.pos[u] > p.depth) w.bound0 -= P.pmx[w.a][u];
+  return w;
+}
+
+// per-wavefront counters of the candidates it walked
+struct MTally {
+  u64 pruned_new = 0, leaves = 0, offered = 0, bytes = 0, cost = 0, maxcost = 0;
+  long long maxb = LLONG_MIN;
+};
+
+// candidates [t_begin, t_end) of record p's anchor segment
+__device__ inline void match_walk(const MView &m, const MPlan &P, const MRec &p, const MWork &w,
+                                  uint32_t t_begin, uint32_t t_end, long long theta, uint32_t q,
+                                  const MCfg &cf, MStep *ms, StepHdr *hdr, Cand *cands,
+                                  uint32_t *cand_ids, uint32_t cand_cap, int lane, MTally &st) {
+  const uint32_t a = w.a, la = w.la, anchor = w.anchor;
+  for (uint32_t t0 = t_begin; t0 < t_end; t0 += 64) {
+    const uint32_t t = t0 + lane;
+    bool ok = t < t_end;
+    uint32_t c = 0;
+    long long score2 = p.score, bound2 = w.bound0;
+    if (ok) {
+      c = m.lcol[w.base + t];
+      const int32_t wa = m.lew[w.base + t];
+      score2 += wa;
+      bound2 += wa;
+      // injectivity and symmetry breaking against every matched vertex
+      for (uint32_t i = 0; i < p.depth && ok; ++i) {
+        const uint32_t b = P.order[i];
+        const uint32_t mb = p.mu[b];
+        ok = c != mb;
+        if ((P.sb_lt[a] >> b & 1) && !(c < mb)) ok = false;
+        if ((P.sb_lt[b] >> a & 1) && !(mb < c)) ok = false;
+      }
+      // adjacency to the other matched neighbours
+      for (uint32_t i = 0; i < p.depth && ok; ++i) {
+        const uint32_t b = P.order[i];
+        if (b == anchor || !(P.nbr[a] >> b & 1)) continue;
+        long long at = seg_find(m, p.mu[b], la, c);
+        if (at < 0) {
+          ok = false;
+        } else {
+          const int32_t wt = m.lew[at];
+          score2 += wt;
+          bound2 += wt;
+        }
+      }
+      // edges from a to unmatched pattern vertices: one-hop bound from c
+      for (uint32_t u = 0; u < P.q && ok; ++u)
+        if ((P.nbr[a] >> u & 1) && P.pos[u] > p.depth) {
+          const int32_t wt = m.best[(u64)c * NURI_MAX_LABELS + P.label[u]];
+          if (wt <= 0) ok = false;
+          bound2 += wt;
+        }
+    }
+    const bool valid = t < t_end;
+    const bool prune = valid && (!ok || bound2 < theta);
+    const bool complete = ok && !prune && w.last;
+    const bool offer = complete && score2 >= theta;
+    const bool keep = ok && !prune && !w.last;
+    st.pruned_new += __popcll(__ballot(prune));
+    st.leaves += __popcll(__ballot(complete));
+    // children
+    MRec ch;
+    uint32_t nch = 0;
+    if (keep) {
+      ch = p;
+      ch.mu[a] = c;
+      ch.score = score2;
+      ch.bound = bound2;
+      ch.depth = p.depth + 1;
+      nch = child_bound(m, P, ch);
+      ch.nchild = nch;
+    }
+    const bool keep2 = keep && nch > 0;  // a child with no possible candidate is dead
+    st.pruned_new += __popcll(__ballot(keep && !keep2));
+    const u64 km = __ballot(keep2);
+    if (km) {
+      unsigned int h0 = 0;
+      if (lane == 0) h0 = atomicAdd(&ms[q].n_out, (unsigned int)__popcll(km));
+      h0 = __shfl(h0, 0, 64);
+      if (keep2) {
+        const uint32_t rk = __popcll(km & ((1ull << lane) - 1ull));
+        const u64 slot = (u64)cf.out_hdr + h0 + rk;
+        if (slot < cf.hdr_cap) {
+          cf.hdr[slot] = ch;
+          st.cost += nch;
+          st.maxcost = nch > st.maxcost ? nch : st.maxcost;
+          st.maxb = bound2 > st.maxb ? bound2 : st.maxb;
+          st.bytes += 64;
+        } else {
+          atomicAdd(&ms[q].overflow, 1u);
+        }
+      }
+    }
+    const u64 fm = __ballot(offer);
+    if (fm) {
+      long long cm = offer ? score2 : LLONG_MIN;
+      cm = wave_max(cm);
+      if (lane == 0) {
+        atomicAdd(&ms[q].cand_n, (unsigned int)__popcll(fm));
+        atomicMax(&ms[q].cand_max, cm);
+      }
+      unsigned int c0 = 0;
+      if (lane == 0) c0 = atomicAdd(&hdr->leaf_count, (unsigned int)__popcll(fm));
+      c0 = __shfl(c0, 0, 64);
+      if (offer) {
+        const uint32_t slot = c0 + __popcll(fm & ((1ull << lane) - 1ull));
+        if (slot < cand_cap) {
+          Cand cd;
+          cd.score = score2;
+          cd.qid = q;
+          cd.len = P.q;
+          cands[slot] = cd;
+          uint32_t *dst = cand_ids + (u64)slot * QM;
+          for (uint32_t i = 0; i < P.q; ++i) dst[i] = (i == a) ? c : p.mu[i];
+          st.offered++;
+        } else {
+          atomicAdd(&ms[q].overflow, 1u);
+        }
+      }
+    }
+  }
+}
+
+// flush one wavefront's tally into the query's counters
+__device__ inline void match_flush(MTally &st, MCtr &C, MStep &S, int lane) {
+  st.cost = wave_sum(st.cost);
+  st.maxcost = wave_max_u64(st.maxcost);
+  st.bytes = wave_sum(st.bytes);
+  st.offered = wave_sum(st.offered);
+  st.maxb = wave_max(st.maxb);
+  if (lane == 0) {
+    if (st.pruned_new) atomicAdd(&C.pruned_new, st.pruned_new);
+    if (st.leaves) atomicAdd(&C.leaves, st.leaves);
+    if (st.offered) atomicAdd(&C.offered, st.offered);
+    if (st.bytes) atomicAdd(&C.logical_bytes, st.bytes);
+    if (st.cost) {
+      atomicAdd(&S.out_cost, st.cost);
+      atomicMax(&S.out_max_cost, st.maxcost);
+    }
+    if (st.maxb != LLONG_MIN) atomicMax(&S.out_max_bound, st.maxb);
+  }
+}
 
 __global__ void __launch_bounds__(64 * kMatchWaves)
     k_match_expand(MView m, const MPlan *plans, const MRec *__restrict__ batch, StepHdr *hdr,
                    const MCfg *cfg, MStep *ms, MCtr *ctr, const QRes *res, Cand *cands,
-                   uint32_t *cand_ids, uint32_t cand_cap) {
+                   uint32_t *cand_ids, uint32_t cand_cap, uint32_t *big_rec, uint32_t *big_base) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t rec = blockIdx.x * kMatchWaves + wv;
   if (rec >= hdr->batch_count) return;
@@ -294,171 +484,71 @@ __global__ void __launch_bounds__(64 * kMatchWaves)
   const MPlan &P = plans[q];
   const MCfg cf = cfg[q];
   const long long theta = mprune_theta(cf, res[q]);
-  u64 st_children = 0, st_pruned_new = 0, st_leaves = 0, st_offered = 0, st_bytes = 0,
-      st_cost = 0, st_maxcost = 0;
-  long long st_maxb = LLONG_MIN;
+  MTally st;
+  u64 children = 0;
   const bool pruned_pop = p.bound < theta;
   if (!pruned_pop && p.depth < P.q) {
-    const uint32_t a = P.order[p.depth];
-    const uint32_t la = P.label[a];
-    // anchor: the matched neighbour of a with the shortest label-la segment
-    uint32_t anchor = QM, alen = 0xFFFFFFFFu;
-    for (uint32_t i = 0; i < p.depth; ++i) {
-      const uint32_t b = P.order[i];
-      if (P.nbr[a] >> b & 1) {
-        uint32_t s = seg_len(m, p.mu[b], la);
-        if (s < alen) {
-          alen = s;
-          anchor = b;
-        }
-      }
+    const MWork w = match_work(m, P, p);
+    children = w.alen;
+    if (lane == 0) st.bytes += 64 + 8ull * w.alen;
+    if (w.alen > kMatchChunk && lane == 0) {
+      // the chunks past the first go to k_match_expand_big; one 64-bit
+      // atomic reserves both the list slot and the chunk numbers, so the
+      // list stays sorted by its first chunk
+      const u64 nrest = (w.alen - 1) / kMatchChunk;
+      const u64 old = atomicAdd(&hdr->big_packed, (1ull << 32) | nrest);
+      const uint32_t slot = (uint32_t)(old >> 32);
+      big_rec[slot] = rec;
+      big_base[slot] = (uint32_t)old;
     }
-    if (anchor == QM) alen = 0;  // cannot happen for a connected pattern
-    const uint32_t av = anchor == QM ? 0 : p.mu[anchor];
-    const u64 base = m.orow[av] + m.loff[(u64)av * 17 + la];
-    const bool last = p.depth + 1 == P.q;
-    // the anchor's own bound term is replaced by the candidate's weight
-    long long bound0 = p.bound;
-    for (uint32_t i = 0; i < p.depth; ++i) {
-      const uint32_t b = P.order[i];
-      if (P.nbr[a] >> b & 1) bound0 -= m.best[(u64)p.mu[b] * NURI_MAX_LABELS + la];
-    }
-    for (uint32_t u = 0; u < P.q; ++u)
-      if ((P.nbr[a] >> u & 1) && P.pos[u] > p.depth) bound0 -= P.pmx[a][u];
-    if (lane == 0) {
-      st_children = alen;
-      st_bytes += 64 + 8ull * alen;
-    }
-    for (uint32_t t0 = 0; t0 < alen; t0 += 64) {
-      const uint32_t t = t0 + lane;
-      bool ok = t < alen;
-      uint32_t c = 0;
-      long long score2 = p.score, bound2 = bound0;
-      if (ok) {
-        c = m.lcol[base + t];
-        const int32_t wa = m.lew[base + t];
-        score2 += wa;
-        bound2 += wa;
-        // injectivity and symmetry breaking against every matched vertex
-        for (uint32_t i = 0; i < p.depth && ok; ++i) {
-          const uint32_t b = P.order[i];
-          const uint32_t mb = p.mu[b];
-          ok = c != mb;
-          if ((P.sb_lt[a] >> b & 1) && !(c < mb)) ok = false;
-          if ((P.sb_lt[b] >> a & 1) && !(mb < c)) ok = false;
-        }
-        // adjacency to the other matched neighbours
-        for (uint32_t i = 0; i < p.depth && ok; ++i) {
-          const uint32_t b = P.order[i];
-          if (b == anchor || !(P.nbr[a] >> b & 1)) continue;
-          long long at = seg_find(m, p.mu[b], la, c);
-          if (at < 0) {
-            ok = false;
-          } else {
-            const int32_t w = m.lew[at];
-            score2 += w;
-            bound2 += w;
-          }
-        }
-        // edges from a to unmatched pattern vertices: one-hop bound from c
-        for (uint32_t u = 0; u < P.q && ok; ++u)
-          if ((P.nbr[a] >> u & 1) && P.pos[u] > p.depth) {
-            const int32_t w = m.best[(u64)c * NURI_MAX_LABELS + P.label[u]];
-            if (w <= 0) ok = false;
-            bound2 += w;
-          }
-      }
-      const bool valid = t < alen;
-      const bool prune = valid && (!ok || bound2 < theta);
-      const bool complete = ok && !prune && last;
-      const bool offer = complete && score2 >= theta;
-      const bool keep = ok && !prune && !last;
-      st_pruned_new += __popcll(__ballot(prune));
-      st_leaves += __popcll(__ballot(complete));
-      // children
-      MRec ch;
-      uint32_t nch = 0;
-      if (keep) {
-        ch = p;
-        ch.mu[a] = c;
-        ch.score = score2;
-        ch.bound = bound2;
-        ch.depth = p.depth + 1;
-        nch = child_bound(m, P, ch);
-        ch.nchild = nch;
-      }
-      const bool keep2 = keep && nch > 0;  // a child with no possible candidate is dead
-      st_pruned_new += __popcll(__ballot(keep && !keep2));
-      const u64 km = __ballot(keep2);
-      if (km) {
-        unsigned int h0 = 0;
-        if (lane == 0) h0 = atomicAdd(&ms[q].n_out, (unsigned int)__popcll(km));
-        h0 = __shfl(h0, 0, 64);
-        if (keep2) {
-          const uint32_t rk = __popcll(km & ((1ull << lane) - 1ull));
-          const u64 slot = (u64)cf.out_hdr + h0 + rk;
-          if (slot < cf.hdr_cap) {
-            cf.hdr[slot] = ch;
-            st_cost += nch;
-            st_maxcost = nch > st_maxcost ? nch : st_maxcost;
-            st_maxb = bound2 > st_maxb ? bound2 : st_maxb;
-            st_bytes += 64;
-          } else {
-            atomicAdd(&ms[q].overflow, 1u);
-          }
-        }
-      }
-      const u64 fm = __ballot(offer);
-      if (fm) {
-        long long cm = offer ? score2 : LLONG_MIN;
-        cm = wave_max(cm);
-        if (lane == 0) {
-          atomicAdd(&ms[q].cand_n, (unsigned int)__popcll(fm));
-          atomicMax(&ms[q].cand_max, cm);
-        }
-        unsigned int c0 = 0;
-        if (lane == 0) c0 = atomicAdd(&hdr->leaf_count, (unsigned int)__popcll(fm));
-        c0 = __shfl(c0, 0, 64);
-        if (offer) {
-          const uint32_t slot = c0 + __popcll(fm & ((1ull << lane) - 1ull));
-          if (slot < cand_cap) {
-            Cand cd;
-            cd.score = score2;
-            cd.qid = q;
-            cd.len = P.q;
-            cands[slot] = cd;
-            uint32_t *dst = cand_ids + (u64)slot * QM;
-            for (uint32_t i = 0; i < P.q; ++i) dst[i] = (i == a) ? c : p.mu[i];
-            st_offered++;
-          } else {
-            atomicAdd(&ms[q].overflow, 1u);
-          }
-        }
-      }
-    }
+    match_walk(m, P, p, w, 0, min(w.alen, kMatchChunk), theta, q, cf, ms, hdr, cands, cand_ids,
+               cand_cap, lane, st);
   }
-  st_cost = wave_sum(st_cost);
-  st_maxcost = wave_max_u64(st_maxcost);
-  st_bytes = wave_sum(st_bytes);
-  st_offered = wave_sum(st_offered);
-  st_maxb = wave_max(st_maxb);
+  match_flush(st, ctr[q], ms[q], lane);
   if (lane == 0) {
     MCtr &C = ctr[q];
     atomicAdd(&C.popped, 1ull);
     if (pruned_pop) atomicAdd(&C.pruned_pop, 1ull);
-    if (st_children) {
+    if (children) {
       atomicAdd(&C.expanded, 1ull);
-      atomicAdd(&C.children, st_children);
+      atomicAdd(&C.children, children);
     }
-    if (st_pruned_new) atomicAdd(&C.pruned_new, st_pruned_new);
-    if (st_leaves) atomicAdd(&C.leaves, st_leaves);
-    if (st_offered) atomicAdd(&C.offered, st_offered);
-    if (st_bytes) atomicAdd(&C.logical_bytes, st_bytes);
-    if (st_cost) {
-      atomicAdd(&ms[q].out_cost, st_cost);
-      atomicMax(&ms[q].out_max_cost, st_maxcost);
+  }
+}
+
+// The chunks of long anchor segments: wavefronts take chunk numbers from a
+// shared counter until none is left; a chunk's record is found by binary
+// search in the list (sorted by first chunk).  grid: kBigBlocks blocks.
+__global__ void __launch_bounds__(64 * kMatchWaves)
+    k_match_expand_big(MView m, const MPlan *plans, const MRec *__restrict__ batch, StepHdr *hdr,
+                       const MCfg *cfg, MStep *ms, MCtr *ctr, const QRes *res, Cand *cands,
+                       uint32_t *cand_ids, uint32_t cand_cap, const uint32_t *big_rec,
+                       const uint32_t *big_base) {
+  const int lane = threadIdx.x & 63;
+  const u64 packed = hdr->big_packed;
+  const uint32_t nbig = (uint32_t)(packed >> 32), nchunks = (uint32_t)packed;
+  for (;;) {
+    uint32_t c = 0;
+    if (lane == 0) c = atomicAdd(&hdr->big_next, 1u);
+    c = __shfl(c, 0, 64);
+    if (c >= nchunks) break;
+    uint32_t lo = 0, hi = nbig;  // last slot whose first chunk is <= c
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (big_base[mid] <= c) lo = mid;
+      else hi = mid;
     }
-    if (st_maxb != LLONG_MIN) atomicMax(&ms[q].out_max_bound, st_maxb);
+    const MRec p = batch[big_rec[lo]];
+    const uint32_t q = p.qid;
+    const MPlan &P = plans[q];
+    const MCfg cf = cfg[q];
+    const long long theta = mprune_theta(cf, res[q]);
+    const MWork w = match_work(m, P, p);
+    const uint32_t t0 = (c - big_base[lo] + 1) * kMatchChunk;
+    MTally st;
+    match_walk(m, P, p, w, t0, min(w.alen, t0 + kMatchChunk), theta, q, cf, ms, hdr, cands,
+               cand_ids, cand_cap, lane, st);
+    match_flush(st, ctr[q], ms[q], lane);
   }
 }
 
@@ -644,9 +734,11 @@ struct MQHost {
   int lvl = -1;  // stack index of the level this step takes from
 };
 
+// per-slot top-k buffers and frontier arena, taken at admission
 struct MSlotTopk {
   PoolBuf<long long> score;
   PoolBuf<unsigned int> len, ids;
+  PoolBuf<MRec> hdr;
 };
 
 struct MStepLayout {
@@ -684,7 +776,9 @@ struct MatchEngine {
   std::vector<std::unique_ptr<MSlotTopk>> tk;
   PoolBuf<MPlan> d_plans;
   PoolBuf<uint64_t> d_lab_off;
-  PoolBuf<MRec> hdr, batch, temp;
+  PoolBuf<MRec> batch, temp;
+  u64 arena_bytes = 0;  // frontier arena of a slot unless admit() is given one
+  PoolBuf<uint32_t> big_rec, big_base;  // records whose candidates are shared out in chunks
   PoolBuf<MCtr> d_ctr;
   PoolBuf<QRes> d_res;
   PoolBuf<uint32_t> d_k, d_rootq;
@@ -748,14 +842,8 @@ struct MatchEngine {
     tk.clear();
     for (uint32_t i = 0; i < nq; ++i) tk.emplace_back(new MSlotTopk);
     L.reset(new MStepLayout(nq));
-    const u64 per_q = o.frontier_budget / nq;
-    u64 hdr_per_q = std::max<u64>(4096, per_q / sizeof(MRec));
-    hdr_per_q = std::min<u64>(hdr_per_q, 0x7FFFFFFFull);
-    hdr.alloc(g.pool, hdr_per_q * nq);
+    arena_bytes = o.frontier_budget / nq;
     for (uint32_t i = 0; i < nq; ++i) {
-      qh[i].hdr_cap = (uint32_t)hdr_per_q;
-      cfg[i].hdr = hdr.p + (u64)i * hdr_per_q;
-      cfg[i].hdr_cap = (uint32_t)hdr_per_q;
       cfg[i].out_hdr = 0;
       cfg[i].prio = o.priority;
       cfg[i].pad = 0;
@@ -788,6 +876,8 @@ struct MatchEngine {
     cand_cap = (uint32_t)std::min<u64>(step_children, 1ull << 22);
     batch_cap = (uint32_t)std::min<u64>((u64)nq * B, 1u << 24);
     batch.alloc(g.pool, batch_cap);
+    big_rec.alloc(g.pool, batch_cap);
+    big_base.alloc(g.pool, batch_cap);
     cands.alloc(g.pool, cand_cap);
     cand_ids.alloc(g.pool, (u64)cand_cap * QM);
     cands2.alloc(g.pool, cand_cap);
@@ -811,15 +901,25 @@ struct MatchEngine {
     }
   }
 
-  // start a query in a free slot (its unit subgraphs are made on the next step)
-  void admit(uint32_t i, const nuri_pattern &pt, uint32_t k) {
+  // records in an arena of `bytes`
+  static u64 arena_records(u64 bytes) {
+    return std::min<u64>(std::max<u64>(4096, bytes / sizeof(MRec)), 0x7FFFFFFFull);
+  }
+
+  // start a query in a free slot (its unit subgraphs are made on the next
+  // step) with a frontier arena of `bytes` (0: the slot default)
+  void admit(uint32_t i, const nuri_pattern &pt, uint32_t k, u64 bytes = 0) {
     MPlan P;
     plan_pattern(g, pt, k, P);  // throws on an invalid pattern
     MQHost &Q = qh[i];
     Q = MQHost{};
     Q.active = true;
     Q.k = k;
-    Q.hdr_cap = cfg[i].hdr_cap;
+    const u64 cap = arena_records(bytes ? bytes : arena_bytes);
+    tk[i]->hdr.alloc(g.pool, cap);
+    cfg[i].hdr = tk[i]->hdr.p;
+    cfg[i].hdr_cap = (uint32_t)cap;
+    Q.hdr_cap = (uint32_t)cap;
     Q.t_admit = now_ns();
     Q.done = P.rest0 == LLONG_MIN / 4;  // some pattern edge has no data edge
     Q.rooted = Q.done;
@@ -1038,8 +1138,17 @@ struct MatchEngine {
     if (o.profile) NURI_HIP(hipEventRecord(ev0, s));
     hipLaunchKernelGGL(k_match_expand, dim3((batch_ub + kMatchWaves - 1) / kMatchWaves),
                        dim3(64 * kMatchWaves), 0, s, view(), d_plans.p, batch.p, dh, dcfg, dms,
-                       d_ctr.p, d_res.p, cands.p, cand_ids.p, cand_cap);
+                       d_ctr.p, d_res.p, cands.p, cand_ids.p, cand_cap, big_rec.p, big_base.p);
     NURI_HIP(hipGetLastError());
+    // long candidate lists were cut into chunks: share those out
+    bool any_big = false;
+    for (uint32_t t = 0; t < nseg; ++t) any_big |= sseg()[t].maxcost > kMatchChunk;
+    if (any_big) {
+      hipLaunchKernelGGL(k_match_expand_big, dim3(kBigBlocks), dim3(64 * kMatchWaves), 0, s,
+                         view(), d_plans.p, batch.p, dh, dcfg, dms, d_ctr.p, d_res.p, cands.p,
+                         cand_ids.p, cand_cap, big_rec.p, big_base.p);
+      NURI_HIP(hipGetLastError());
+    }
     if (o.profile) NURI_HIP(hipEventRecord(ev1, s));
     read_step();
     uint64_t ens = 0;
@@ -1196,6 +1305,8 @@ struct MatchEngine {
     tk[i]->score.release();
     tk[i]->len.release();
     tk[i]->ids.release();
+    tk[i]->hdr.release();
+    cfg[i].hdr = nullptr;
   }
 };
 
@@ -1206,13 +1317,38 @@ void run_matches(Graph &g, const std::vector<const nuri_pattern *> &ps,
   if (ps.empty()) return;
   if (!g.has_lab) throw Error{NURI_EINVAL, "labelled matching needs vertex labels"};
   if (ps.size() > 65535) throw Error{NURI_EINVAL, "at most 65535 queries per batch"};
+  // as many patterns live at once as the frontier budget holds arenas of
+  // at least kMinArena bytes; the others wait for a slot
+  constexpr u64 kMinArena = 4096 * sizeof(MRec);
+  const uint32_t nq = (uint32_t)ps.size();
+  const u64 per = std::max<u64>(kMinArena, o.frontier_budget / nq);
+  const uint32_t slots = (uint32_t)std::max<u64>(1, std::min<u64>(nq, o.frontier_budget / per));
   MatchEngine e(g, o);
-  e.setup((uint32_t)ps.size());
-  for (uint32_t i = 0; i < ps.size(); ++i) e.admit(i, *ps[i], ks[i]);
-  while (e.step_all()) {
+  e.setup(slots);
+  e.arena_bytes = o.frontier_budget / slots;
+  std::vector<uint32_t> slot_query(slots, UINT32_MAX);
+  uint32_t next = 0;
+  out.resize(nq);
+  auto fill = [&] {
+    for (uint32_t s = 0; s < slots && next < nq; ++s)
+      if (e.slot_free(s)) {
+        e.admit(s, *ps[next], ks[next]);
+        slot_query[s] = next++;
+      }
+  };
+  fill();
+  for (;;) {
+    const bool more = e.step_all();
+    bool freed = false;
+    for (uint32_t s = 0; s < slots; ++s)
+      if (e.finished(s)) {
+        e.harvest(s, out[slot_query[s]]);
+        slot_query[s] = UINT32_MAX;
+        freed = true;
+      }
+    if (freed) fill();
+    if (!more && !e.any_live() && next >= nq) break;
   }
-  out.resize(ps.size());
-  for (uint32_t i = 0; i < ps.size(); ++i) e.harvest(i, out[i]);
 }
 
 // ------------------------------------------------------------------
@@ -1233,7 +1369,10 @@ uint32_t MatchSlots::slots() const { return impl->e.nq; }
 bool MatchSlots::free(uint32_t i) const { return impl->e.slot_free(i); }
 bool MatchSlots::finished(uint32_t i) const { return impl->e.finished(i); }
 bool MatchSlots::live() const { return impl->e.any_live(); }
-void MatchSlots::admit(uint32_t i, const nuri_pattern &p, uint32_t k) { impl->e.admit(i, p, k); }
+void MatchSlots::admit(uint32_t i, const nuri_pattern &p, uint32_t k, uint64_t bytes) {
+  impl->e.admit(i, p, k, bytes);
+}
+uint64_t MatchSlots::min_arena_bytes() const { return 4096 * sizeof(MRec); }
 bool MatchSlots::step() { return impl->e.step_all(); }
 void MatchSlots::harvest(uint32_t i, Result &r) { impl->e.harvest(i, r); }
 

@@ -282,9 +282,12 @@ struct CliqueSlots {
   bool free(uint32_t i) const;
   bool finished(uint32_t i) const;
   bool live() const;
-  void admit(uint32_t i, uint32_t k, int kind);  // throws on invalid arguments
-  bool step();                                    // false when no slot has work
+  // starts a query in slot i with a frontier arena of `bytes`; throws on
+  // invalid arguments
+  void admit(uint32_t i, uint32_t k, int kind, uint64_t bytes);
+  bool step();  // false when no slot has work
   void harvest(uint32_t i, Result &r);
+  uint64_t min_arena_bytes() const;  // smallest arena a query can start with
 };
 
 struct MatchSlots {
@@ -296,9 +299,10 @@ struct MatchSlots {
   bool free(uint32_t i) const;
   bool finished(uint32_t i) const;
   bool live() const;
-  void admit(uint32_t i, const nuri_pattern &p, uint32_t k);  // throws on invalid arguments
+  void admit(uint32_t i, const nuri_pattern &p, uint32_t k, uint64_t bytes);
   bool step();
   void harvest(uint32_t i, Result &r);
+  uint64_t min_arena_bytes() const;
 };
 
 // matching engine

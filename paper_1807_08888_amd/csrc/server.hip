@@ -3,12 +3,17 @@
 // The paper's communication component takes a computation from the user
 // and returns its result set (Section 5); here many computations are live
 // at once.  A worker thread owns two slot engines (cliques, matching), each
-// holding up to max_slots queries with an equal share of the frontier
-// memory.  Between steps it admits queued queries into free slots (a slot
-// is a unit of frontier memory), runs one step for every live query of
-// each engine -- so the work of all of them shares every launch -- and
-// harvests finished slots.  A query's result does not depend on what else
-// is in flight: every search is exact.
+// holding up to max_slots live queries.  All live queries draw their
+// frontier arenas from one budget: a queued query is admitted, in arrival
+// order, when a slot of its kind is free and its arena fits in what the
+// budget has left (a query waiting for memory holds back the ones behind
+// it, so a large query is not starved).  A query starts with a base arena
+// (the budget over twice the slot count); one that outgrows its arena is
+// started again with twice the arena, up to the whole budget, so a served
+// result is exact whenever the budget can hold the search at all.  Every
+// step serves all live queries of each engine -- their work shares every
+// launch -- and finished slots are harvested.  A query's result does not
+// depend on what else is in flight: every search is exact.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -27,6 +32,8 @@ struct Served {
   std::vector<uint8_t> labels;
   std::vector<uint32_t> edges;
   uint64_t t_submit = 0;
+  uint64_t arena = 0;     // frontier bytes to admit it with (0: the base arena)
+  uint32_t restarts = 0;  // times it outgrew its arena and was started again
 };
 
 struct Server {
@@ -36,6 +43,9 @@ struct Server {
   std::unique_ptr<CliqueSlots> cs;
   std::unique_ptr<MatchSlots> ms;
   std::vector<uint64_t> c_ticket, m_ticket;      // ticket per slot (0 = free)
+  std::vector<Served> c_query, m_query;          // the query in each slot
+  uint64_t budget = 0, used = 0;                 // frontier bytes: total, held by live queries
+  uint64_t base_arena = 0;
   std::unordered_map<uint64_t, uint64_t> submit_t;
   std::mutex mu;
   std::condition_variable cv;
@@ -65,7 +75,14 @@ struct Server {
     finish(ticket, std::move(r));
   }
 
-  // move queued queries into free slots, in arrival order per engine
+  uint64_t arena_of(const Served &q) const {
+    const uint64_t lo = q.kind == 0 ? cs->min_arena_bytes() : ms->min_arena_bytes();
+    return std::min<uint64_t>(budget, std::max<uint64_t>(q.arena ? q.arena : base_arena, lo));
+  }
+
+  // move queued queries into free slots, in arrival order: a query is
+  // admitted when a slot of its kind is free and its arena fits in the
+  // budget; the first query that waits for memory stops the scan
   void admit() {
     std::deque<Served> take;
     {
@@ -74,16 +91,19 @@ struct Server {
       for (auto t : c_ticket) cfree += t == 0;
       for (auto t : m_ticket) mfree += t == 0;
       std::deque<Served> keep;
+      bool blocked = false;
       while (!queue.empty()) {
         Served q = std::move(queue.front());
         queue.pop_front();
-        if (q.kind == 0 && cfree) {
-          --cfree;
-          take.push_back(std::move(q));
-        } else if (q.kind == 1 && mfree) {
-          --mfree;
+        const bool slot = q.kind == 0 ? cfree > 0 : mfree > 0;
+        const uint64_t need = (q.kind == 1 && !ms) ? 0 : arena_of(q);
+        if (!blocked && slot && used + need <= budget) {
+          (q.kind == 0 ? cfree : mfree)--;
+          used += need;
+          q.arena = need;
           take.push_back(std::move(q));
         } else {
+          if (slot) blocked = true;  // waits for memory: nothing overtakes it
           keep.push_back(std::move(q));
         }
       }
@@ -94,19 +114,22 @@ struct Server {
         if (q.kind == 0) {
           uint32_t i = 0;
           while (c_ticket[i]) ++i;
-          cs->admit(i, q.k, q.wf);
+          cs->admit(i, q.k, q.wf, q.arena);
           c_ticket[i] = q.ticket;
+          c_query[i] = q;
         } else {
           if (!ms) throw Error{NURI_EINVAL, "labelled matching needs vertex labels"};
           uint32_t i = 0;
           while (m_ticket[i]) ++i;
           nuri_pattern p{(uint32_t)q.labels.size(), (uint32_t)(q.edges.size() / 2),
                          q.labels.data(), q.edges.data()};
-          ms->admit(i, p, q.k);
+          ms->admit(i, p, q.k, q.arena);
           m_ticket[i] = q.ticket;
+          m_query[i] = q;
         }
       } catch (const Error &e) {
         if (e.code == NURI_EINVAL) {
+          used -= q.arena;
           fail_ticket(q.ticket, e.code, e.msg);
         } else {
           throw;
@@ -115,20 +138,35 @@ struct Server {
     }
   }
 
+  // a finished slot: its arena returns to the budget; a query that outgrew
+  // its arena goes back to the head of the queue with twice the arena
+  void settle(Served &q, Result &&r) {
+    used -= q.arena;
+    if (r.error == NURI_EBUDGET && q.arena < budget) {
+      q.arena = std::min<uint64_t>(budget, 2 * q.arena);
+      q.restarts++;
+      std::lock_guard<std::mutex> lk(mu);
+      queue.push_front(std::move(q));
+      return;
+    }
+    r.stats.restarts = q.restarts;
+    finish(q.ticket, std::move(r));
+  }
+
   void harvest() {
     for (uint32_t i = 0; i < c_ticket.size(); ++i)
       if (c_ticket[i] && cs->finished(i)) {
         Result r;
         cs->harvest(i, r);
-        finish(c_ticket[i], std::move(r));
         c_ticket[i] = 0;
+        settle(c_query[i], std::move(r));
       }
     for (uint32_t i = 0; i < m_ticket.size(); ++i)
       if (m_ticket[i] && ms->finished(i)) {
         Result r;
         ms->harvest(i, r);
-        finish(m_ticket[i], std::move(r));
         m_ticket[i] = 0;
+        settle(m_query[i], std::move(r));
       }
   }
 
@@ -203,18 +241,20 @@ int nuri_server_create(nuri_graph *g, uint64_t frontier_budget_bytes, uint32_t m
     S.g = g->g;
     S.opts = qo;
     S.max_slots = max_slots;
-    // the frontier memory is split between the two engines
-    QueryOpts half = qo;
-    half.frontier_budget = g->g->has_lab ? qo.frontier_budget / 2 : qo.frontier_budget;
+    // one frontier budget shared by all live queries of both engines
+    S.budget = qo.frontier_budget;
+    S.base_arena = qo.frontier_budget / (2ull * max_slots);
     try {
-      S.cs.reset(new CliqueSlots(*g->g, half, max_slots));
-      if (g->g->has_lab) S.ms.reset(new MatchSlots(*g->g, half, max_slots));
+      S.cs.reset(new CliqueSlots(*g->g, qo, max_slots));
+      if (g->g->has_lab) S.ms.reset(new MatchSlots(*g->g, qo, max_slots));
     } catch (...) {
       delete srv;
       throw;
     }
     S.c_ticket.assign(max_slots, 0);
     S.m_ticket.assign(S.ms ? max_slots : 0, 0);
+    S.c_query.assign(max_slots, Served{});
+    S.m_query.assign(S.ms ? max_slots : 0, Served{});
     S.worker = std::thread([&S] { S.loop(); });
     *out = srv;
     return NURI_OK;

@@ -67,7 +67,7 @@ class _View(ctypes.Structure):
 
 STAT_FIELDS = ("steps", "popped", "expanded", "children", "pruned_at_pop", "pruned_at_creation",
                "leaves", "offered", "frontier_peak_bytes", "logical_bytes", "expand_launches",
-               "expand_ns", "wall_ns", "ties_at_k")
+               "expand_ns", "wall_ns", "ties_at_k", "restarts", "onchip_bytes")
 
 
 class _Stats(ctypes.Structure):

@@ -1,11 +1,11 @@
-"""Writes rmat16_weighted_top1000.txt: the CPU oracle's top-1000 maximal
-cliques by vertex weight on R-MAT scale 16 (a = 0.57, b = c = 0.19, vertex
+"""Writes rmat15_weighted_top1000.txt: the CPU oracle's top-1000 maximal
+cliques by vertex weight on R-MAT scale 15 (a = 0.57, b = c = 0.19, vertex
 weights U{1..100}, the generator's default seed), with the graph's hash.
 
 Every top-k list of this graph for k <= 1000 is a prefix of this list (the
 results are ranked under a total order), so one stored list checks all the
 queries of a batch with k drawn in 1..1000.  Run from anywhere:
-python tests/golden/make_rmat16_weighted_top1000.py
+python tests/golden/make_rmat15_weighted_top1000.py
 """
 import os
 import sys
@@ -18,8 +18,8 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 from tests.golden_lists import workload_sha256  # noqa: E402
 
-SCALE, K = 16, 1000
-OUT = os.path.join(HERE, "rmat16_weighted_top1000.txt")
+SCALE, K = 15, 1000
+OUT = os.path.join(HERE, "rmat15_weighted_top1000.txt")
 
 
 def workload():
@@ -34,8 +34,8 @@ def main():
     res, st = oracle.topk_cliques(g, K, weighted=True, bound=1)
     print(f"oracle: {len(res)} results in {time.time() - t:.1f} s, {st['children']} children")
     with open(OUT, "w") as f:
-        f.write("# Top-1000 maximal cliques by vertex weight, R-MAT scale 16, from the CPU\n"
-                "# oracle; written by make_rmat16_weighted_top1000.py.  result <score> <ids>\n")
+        f.write("# Top-1000 maximal cliques by vertex weight, R-MAT scale 15, from the CPU\n"
+                "# oracle; written by make_rmat15_weighted_top1000.py.  result <score> <ids>\n")
         f.write(f"workload_sha256 {workload_sha256(g)}\n")
         for s, ids in res:
             f.write(f"result {s} {' '.join(str(v) for v in ids)}\n")

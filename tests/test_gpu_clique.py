@@ -357,10 +357,11 @@ def test_deadline_fails_loudly_and_leaves_the_graph_usable(nuri):
 
 
 def test_many_queries_with_the_smallest_arenas(nuri):
-    """4096 vertex-weighted queries share a 64 MiB budget: 16 KiB each, below
-    the smallest arena the engine makes (1024 records, 4096 words), so each
-    gets that minimum.  Results equal the same batch under the default
-    budget, and the oracle on three of them.
+    """4096 vertex-weighted queries share a 64 MiB budget: 16 KiB each would
+    be below the smallest arena the engine makes (64 KiB), so at most 1024
+    run at once and the others start as those finish; the budget is never
+    exceeded.  Results equal the same batch under the default budget, and
+    the oracle on three of them.
     """
     g = synth.rmat(12)
     synth.add_vertex_weights(g)

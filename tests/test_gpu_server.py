@@ -6,6 +6,7 @@ served result must equal the same query run alone, and the oracle.
 """
 import time
 
+import numpy as np
 import pytest
 
 import oracle
@@ -156,3 +157,54 @@ def test_ticket_errors(nuri):
     finally:
         S.close()
         G.close()
+
+
+def test_small_budget_admits_by_memory_and_restarts_exactly(nuri, workload):
+    """A 64 MiB budget over 4096 slots gives each query only the smallest
+    arena to start with: queries wait for memory, the ones that outgrow
+    their arena are started again with twice the arena, and every result
+    still equals the query run alone."""
+    g, G, queries = workload
+    _case("server: 64 MiB budget, 4096 slots")
+    alone = [_alone(nuri, G, q) for q in queries]
+    S = nuri.Server(G, frontier_budget_bytes=64 << 20, max_slots=4096)
+    try:
+        tickets = [S.submit(q) for q in queries]
+        res = _wait(nuri, S, tickets, timeout=180.0)
+    finally:
+        S.close()
+    for i, t in enumerate(tickets):
+        assert res[t].items == alone[i], i
+
+
+def test_query_that_outgrows_its_arena_restarts_exactly(nuri):
+    """A labelled path on a graph where 12,001 vertices carry the pattern's
+    label: its unit subgraphs alone (64 bytes each) overflow the smallest
+    matching arena (4,096 records), so under a 64 MiB budget over 4096
+    slots the query must be restarted with larger arenas -- and its result
+    must still equal the query run alone."""
+    n = 12001
+    rng = np.random.default_rng(5)
+    edges = {(0, v) for v in range(1, n)}
+    for _ in range(3 * n):
+        a, b = (int(x) for x in rng.integers(1, n, 2))
+        if a != b:
+            edges.add((min(a, b), max(a, b)))
+    g = synth.from_edges(n, sorted(edges))
+    g.vertex_label = np.zeros(n, np.uint8)
+    synth.add_edge_weights(g, 1, 1000, master=5)
+    labels, pedges = [0, 0, 0], [(0, 1), (1, 2)]
+    _case("server: a query larger than its first arena")
+    G = nuri.Graph.from_synth(g)
+    try:
+        alone = nuri.topk_match(G, labels, pedges, 20).items
+        S = nuri.Server(G, frontier_budget_bytes=64 << 20, max_slots=4096)
+        try:
+            t = S.submit({"kind": "match", "k": 20, "labels": labels, "edges": pedges})
+            res = _wait(nuri, S, [t], timeout=120.0)
+        finally:
+            S.close()
+    finally:
+        G.close()
+    assert res[t].items == alone
+    assert res[t].stats["restarts"] >= 1
