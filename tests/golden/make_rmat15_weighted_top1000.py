@@ -33,12 +33,18 @@ def main():
     t = time.time()
     res, st = oracle.topk_cliques(g, K, weighted=True, bound=1)
     print(f"oracle: {len(res)} results in {time.time() - t:.1f} s, {st['children']} children")
+    # the results share most of their vertices: store the sorted union once
+    # and each result as a hex mask over it
+    base = sorted({v for _, ids in res for v in ids})
+    at = {v: i for i, v in enumerate(base)}
     with open(OUT, "w") as f:
         f.write("# Top-1000 maximal cliques by vertex weight, R-MAT scale 15, from the CPU\n"
-                "# oracle; written by make_rmat15_weighted_top1000.py.  result <score> <ids>\n")
+                "# oracle; written by make_rmat15_weighted_top1000.py.  base <the sorted\n"
+                "# vertices of all results>; result <score> <hex mask over base>\n")
         f.write(f"workload_sha256 {workload_sha256(g)}\n")
+        f.write(f"base {' '.join(str(v) for v in base)}\n")
         for s, ids in res:
-            f.write(f"result {s} {' '.join(str(v) for v in ids)}\n")
+            f.write(f"result {s} {sum(1 << at[v] for v in ids):x}\n")
     print(f"wrote {OUT}")
 
 

@@ -73,16 +73,19 @@ def power_law_top100():
     return sha, items
 
 
-def rmat16_weighted_top1000():
-    """(workload_sha256, [(score, ids ascending)]) from rmat16_weighted_top1000.txt."""
-    items, sha = [], None
-    with open(os.path.join(GOLDEN, "rmat16_weighted_top1000.txt")) as f:
+def rmat15_weighted_top1000():
+    """(workload_sha256, [(score, ids ascending)]) from rmat15_weighted_top1000.txt."""
+    items, sha, base = [], None, []
+    with open(os.path.join(GOLDEN, "rmat15_weighted_top1000.txt")) as f:
         for line in f:
             if line.startswith("#") or not line.strip():
                 continue
             parts = line.split()
             if parts[0] == "workload_sha256":
                 sha = parts[1]
+            elif parts[0] == "base":
+                base = [int(x) for x in parts[1:]]
             elif parts[0] == "result":
-                items.append((int(parts[1]), tuple(int(x) for x in parts[2:])))
+                m = int(parts[2], 16)
+                items.append((int(parts[1]), tuple(base[j] for j in range(len(base)) if m >> j & 1)))
     return sha, items
