@@ -43,6 +43,12 @@ def _load():
     lib.oracle_clique_trace.argtypes = [u32, vp, vp, u32, vp, u64, vp, u64, vp]
     lib.oracle_topk_match.restype = ctypes.c_int64
     lib.oracle_topk_match.argtypes = [u32, vp, vp, vp, vp, u32, u32, vp, u32, vp, u32, i32, vp, vp, vp]
+    lib.oracle_topk_match_degree.restype = ctypes.c_int64
+    lib.oracle_topk_match_degree.argtypes = [u32, vp, vp, vp, u32, u32, vp, u32, vp, u32, i32, vp, vp,
+                                             vp]
+    lib.oracle_hop_index.argtypes = [u32, vp, vp, vp, u32, u32, vp]
+    lib.oracle_match_root_bounds.restype = ctypes.c_int64
+    lib.oracle_match_root_bounds.argtypes = [u32, vp, vp, vp, vp, u32, u32, vp, u32, vp, i32, vp]
     lib.oracle_vertex_order.argtypes = [u32, vp, vp, i32, vp]
     lib.oracle_core_numbers.argtypes = [u32, vp, vp, vp]
     lib.oracle_set_work_limit.argtypes = [u64]
@@ -136,9 +142,12 @@ def clique_trace(g, k: int):
     return pops, R[:st["r_size"]], st
 
 
-def topk_match(g, labels, edges, k: int, n_labels: int = 16, priority: int = 0):
+def topk_match(g, labels, edges, k: int, n_labels: int = 16, priority: int = 0,
+               score: str = "edge"):
     """Top-k labelled matches of the pattern (labels[q], edges [(a,b)]) in g.
 
+    score: "edge" (sum of matched edge weights) or "degree" (sum of the
+    degrees of the matched vertices, bounded with the multi-hop index).
     Returns ([(score, (mu(0), ..., mu(q-1))), ...] best first, stats).
     """
     lib = _load()
@@ -151,14 +160,55 @@ def topk_match(g, labels, edges, k: int, n_labels: int = 16, priority: int = 0):
     scores = np.zeros(k, np.int64)
     ids = np.zeros(k * q, np.uint32)
     stats = np.zeros(8, np.uint64)
-    c = lib.oracle_topk_match(g.n, rp.ctypes.data, col.ctypes.data, lab.ctypes.data,
-                              ew.ctypes.data if ew is not None else None, n_labels, q,
-                              pl.ctypes.data, len(edges), pe.ctypes.data, k, priority,
-                              scores.ctypes.data, ids.ctypes.data, stats.ctypes.data)
+    if score == "degree":
+        c = lib.oracle_topk_match_degree(g.n, rp.ctypes.data, col.ctypes.data, lab.ctypes.data,
+                                         n_labels, q, pl.ctypes.data, len(edges), pe.ctypes.data,
+                                         k, priority, scores.ctypes.data, ids.ctypes.data,
+                                         stats.ctypes.data)
+    elif score == "edge":
+        c = lib.oracle_topk_match(g.n, rp.ctypes.data, col.ctypes.data, lab.ctypes.data,
+                                  ew.ctypes.data if ew is not None else None, n_labels, q,
+                                  pl.ctypes.data, len(edges), pe.ctypes.data, k, priority,
+                                  scores.ctypes.data, ids.ctypes.data, stats.ctypes.data)
+    else:
+        raise ValueError("score must be 'edge' or 'degree'")
     if c < 0:
         raise ValueError("invalid pattern or k")
     res = [(int(scores[i]), tuple(int(x) for x in ids[i * q:(i + 1) * q])) for i in range(c)]
     return res, dict(zip(MATCH_STATS, (int(x) for x in stats[:7])))
+
+
+def hop_index(g, hops: int, n_labels: int = 16) -> np.ndarray:
+    """The multi-hop max-degree index, int32 [hops, n, n_labels]: entry
+    [h-1, v, l] = largest degree of a label-l vertex 1..h hops from v, 0 if
+    none."""
+    lib = _load()
+    rp, col = _arr(g.row_ptr, np.uint64), _arr(g.col, np.uint32)
+    lab = _arr(g.vertex_label, np.uint8)
+    out = np.zeros((hops, g.n, n_labels), np.int32)
+    lib.oracle_hop_index(g.n, rp.ctypes.data, col.ctypes.data, lab.ctypes.data, n_labels, hops,
+                         out.ctypes.data)
+    return out
+
+
+def match_root_bounds(g, labels, edges, n_labels: int = 16, score: str = "edge"):
+    """(first pattern vertex of the matching order, int64 bound per data
+    vertex of the unit subgraph it hosts; -1 for non-roots and for roots
+    with no completion)."""
+    lib = _load()
+    rp, col = _arr(g.row_ptr, np.uint64), _arr(g.col, np.uint32)
+    lab = _arr(g.vertex_label, np.uint8)
+    ew = _arr(g.edge_weight, np.int32) if g.edge_weight is not None else None
+    pl = _arr(labels, np.uint8)
+    pe = _arr(np.array(edges, dtype=np.uint32).reshape(-1), np.uint32)
+    out = np.zeros(g.n, np.int64)
+    first = lib.oracle_match_root_bounds(g.n, rp.ctypes.data, col.ctypes.data, lab.ctypes.data,
+                                         ew.ctypes.data if ew is not None else None, n_labels,
+                                         len(labels), pl.ctypes.data, len(edges), pe.ctypes.data,
+                                         int(score == "degree"), out.ctypes.data)
+    if first < 0:
+        raise ValueError("invalid pattern")
+    return int(first), out
 
 
 def vertex_order(g, order: int = 1) -> np.ndarray:

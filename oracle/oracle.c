@@ -8,7 +8,9 @@
  *   - top-k maximal cliques (Section 3.2 "Example: Maximum Clique
  *     Discovery", Section 4.1, Listing 1), and
  *   - top-k labelled subgraph matching (Section 2.1 "Subgraph Isomorphism",
- *     Section 4.3), scored by the sum of matched edge weights.
+ *     Section 4.3), scored by the sum of matched edge weights, or by the
+ *     sum of the degrees of the matched vertices with the multi-hop
+ *     (label, hop) max-degree index of Section 4.3 (Listing 3).
  *
  * It exists to check the GPU engine.  It shares no code with it: no
  * headers, helpers or tables.  Only the tests, the smoke check and the
@@ -32,6 +34,11 @@
  *   - Matching is non-induced (a monomorphism); two embeddings with the
  *     same image are one result, represented by the lexicographically
  *     smallest tuple (mu(0), ..., mu(q-1)) in its automorphism orbit.
+ *   - The multi-hop index entry for hop h covers every vertex at distance
+ *     1..h (not exactly h): the image of a pattern vertex h hops from the
+ *     seed's pattern vertex can lie closer to the seed than h, so only the
+ *     cumulative entry bounds it.  The seed itself (distance 0) is never
+ *     counted.  Degree = number of neighbours in the data graph.
  *
  * All arithmetic is integer.  parity pins: see tests/test_oracle_*.py.
  */
@@ -679,6 +686,7 @@ typedef struct {
   uint32_t ea[QMAX * QMAX], eb[QMAX * QMAX];
   uint8_t adj[QMAX][QMAX];
   uint32_t order[QMAX], pos[QMAX];
+  uint32_t hop[QMAX]; /* distance from order[0] in the pattern */
   uint32_t naut;
   uint8_t *aut; /* naut x q permutations */
 } pattern_t;
@@ -761,6 +769,79 @@ static int64_t match_bound(const graph_t *g, const pattern_t *P, const tables_t 
   return b;
 }
 
+static int64_t degree_of(const graph_t *g, uint32_t v) {
+  return (int64_t)(g->row_ptr[v + 1] - g->row_ptr[v]);
+}
+
+/*
+ * The Section 4.3 index (Listing 3), cumulative over hops:
+ * out[(h-1)*n*nl + v*nl + l] = the largest degree of a label-l vertex x
+ * with 1 <= dist(v, x) <= h, or 0 when there is none, for h = 1..H.  A
+ * breadth-first search from every vertex, cut at depth H.
+ */
+static void hop_index(const graph_t *g, uint32_t nl, uint32_t H, int32_t *out) {
+  const uint32_t n = g->n;
+  memset(out, 0, (uint64_t)H * n * nl * sizeof(int32_t));
+  int32_t *dist = (int32_t *)xmalloc((uint64_t)n * sizeof(int32_t));
+  uint32_t *queue = (uint32_t *)xmalloc((uint64_t)n * sizeof(uint32_t));
+  int32_t *layer = (int32_t *)xmalloc((uint64_t)(H + 1) * nl * sizeof(int32_t));
+  for (uint32_t v = 0; v < n; ++v) dist[v] = -1;
+  for (uint32_t v = 0; v < n; ++v) {
+    memset(layer, 0, (uint64_t)(H + 1) * nl * sizeof(int32_t));
+    uint64_t head = 0, tail = 0;
+    queue[tail++] = v;
+    dist[v] = 0;
+    while (head < tail) {
+      uint32_t x = queue[head++];
+      if (dist[x] > 0) {
+        int32_t *m = &layer[(uint64_t)dist[x] * nl + g->lab[x]];
+        if (degree_of(g, x) > *m) *m = (int32_t)degree_of(g, x);
+      }
+      if ((uint32_t)dist[x] == H) continue;
+      for (uint64_t e = g->row_ptr[x]; e < g->row_ptr[x + 1]; ++e) {
+        uint32_t y = g->col[e];
+        if (dist[y] < 0) { dist[y] = dist[x] + 1; queue[tail++] = y; }
+      }
+    }
+    for (uint64_t i = 0; i < tail; ++i) dist[queue[i]] = -1;
+    /* entry for hop h = max over the layers 1..h */
+    for (uint32_t l = 0; l < nl; ++l) {
+      int32_t run = 0;
+      for (uint32_t h = 1; h <= H; ++h) {
+        if (layer[(uint64_t)h * nl + l] > run) run = layer[(uint64_t)h * nl + l];
+        out[((uint64_t)(h - 1) * n + v) * nl + l] = run;
+      }
+    }
+  }
+  free(dist);
+  free(queue);
+  free(layer);
+}
+
+/*
+ * Degree-score bound (Section 4.3): the current score plus, for every
+ * pattern vertex u not yet matched, index(seed, label(u), hop(u)), where
+ * the seed is the data vertex of the unit subgraph (mu(order[0])) and
+ * hop(u) is u's distance from order[0] in the pattern.  A pattern path of
+ * length h maps onto a data walk of length h, so mu(u) lies within hop(u)
+ * of the seed and is not the seed.  Returns -1 when an entry is 0 (no
+ * vertex of that label within reach: no completion exists).
+ */
+static int64_t match_bound_degree(const graph_t *g, const pattern_t *P, const int32_t *hidx,
+                                  uint32_t nl, const match_rec *r) {
+  uint8_t matched[QMAX] = {0};
+  for (uint32_t i = 0; i < r->depth; ++i) matched[P->order[i]] = 1;
+  const uint32_t seed = r->mu[P->order[0]];
+  int64_t b = r->score;
+  for (uint32_t u = 0; u < P->q; ++u) {
+    if (matched[u]) continue;
+    int32_t x = hidx[((uint64_t)(P->hop[u] - 1) * g->n + seed) * nl + P->label[u]];
+    if (x <= 0) return -1;
+    b += x;
+  }
+  return b;
+}
+
 /*
  * True when the complete embedding mu is the lexicographically smallest
  * tuple (mu(0), ..., mu(q-1)) among mu o s for all automorphisms s.
@@ -800,73 +881,148 @@ static int match_may_be_canonical(const pattern_t *P, const match_rec *r) {
 }
 
 /*
- * Top-k matches of the labelled pattern (q vertices, edges as pairs) by
- * Algorithm 1 with vertex-at-a-time expansion in a fixed matching order.
- * Score = sum of the data-edge weights under the pattern's edges (int64).
- * Results: score_out[i] and mu(0..q-1) at ids_out[i*q ..].  Returns count.
+ * Reads the pattern (q vertices, edges as pairs), checks it, and fixes the
+ * matching order: first the vertex whose label is rarest in the graph
+ * (ties: larger pattern degree, then smaller id); then repeatedly the
+ * vertex with the most edges to the ones already ordered (ties: smaller
+ * id).  hop[u] = distance of u from order[0].  Returns 0, or -2 for an
+ * invalid pattern.
  */
-int64_t oracle_topk_match(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
-                          const uint8_t *lab, const int32_t *ew, uint32_t n_labels, uint32_t q,
-                          const uint8_t *plabel, uint32_t ne, const uint32_t *pedges, uint32_t k,
-                          int priority_kind, int64_t *score_out, uint32_t *ids_out,
-                          uint64_t *stats_out) {
-  graph_t G = {n, row_ptr, col, NULL, lab, ew, NULL};
-  const graph_t *g = &G;
-  if (k == 0 || q < 2 || q > QMAX) return -2;
-  pattern_t P;
-  memset(&P, 0, sizeof(P));
-  P.q = q;
-  P.ne = ne;
-  for (uint32_t a = 0; a < q; ++a) P.label[a] = plabel[a];
+static int pattern_setup(pattern_t *P, const graph_t *g, uint32_t n_labels, uint32_t q,
+                         const uint8_t *plabel, uint32_t ne, const uint32_t *pedges) {
+  memset(P, 0, sizeof(*P));
+  if (q < 2 || q > QMAX) return -2;
+  P->q = q;
+  P->ne = ne;
+  for (uint32_t a = 0; a < q; ++a) P->label[a] = plabel[a];
   for (uint32_t e = 0; e < ne; ++e) {
     uint32_t a = pedges[2 * e], b = pedges[2 * e + 1];
-    if (a >= q || b >= q || a == b || P.adj[a][b]) return -2;
-    P.ea[e] = a; P.eb[e] = b;
-    P.adj[a][b] = P.adj[b][a] = 1;
+    if (a >= q || b >= q || a == b || P->adj[a][b]) return -2;
+    P->ea[e] = a; P->eb[e] = b;
+    P->adj[a][b] = P->adj[b][a] = 1;
   }
   /* connectivity */
   {
     uint8_t seen[QMAX] = {1};
     for (uint32_t round = 0; round < q; ++round)
       for (uint32_t a = 0; a < q; ++a)
-        if (seen[a]) for (uint32_t b = 0; b < q; ++b) if (P.adj[a][b]) seen[b] = 1;
+        if (seen[a]) for (uint32_t b = 0; b < q; ++b) if (P->adj[a][b]) seen[b] = 1;
     for (uint32_t a = 0; a < q; ++a) if (!seen[a]) return -2;
   }
-  pattern_automorphisms(&P);
-
-  /* matching order: first the vertex whose label is rarest in the graph
-     (ties: larger pattern degree, then smaller id); then repeatedly the
-     vertex with the most edges to the ones already ordered (ties: smaller
-     id). */
   uint64_t *lcount = (uint64_t *)calloc(n_labels ? n_labels : 1, sizeof(uint64_t));
-  for (uint32_t v = 0; v < n; ++v) if (lab[v] < n_labels) lcount[lab[v]]++;
+  for (uint32_t v = 0; v < g->n; ++v) if (g->lab[v] < n_labels) lcount[g->lab[v]]++;
   {
     uint8_t used[QMAX] = {0};
     uint32_t best = 0;
     for (uint32_t a = 1; a < q; ++a) {
       uint32_t da = 0, db = 0;
-      for (uint32_t x = 0; x < q; ++x) { da += P.adj[a][x]; db += P.adj[best][x]; }
-      uint64_t ca = P.label[a] < n_labels ? lcount[P.label[a]] : 0;
-      uint64_t cb = P.label[best] < n_labels ? lcount[P.label[best]] : 0;
+      for (uint32_t x = 0; x < q; ++x) { da += P->adj[a][x]; db += P->adj[best][x]; }
+      uint64_t ca = P->label[a] < n_labels ? lcount[P->label[a]] : 0;
+      uint64_t cb = P->label[best] < n_labels ? lcount[P->label[best]] : 0;
       if (ca < cb || (ca == cb && da > db)) best = a;
     }
-    P.order[0] = best; used[best] = 1;
+    P->order[0] = best; used[best] = 1;
     for (uint32_t i = 1; i < q; ++i) {
       uint32_t pick = q, pc = 0;
       for (uint32_t a = 0; a < q; ++a) {
         if (used[a]) continue;
         uint32_t c = 0;
-        for (uint32_t j = 0; j < i; ++j) c += P.adj[a][P.order[j]];
+        for (uint32_t j = 0; j < i; ++j) c += P->adj[a][P->order[j]];
         if (pick == q || c > pc) { pick = a; pc = c; }
       }
-      P.order[i] = pick; used[pick] = 1;
+      P->order[i] = pick; used[pick] = 1;
     }
-    for (uint32_t i = 0; i < q; ++i) P.pos[P.order[i]] = i;
+    for (uint32_t i = 0; i < q; ++i) P->pos[P->order[i]] = i;
   }
   free(lcount);
+  /* distances from order[0] by breadth-first search over the pattern */
+  {
+    uint32_t queue[QMAX], head = 0, tail = 0;
+    uint8_t seen[QMAX] = {0};
+    queue[tail++] = P->order[0];
+    seen[P->order[0]] = 1;
+    P->hop[P->order[0]] = 0;
+    while (head < tail) {
+      uint32_t a = queue[head++];
+      for (uint32_t b = 0; b < q; ++b)
+        if (P->adj[a][b] && !seen[b]) { seen[b] = 1; P->hop[b] = P->hop[a] + 1; queue[tail++] = b; }
+    }
+  }
+  pattern_automorphisms(P);
+  return 0;
+}
 
-  tables_t T;
-  build_tables(g, n_labels, &T);
+static uint32_t pattern_max_hop(const pattern_t *P) {
+  uint32_t H = 1;
+  for (uint32_t u = 0; u < P->q; ++u) if (P->hop[u] > H) H = P->hop[u];
+  return H;
+}
+
+/* what the search needs to score and bound a partial match */
+typedef struct {
+  int degree;      /* 0: edge-weight score, 1: degree score */
+  uint32_t nl;
+  tables_t T;      /* edge-weight bound tables */
+  int32_t *hidx;   /* multi-hop index (degree score) */
+} scoring_t;
+
+static void scoring_init(scoring_t *S, const graph_t *g, const pattern_t *P, uint32_t nl,
+                         int degree) {
+  memset(S, 0, sizeof(*S));
+  S->degree = degree;
+  S->nl = nl;
+  if (degree) {
+    uint32_t H = pattern_max_hop(P);
+    S->hidx = (int32_t *)xmalloc((uint64_t)H * g->n * nl * sizeof(int32_t));
+    hop_index(g, nl, H, S->hidx);
+  } else {
+    build_tables(g, nl, &S->T);
+  }
+}
+
+static void scoring_free(scoring_t *S) {
+  free(S->hidx);
+  free(S->T.best);
+  free(S->T.pairmax);
+}
+
+static int64_t scoring_bound(const scoring_t *S, const graph_t *g, const pattern_t *P,
+                             const match_rec *r) {
+  return S->degree ? match_bound_degree(g, P, S->hidx, S->nl, r) : match_bound(g, P, &S->T, r);
+}
+
+/* a unit subgraph: v hosts order[0]; its score is deg(v) under the degree score */
+static void match_root(const scoring_t *S, const graph_t *g, const pattern_t *P, uint32_t v,
+                       match_rec *r) {
+  memset(r, 0, sizeof(*r));
+  r->depth = 1;
+  r->mu[P->order[0]] = v;
+  r->score = S->degree ? degree_of(g, v) : 0;
+  r->bound = scoring_bound(S, g, P, r);
+}
+
+/*
+ * Top-k matches of the labelled pattern by Algorithm 1 with
+ * vertex-at-a-time expansion in the fixed matching order.  Score = the sum
+ * of the data-edge weights under the pattern's edges, or (degree) the sum
+ * of the degrees of the matched vertices (int64).  Results: score_out[i]
+ * and mu(0..q-1) at ids_out[i*q ..].  Returns count, or -2 for an invalid
+ * pattern or k.
+ */
+static int64_t topk_match(const graph_t *g, uint32_t n_labels, uint32_t q, const uint8_t *plabel,
+                          uint32_t ne, const uint32_t *pedges, uint32_t k, int priority_kind,
+                          int degree, int64_t *score_out, uint32_t *ids_out,
+                          uint64_t *stats_out) {
+  const uint32_t n = g->n;
+  const uint64_t *row_ptr = g->row_ptr;
+  const uint32_t *col = g->col;
+  const uint8_t *lab = g->lab;
+  if (k == 0) return -2;
+  pattern_t P;
+  if (pattern_setup(&P, g, n_labels, q, plabel, ne, pedges) != 0) return -2;
+
+  scoring_t S;
+  scoring_init(&S, g, &P, n_labels, degree);
   pq_t Q = {0};
   rset_t R = {(result_t *)xmalloc((uint64_t)k * sizeof(result_t)), 0, k};
   ostats_t st = {0};
@@ -876,11 +1032,7 @@ int64_t oracle_topk_match(uint32_t n, const uint64_t *row_ptr, const uint32_t *c
   for (uint32_t v = 0; v < n; ++v) {
     if (lab[v] != P.label[first]) continue;
     match_rec *r = (match_rec *)xmalloc(sizeof(match_rec));
-    memset(r, 0, sizeof(*r));
-    r->depth = 1;
-    r->mu[first] = v;
-    r->score = 0;
-    r->bound = match_bound(g, &P, &T, r);
+    match_root(&S, g, &P, v, r);
     if (r->bound < 0) { free(r); continue; }
     int64_t key[3] = {priority_kind == 2 ? 0 : 1, priority_kind == 2 ? 0 : r->bound, 0};
     if (priority_kind == 1) { key[0] = r->bound; key[1] = 0; }
@@ -919,6 +1071,7 @@ int64_t oracle_topk_match(uint32_t n, const uint64_t *row_ptr, const uint32_t *c
         }
       }
       if (!ok) continue;
+      if (degree) add = degree_of(g, c);
       match_rec *ch = (match_rec *)xmalloc(sizeof(match_rec));
       *ch = *r;
       ch->mu[a] = c;
@@ -926,7 +1079,7 @@ int64_t oracle_topk_match(uint32_t n, const uint64_t *row_ptr, const uint32_t *c
       ch->score = r->score + add;
       st.children++;
       if (!match_may_be_canonical(&P, ch)) { free(ch); continue; }
-      ch->bound = match_bound(g, &P, &T, ch);
+      ch->bound = scoring_bound(&S, g, &P, ch);
       if (ch->bound < 0 || rset_dominates(&R, ch->bound)) {
         st.pruned_at_creation++;
         free(ch);
@@ -940,8 +1093,7 @@ int64_t oracle_topk_match(uint32_t n, const uint64_t *row_ptr, const uint32_t *c
     free(r);
   }
   free(Q.a);
-  free(T.best);
-  free(T.pairmax);
+  scoring_free(&S);
   free(P.aut);
   if (stats_out) {
     stats_out[0] = st.popped; stats_out[1] = st.expanded; stats_out[2] = st.children;
@@ -956,6 +1108,62 @@ int64_t oracle_topk_match(uint32_t n, const uint64_t *row_ptr, const uint32_t *c
   }
   free(R.e);
   return cnt;
+}
+
+/* top-k matches scored by the sum of matched edge weights (ew NULL: 1 each) */
+int64_t oracle_topk_match(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                          const uint8_t *lab, const int32_t *ew, uint32_t n_labels, uint32_t q,
+                          const uint8_t *plabel, uint32_t ne, const uint32_t *pedges, uint32_t k,
+                          int priority_kind, int64_t *score_out, uint32_t *ids_out,
+                          uint64_t *stats_out) {
+  graph_t G = {n, row_ptr, col, NULL, lab, ew, NULL};
+  return topk_match(&G, n_labels, q, plabel, ne, pedges, k, priority_kind, 0, score_out, ids_out,
+                    stats_out);
+}
+
+/* top-k matches scored by the sum of the degrees of the matched vertices */
+int64_t oracle_topk_match_degree(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                                 const uint8_t *lab, uint32_t n_labels, uint32_t q,
+                                 const uint8_t *plabel, uint32_t ne, const uint32_t *pedges,
+                                 uint32_t k, int priority_kind, int64_t *score_out,
+                                 uint32_t *ids_out, uint64_t *stats_out) {
+  graph_t G = {n, row_ptr, col, NULL, lab, NULL, NULL};
+  return topk_match(&G, n_labels, q, plabel, ne, pedges, k, priority_kind, 1, score_out, ids_out,
+                    stats_out);
+}
+
+/* the multi-hop index for hops 1..H, [H][n][n_labels] */
+void oracle_hop_index(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, const uint8_t *lab,
+                      uint32_t n_labels, uint32_t H, int32_t *out) {
+  graph_t G = {n, row_ptr, col, NULL, lab, NULL, NULL};
+  hop_index(&G, n_labels, H, out);
+}
+
+/*
+ * Bounds of the unit subgraphs (Algorithm 1, lines 1-3): bound_out[v] for
+ * every vertex v that can host the first pattern vertex of the matching
+ * order, -1 for the others and for roots with no completion.  Returns that
+ * pattern vertex, or -2 for an invalid pattern.
+ */
+int64_t oracle_match_root_bounds(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                                 const uint8_t *lab, const int32_t *ew, uint32_t n_labels,
+                                 uint32_t q, const uint8_t *plabel, uint32_t ne,
+                                 const uint32_t *pedges, int degree, int64_t *bound_out) {
+  graph_t G = {n, row_ptr, col, NULL, lab, degree ? NULL : ew, NULL};
+  pattern_t P;
+  if (pattern_setup(&P, &G, n_labels, q, plabel, ne, pedges) != 0) return -2;
+  scoring_t S;
+  scoring_init(&S, &G, &P, n_labels, degree);
+  for (uint32_t v = 0; v < n; ++v) {
+    bound_out[v] = -1;
+    if (lab[v] != P.label[P.order[0]]) continue;
+    match_rec r;
+    match_root(&S, &G, &P, v, &r);
+    bound_out[v] = r.bound;
+  }
+  scoring_free(&S);
+  free(P.aut);
+  return P.order[0];
 }
 
 /* order used by the clique oracle, exposed for tests */

@@ -41,9 +41,12 @@ def topk_cliques(g, k: int, weights: Sequence[int] = None):
     return [(score(c), c) for c in ranked[:k]]
 
 
-def all_images(g, labels: Sequence[int], edges: Sequence[Tuple[int, int]]):
+def all_images(g, labels: Sequence[int], edges: Sequence[Tuple[int, int]],
+               score: str = "edge"):
     """Every injective, label- and edge-preserving map, grouped by image.
 
+    score "edge": sum of the weights of the data edges under the pattern
+    edges; "degree": sum of the degrees of the matched data vertices.
     Returns {image_key: (score, lexicographically smallest mu tuple)}.
     """
     q = len(labels)
@@ -65,14 +68,17 @@ def all_images(g, labels: Sequence[int], edges: Sequence[Tuple[int, int]]):
         vs = frozenset(mu)
         es = frozenset(frozenset((mu[a], mu[b])) for a, b in edges)
         key = (vs, es)
-        sc = sum(w[(mu[a], mu[b])] for a, b in edges)
+        if score == "degree":
+            sc = sum(len(adj[v]) for v in mu)
+        else:
+            sc = sum(w[(mu[a], mu[b])] for a, b in edges)
         if key not in images or mu < images[key][1]:
             images[key] = (sc, mu)
     return images
 
 
-def topk_matches(g, labels, edges, k):
-    imgs = all_images(g, labels, edges)
+def topk_matches(g, labels, edges, k, score: str = "edge"):
+    imgs = all_images(g, labels, edges, score)
     ranked = sorted(imgs.values(), key=lambda t: (-t[0], t[1]))
     return [(s, mu) for s, mu in ranked[:k]], len(imgs)
 

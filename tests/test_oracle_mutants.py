@@ -11,11 +11,13 @@ import contextlib
 import os
 import subprocess
 
+import numpy as np
 import pytest
 
 import oracle
 import synth
 from tests import bruteforce
+from tests.test_oracle_match_degree import _index_from_distances as index_from_distances
 
 ORACLE_C = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -79,6 +81,21 @@ MUTANTS = [
     ("one-endpoint matching bound looks up the matched vertex's own label",
      "else if (matched[a]) ub = T->best[(uint64_t)r->mu[a] * T->nl + P->label[c]];",
      "else if (matched[a]) ub = T->best[(uint64_t)r->mu[a] * T->nl + P->label[a]];"),
+    ("multi-hop index by exact distance, not cumulative",
+     "if (layer[(uint64_t)h * nl + l] > run) run = layer[(uint64_t)h * nl + l];",
+     "run = layer[(uint64_t)h * nl + l];"),
+    ("degree bound without the current score",
+     "  int64_t b = r->score;\n  for (uint32_t u = 0; u < P->q; ++u) {",
+     "  int64_t b = 0;\n  for (uint32_t u = 0; u < P->q; ++u) {"),
+    ("degree bound looks every unmatched vertex up at one hop",
+     "hidx[((uint64_t)(P->hop[u] - 1) * g->n + seed) * nl + P->label[u]]",
+     "hidx[((uint64_t)0 * g->n + seed) * nl + P->label[u]]"),
+    ("degree score adds the anchor's degree, not the candidate's",
+     "if (degree) add = degree_of(g, c);",
+     "if (degree) add = degree_of(g, av);"),
+    ("degree score leaves out the seed",
+     "r->score = S->degree ? degree_of(g, v) : 0;",
+     "r->score = 0;"),
 ]
 
 MATCH_PATTERNS = [
@@ -121,6 +138,16 @@ def _battery():
                 got, _ = oracle.topk_match(g, labels, edges, k, n_labels=2)
                 if got != want:
                     failed.append(f"match pattern {pi} seed {seed} k={k}")
+                want, _ = bruteforce.topk_matches(g, labels, edges, k, score="degree")
+                got, _ = oracle.topk_match(g, labels, edges, k, n_labels=2, score="degree")
+                if got != want:
+                    failed.append(f"degree match pattern {pi} seed {seed} k={k}")
+    for seed in (1, 2):
+        g = synth.gnp(40, 0.08, 60 + seed)
+        synth.add_zipf_labels(g, n_labels=3, s=0.5, master=60 + seed)
+        if not np.array_equal(oracle.hop_index(g, 4, n_labels=3),
+                              index_from_distances(g, 4, 3)):
+            failed.append(f"hop index seed {seed}")
     return failed
 
 
