@@ -9,7 +9,7 @@
  *     of vertex weights, and
  *   - top-k labelled subgraph matching (Section 2.1 "Subgraph
  *     Isomorphism", Section 4.3), scored by the sum of matched edge
- *     weights.
+ *     weights or by the sum of the degrees of the matched vertices.
  * The user functions of Table 1 are fixed specialisations selected by the
  * arguments below; no user code runs on the device.
  *
@@ -107,6 +107,19 @@ typedef struct {
 } nuri_graph_info;
 int nuri_graph_get_info(const nuri_graph *g, nuri_graph_info *info);
 
+/*
+ * The multi-hop (label, hop) max-degree index of Section 4.3 (Listing 3),
+ * the index behind NURI_MATCH_DEGREE: builds it on the device up to `hops`
+ * hops if it is not there yet (it stays with the graph), then, unless out
+ * is NULL, copies it to out (host, caller-owned, int32 [hops][n][16]):
+ *   out[(h-1)*n*16 + v*16 + l] = the largest degree of a vertex of label l
+ *   at distance 1..h from v (cumulative over hops), 0 when there is none.
+ * 1 <= hops <= NURI_MAX_PATTERN - 1; the graph must have vertex labels.
+ * build_ns (may be NULL) receives the build time of this call (0 when the
+ * hops were already there).
+ */
+int nuri_graph_hop_index(nuri_graph *g, uint32_t hops, int32_t *out, uint64_t *build_ns);
+
 /* Clique score (relevant results are maximal cliques, ranked by score). */
 typedef enum {
   NURI_SCORE_SIZE = 0,          /* |C| */
@@ -114,15 +127,37 @@ typedef enum {
 } nuri_weight_fn;
 
 /*
+ * Match score (Section 4.3).
+ *   EDGE_WEIGHT  sum over the pattern edges of the data edge weight (1 when
+ *                the graph has none); bounded with one-hop tables: the
+ *                largest edge weight from a vertex to a label, and over
+ *                each label pair
+ *   DEGREE       sum of the degrees of the matched data vertices (the
+ *                paper's example); bounded with the multi-hop index: for
+ *                every unmatched pattern vertex u, the largest degree of a
+ *                vertex with u's label within hop(u) hops of the seed (the
+ *                data vertex of the first pattern vertex matched), hop(u)
+ *                being u's distance from that pattern vertex.  The index is
+ *                built on the device the first time a query needs it (up
+ *                to the hops that query needs) and stays with the graph.
+ */
+typedef enum {
+  NURI_MATCH_EDGE_WEIGHT = 0,
+  NURI_MATCH_DEGREE = 1
+} nuri_match_score;
+
+/*
  * A connected labelled query pattern (Section 2.1): q vertices 0..q-1 with
  * label[q] and n_edges undirected edges edges[2*i], edges[2*i+1]
- * (distinct, a != b, a, b < q).  2 <= q <= NURI_MAX_PATTERN.
+ * (distinct, a != b, a, b < q).  2 <= q <= NURI_MAX_PATTERN.  score is a
+ * nuri_match_score (0 = edge weights).
  */
 #define NURI_MAX_PATTERN 8
 typedef struct {
   uint32_t q, n_edges;
   const uint8_t *label;
   const uint32_t *edges;
+  uint32_t score;
 } nuri_pattern;
 
 /*
@@ -208,7 +243,7 @@ int nuri_topk_cliques(nuri_graph *g, uint32_t k, nuri_weight_fn wf, const nuri_o
  * label-preserving maps mu with every pattern edge mapped onto a data edge
  * (non-induced).  Embeddings with the same image are one result,
  * represented by the lexicographically smallest (mu(0), ..., mu(q-1)).
- * Score = sum over pattern edges of the data edge weight (int64).  Order:
+ * Score (int64) as p->score selects (nuri_match_score).  Order:
  * score descending, then the representative tuple ascending.  Needs
  * vertex labels.  k >= 1.
  */
@@ -286,6 +321,12 @@ typedef struct {
   uint64_t onchip_bytes;       /* cliques: local adjacency rows read by expansion (a
                                   working set that stays in the L2 caches), kept apart
                                   from logical_bytes */
+  uint64_t spilled_bytes;      /* cliques: frontier bytes moved to host memory when the
+                                  query's arena filled up (the bottom levels of its
+                                  stack, brought back when the levels above are done) */
+  uint64_t index_ns;           /* matching, degree score: time this query spent building
+                                  the graph's multi-hop index (0 when it was there);
+                                  not part of wall_ns */
 } nuri_stats;
 int nuri_result_stats(const nuri_result *r, nuri_stats *s);
 void nuri_free_result(nuri_result *r);

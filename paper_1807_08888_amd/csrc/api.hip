@@ -93,6 +93,29 @@ void nuri_free_graph(nuri_graph *g) {
   delete g;
 }
 
+int nuri_graph_hop_index(nuri_graph *g, uint32_t hops, int32_t *out, uint64_t *build_ns) {
+  if (!g) {
+    set_error("NULL argument");
+    return NURI_EINVAL;
+  }
+  return guarded([&] {
+    Graph &G = *g->g;
+    if (hops < 1 || hops > NURI_MAX_PATTERN - 1)
+      throw Error{NURI_EINVAL, "hops must be 1..NURI_MAX_PATTERN-1"};
+    const uint64_t t0 = now_ns();
+    ensure_hop_index(G, hops, G.stream);
+    const uint64_t t1 = now_ns();
+    if (build_ns) *build_ns = t1 - t0;
+    if (!out) return;
+    std::lock_guard<std::mutex> lk(G.hidx_mu);
+    const size_t per = (size_t)G.n * NURI_MAX_LABELS;
+    for (uint32_t h = 0; h < hops; ++h)
+      NURI_HIP(hipMemcpyAsync(out + h * per, G.hidx[h].p, per * sizeof(int32_t),
+                              hipMemcpyDeviceToHost, G.stream));
+    NURI_HIP(hipStreamSynchronize(G.stream));
+  });
+}
+
 int nuri_graph_get_info(const nuri_graph *g, nuri_graph_info *info) {
   if (!g || !info) {
     set_error("NULL argument");

@@ -249,6 +249,13 @@ __global__ void k_sel_part(const SelSeg *segs, const QCfg *cfg, const QRes *res,
   }
 }
 
+// records moved down in their arena by the frontier spill: their word
+// offsets move down by the same shift (the |P| bits above stay as they are)
+__global__ void k_rebase(CRec *h, u64 n, u64 wshift) {
+  for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
+    h[i].woff -= wshift;
+}
+
 __global__ void k_copy_back(const SelSeg *segs, const QCfg *cfg, const CRec *temp,
                             const unsigned int *temp_count) {
   const uint32_t s = blockIdx.y;
@@ -421,7 +428,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   __shared__ uint32_t s_ccnt[kExpandWaves];
   __shared__ u64 s_cost[kExpandWaves], s_maxcc[kExpandWaves];
   __shared__ long long s_maxb[kExpandWaves];
-  __shared__ u64 s_st[kExpandWaves][8];
+  __shared__ u64 s_st[kExpandWaves][9];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   u64 *s_pw = s_dyn + (u64)wv * 5 * wst;
   u64 *s_vw = s_pw + wst;
@@ -444,6 +451,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     ST_POPPED, ST_PRUNED_POP, ST_EXPANDED, ST_CHILDREN, ST_PRUNED_NEW, ST_LEAVES,
     ST_BYTES,   // frontier records and leaves read and written
     ST_ONCHIP,  // local adjacency rows read (L2-resident)
+    ST_MARK,    // pruned count before this record's children (undone by absorption)
     ST_N
   };
   u64 *st = s_st[wv];
@@ -835,6 +843,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         }
       }
     } else {
+      if (lane == 0) st[ST_MARK] = st[ST_PRUNED_NEW];
       stat(ST_PRUNED_NEW, nchild - n_eff);
     }
     // Screening, for records with more children than one round of lane
@@ -846,6 +855,13 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     // Children that this bound or the witness rule out are counted as
     // pruned here; the others, in order, replace the list and are built by
     // the lane groups below, which repeat the exact test.
+    // A run of first candidates each adjacent to all the others is in every
+    // maximal clique below the record (any clique of the subtree extends by
+    // them), and a chain would add them one link at a time; the screening's
+    // first round finds such a run (candidate i, in position order, sees
+    // all nchild - 1 - i later candidates) and absorbs it below.
+    bool absorbed = false, absorb_keep = false;
+    uint32_t absorb_n = 0;  // length of the run
     if (!whole && n_eff > per && W >= 2) {
       int32_t wmx = 0;  // lane w: heaviest candidate of word w
       if (weighted)
@@ -856,6 +872,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
           if (lane == (int)w) wmx = (int32_t)m;
         }
       uint32_t kept = 0;
+      bool uni0 = false;  // first round: this lane's candidate sees all later ones
       for (uint32_t b0 = 0; b0 < n_eff; b0 += 64) {
         const uint32_t ci = b0 + lane;
         const bool valid = ci < n_eff;
@@ -865,7 +882,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         long long wub = 0;
         int x0 = -1;
         if (valid) {
-#pragma unroll 1
+#pragma unroll 4
           for (uint32_t w = 0; w < W; ++w) {
             const u64 row = rj[w];
             const u64 pv = s_pw[w];
@@ -877,12 +894,13 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
             if (x0 < 0 && xc) x0 = (int)w * 64 + __ffsll((long long)xc) - 1;
           }
         }
+        if (b0 == 0) uni0 = valid && cnt == nchild - 1 - ci;
         const long long score2 = p.score + (weighted ? (long long)wl[j] : 1ll);
         bool pass = valid && score2 + (weighted ? wub : (long long)cnt) >= theta;
         if (pass && x0 >= 0) {
           const u64 *rx = rows + (u64)x0 * W;
           u64 out = 0;
-#pragma unroll 1
+#pragma unroll 4
           for (uint32_t w = 0; w < W; ++w)
             out |= s_pw[w] & rj[w] & gt_mask((int)w, (int)j) & ~rx[w];
           pass = out != 0;  // covered when x0 is adjacent to all of P'
@@ -895,11 +913,100 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         kept += __popcll(pm);
         wave_sync();
       }
-      n_eff = kept;
+      if (nchild >= 3) {
+        const u64 um = __ballot(uni0);
+        const uint32_t run = um == ~0ull ? 64u : (uint32_t)__ffsll((long long)~um) - 1;
+        absorb_n = run < nchild - 1 ? run : nchild - 1;  // keep a candidate
+      }
+      absorbed = absorb_n >= 2;
+      if (absorbed) {
+        // the screened list was rewritten: the run is the first absorb_n
+        // candidates in position order again
+        const u64 mw = (lane < (int)W) ? pw : 0ull;
+        const uint32_t c2 = __popcll(mw);
+        uint32_t o = wave_excl_scan(c2, lane);
+        wave_sync();
+        for (u64 t = mw; t && o < absorb_n; t &= t - 1)
+          s_list[o++] = (uint16_t)(lane * 64 + __ffsll((long long)t) - 1);
+        wave_sync();
+      } else {
+        n_eff = kept;
+      }
+    }
+    if (absorbed) {
+      // The record grows by the run (positions s_list[0 .. absorb_n)): it
+      // keeps its bound, its members reach the run's last position, and X
+      // keeps only what is adjacent to the whole run.  If some vertex of
+      // that X is adjacent to all remaining candidates, no clique below is
+      // maximal and the record is dropped; otherwise it is held as the
+      // record's only child and goes on as a chained link (or is written
+      // to the frontier) below.  It is one child (R10), the candidates it
+      // replaces are not.
+      const uint32_t jl = s_list[absorb_n - 1];
+      const bool mine = (uint32_t)lane < absorb_n;
+      const uint32_t jm = mine ? s_list[lane] : 0;
+      long long add = mine ? (weighted ? (long long)wl[jm] : 1ll) : 0ll;
+      add = (long long)wave_sum((u64)add);
+      u64 xa = 0;  // lane w: word w of X and the run's rows
+      for (uint32_t w = 0; w < W; ++w) {
+        u64 v = mine ? rows[(u64)jm * W + w] : ~0ull;
+        for (int o2 = 32; o2 > 0; o2 >>= 1) v &= __shfl_xor(v, o2, 64);
+        if (lane == (int)w) xa = s_xw[w] & v;
+      }
+      stat(ST_ONCHIP, 8ull * W * absorb_n);
+      const u64 pnew = (lane < (int)W) ? (pw & gt_mask(lane, (int)jl)) : 0ull;
+      // exhaustive witness: each vertex of the new X, one per lane
+      const uint32_t xcn = __popcll(xa);
+      const uint32_t xo = wave_excl_scan(xcn, lane);
+      const uint32_t nx = __shfl(xo + xcn, 63, 64);
+      wave_sync();  // the list is no longer read
+      {
+        uint32_t o = xo;
+        for (u64 t = xa; t; t &= t - 1) s_list[o++] = (uint16_t)(lane * 64 + __ffsll((long long)t) - 1);
+      }
+      wave_sync();
+      if (lane < (int)W) s_cx[lane] = pnew;  // staging: P' for the broadcast reads below
+      wave_sync();
+      bool ext = false;
+      for (uint32_t b0 = 0; b0 < nx && !ext; b0 += 64) {
+        bool all = false;
+        if (b0 + lane < nx) {
+          const u64 *rx = rows + (u64)s_list[b0 + lane] * W;
+          u64 out = 0;
+#pragma unroll 4
+          for (uint32_t w = 0; w < W; ++w) out |= s_cx[w] & ~rx[w];
+          all = out == 0;
+        }
+        ext = __ballot(all) != 0;
+      }
+      stat(ST_ONCHIP, 8ull * W * nx);
+      wave_sync();
+      // children: the absorbed record replaces the nchild counted above
+      if (lane == 0) {
+        st[ST_CHILDREN] -= nchild - 1;
+        st[ST_PRUNED_NEW] = st[ST_MARK];
+      }
+      absorb_keep = !ext;
+      if (ext) {
+        stat(ST_PRUNED_NEW, 1);
+      } else {
+        if (lane < (int)W) {
+          s_cv[lane] = s_vw[lane] | s_pw[lane];  // members up to jl, candidates after
+          s_cx[lane] = xa;
+        }
+        if (lane == 0) {
+          s_cscore[wv] = p.score + add;
+          s_cbound[wv] = p.bound;
+          s_cj[wv] = (int)jl;
+          s_ccnt[wv] = nchild - absorb_n;
+        }
+        wave_sync();
+      }
+      n_eff = 0;  // nothing is built one by one
     }
     // kept children: the first is held back (in s_cv/s_cx) in case it
     // stays the only one; `spilled` once it has been written out
-    bool held = false, spilled = false;
+    bool held = absorb_keep, spilled = false;
     // the first vertex of X is the witness of most children (X' = X and the
     // earlier candidates, both adjacent to the child): its row is loaded
     // once per record, beside the children's rows instead of after them
@@ -1303,6 +1410,19 @@ struct Level {
   uint32_t maxw = 0;
 };
 
+// Frontier levels moved to host memory (the paper's virtual priority queue,
+// Section 5): the bottom of a query's level stack -- its shallowest, lowest
+// priority records -- with the arena range they occupied, which always
+// starts at offset 0, so a chunk returns to the same offsets.  Held in
+// ordinary (pageable) host memory: page-locking every chunk costs more than
+// the copies it would speed up.
+struct SpillChunk {
+  std::vector<Level> levels;
+  u64 n_hdr = 0, n_words = 0;  // header slots and words from offset 0
+  std::vector<CRec> hdr;
+  std::vector<u64> words;
+};
+
 struct QHost {
   bool active = false;  // the slot holds a query
   bool done = true;     // the query needs no more steps
@@ -1317,6 +1437,8 @@ struct QHost {
   uint32_t hdr_cap = 0;
   u64 word_cap = 0;
   uint64_t t_admit = 0, steps = 0, expand_ns = 0, launches = 0, peak_bytes = 0;
+  std::vector<std::shared_ptr<SpillChunk>> spill;  // spilled chunks, the last spilled last
+  uint64_t spilled_bytes = 0;
   // this step
   int plan = 0;  // 0 idle, 1 roots, 2 level
   uint32_t new_begin = 0;
@@ -1410,7 +1532,8 @@ struct Engine {
   size_t expand_lds = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::unique_ptr<StepLayout> L;
-  bool trace = false;  // NURI_TRACE=1: one line per step on stderr
+  // NURI_TRACE=n: one line on stderr every n steps (1: every step)
+  uint64_t trace = 0, trace_steps = 0;
   uint32_t rr = 0;     // round-robin start of the per-step planning
   std::vector<int> level_order;  // scratch of plan()
 
@@ -1422,7 +1545,7 @@ struct Engine {
   Engine(Graph &g_, const QueryOpts &o_, MemPool *pool = nullptr)
       : g(g_), o(o_), s(o_.stream ? o_.stream : g_.stream), mp(pool ? pool : &g_.pool) {
     const char *t = getenv("NURI_TRACE");
-    trace = t && t[0] == '1';
+    trace = t ? strtoull(t, nullptr, 10) : 0;
     const bool pinned = mp->fixed_base == nullptr;
     h_seed.pinned = h_step.pinned = h_res.pinned = h_ctr.pinned = h_k.pinned = pinned;
   }
@@ -1640,6 +1763,81 @@ struct Engine {
   u64 max_rec_children() const { return g.degeneracy; }
   u64 max_rec_words() const { return (u64)g.degeneracy * 2 * ((g.degeneracy + 63) / 64); }
 
+  // The frontier spill (not in a fixed region, where nothing may be
+  // allocated): when a query's arena is nearly full, its bottom levels --
+  // at least half of the used headers and words, never the top level --
+  // are copied to host memory and the levels above are moved
+  // down (their word offsets rebased).  Returns false when there is
+  // nothing to spill.
+  bool spill_bottom(uint32_t i) {
+    QHost &Q = qh[i];
+    if (mp->fixed_base || Q.stack.size() < 2) return false;
+    const Level &T = Q.stack.back();
+    const u64 used_h = (u64)T.begin + T.count, used_w = T.wend;
+    size_t m = 1;  // levels [0, m) go to the host
+    while (m + 1 < Q.stack.size() &&
+           ((u64)Q.stack[m].begin * 2 < used_h || Q.stack[m].wbegin * 2 < used_w))
+      ++m;
+    const u64 hshift = Q.stack[m].begin, wshift = Q.stack[m].wbegin;
+    if (hshift == 0 && wshift == 0) return false;
+    auto C = std::make_shared<SpillChunk>();
+    C->levels.assign(Q.stack.begin(), Q.stack.begin() + m);
+    C->n_hdr = hshift;
+    C->n_words = wshift;
+    C->hdr.resize(std::max<u64>(1, hshift));
+    C->words.resize(std::max<u64>(1, wshift));
+    QCfg &c = cfg[i];
+    NURI_HIP(hipMemcpyAsync(C->hdr.data(), c.hdr, hshift * sizeof(CRec), hipMemcpyDeviceToHost,
+                            s));
+    NURI_HIP(hipMemcpyAsync(C->words.data(), c.words, wshift * 8, hipMemcpyDeviceToHost, s));
+    // move the rest down; the source and destination may overlap, so
+    // through a scratch copy when they do
+    const u64 mh = used_h - hshift, mw = used_w - wshift;
+    auto move = [&](void *base, u64 shift_b, u64 bytes) {
+      if (!bytes) return;
+      char *b = (char *)base;
+      if (shift_b >= bytes) {
+        NURI_HIP(hipMemcpyAsync(b, b + shift_b, bytes, hipMemcpyDeviceToDevice, s));
+      } else {
+        PoolBuf<unsigned char> tmp;
+        tmp.alloc(*mp, bytes);
+        NURI_HIP(hipMemcpyAsync(tmp.p, b + shift_b, bytes, hipMemcpyDeviceToDevice, s));
+        NURI_HIP(hipMemcpyAsync(b, tmp.p, bytes, hipMemcpyDeviceToDevice, s));
+        NURI_HIP(hipStreamSynchronize(s));  // before the scratch returns to the pool
+      }
+    };
+    move(c.hdr, hshift * sizeof(CRec), mh * sizeof(CRec));
+    move(c.words, wshift * 8, mw * 8);
+    if (mh && wshift) {
+      const uint32_t blocks = (uint32_t)std::min<u64>((mh + 255) / 256, 4096);
+      hipLaunchKernelGGL(k_rebase, dim3(blocks), dim3(256), 0, s, c.hdr, mh, wshift);
+      NURI_HIP(hipGetLastError());
+    }
+    NURI_HIP(hipStreamSynchronize(s));
+    Q.stack.erase(Q.stack.begin(), Q.stack.begin() + m);
+    for (Level &L : Q.stack) {
+      L.begin -= (uint32_t)hshift;
+      L.wbegin -= wshift;
+      L.wend -= wshift;
+    }
+    Q.spilled_bytes += hshift * sizeof(CRec) + wshift * 8;
+    Q.spill.push_back(C);
+    return true;
+  }
+
+  // the stack is empty: the last spilled chunk comes back to its offsets
+  void reload(uint32_t i) {
+    QHost &Q = qh[i];
+    std::shared_ptr<SpillChunk> C = Q.spill.back();
+    Q.spill.pop_back();
+    QCfg &c = cfg[i];
+    NURI_HIP(hipMemcpyAsync(c.hdr, C->hdr.data(), C->n_hdr * sizeof(CRec), hipMemcpyHostToDevice,
+                            s));
+    NURI_HIP(hipMemcpyAsync(c.words, C->words.data(), C->n_words * 8, hipMemcpyHostToDevice, s));
+    NURI_HIP(hipStreamSynchronize(s));  // the host copy is freed below
+    Q.stack = C->levels;
+  }
+
   // plan this step for every live query into the staging block; returns
   // false when no query has work
   bool plan(uint32_t &nseg, uint32_t &nrseg, uint32_t &batch_ub, u64 &temp_need,
@@ -1673,6 +1871,11 @@ struct Engine {
         continue;
       }
       while (!Q.stack.empty() && Q.stack.back().count == 0) Q.stack.pop_back();
+      while (Q.stack.empty() && !Q.spill.empty()) {
+        // spilled levels are deeper than any unit subgraph: they go first
+        reload(i);
+        while (!Q.stack.empty() && Q.stack.back().count == 0) Q.stack.pop_back();
+      }
       const u64 share_c =
           std::max<u64>(std::min<u64>(step_share_c, Q.hdr_cap / 8), max_rec_children());
       const u64 share_w =
@@ -1691,8 +1894,19 @@ struct Engine {
       long long level_best = LLONG_MIN;
       for (const Level &Lv : Q.stack)
         if (Lv.count) level_best = std::max(level_best, Lv.max_bound);
-      const bool roots_first = o.priority == NURI_PRIORITY_BOUND && !Q.stack.empty() &&
-                               Q.cursor < end && rb[Q.cursor] > level_best;
+      bool roots_first = o.priority == NURI_PRIORITY_BOUND && !Q.stack.empty() &&
+                         Q.cursor < end && rb[Q.cursor] > level_best;
+      if (roots_first) {
+        // the next unit subgraph goes on top of the stack: with too little
+        // room above it, the bottom levels go to host memory first, and
+        // when that is not possible the levels are expanded this step
+        const u64 d = g.h_dplus[ro[Q.cursor]], w = d * 2 * ((d + 63) / 64);
+        auto fits = [&]() {
+          const Level &T = Q.stack.back();
+          return d <= Q.hdr_cap - ((u64)T.begin + T.count) && w <= Q.word_cap - T.wend;
+        };
+        if (!fits() && !(spill_bottom(i) && fits())) roots_first = false;
+      }
       if (Q.stack.empty() || roots_first) {
         if (Q.cursor >= end) {
           Q.done = true;
@@ -1733,11 +1947,18 @@ struct Engine {
         any = true;
         continue;
       }
+      // one record of the top level must always fit; with less room than
+      // one step's share left, the bottom levels go to host memory
+      {
+        const Level &T0 = Q.stack.back();
+        const u64 rc = std::max<u64>(1, T0.maxcc), rw = rc * 2 * std::max(1u, T0.maxw);
+        const u64 fh = Q.hdr_cap - (u64)(T0.begin + T0.count), fw = Q.word_cap - T0.wend;
+        if (fh < std::max(rc, share_c) || fw < std::max(rw, share_w)) spill_bottom(i);
+      }
       const Level &Top = Q.stack.back();
       const u64 free_h = Q.hdr_cap - (u64)(Top.begin + Top.count);
       const u64 free_w = Q.word_cap - Top.wend;
       u64 lim_c = std::min<u64>(cap_c, free_h), lim_w = std::min<u64>(cap_w, free_w);
-      // one record of the top level must always fit
       const u64 rec_c = std::max<u64>(1, Top.maxcc), rec_w = rec_c * 2 * std::max(1u, Top.maxw);
       if (free_h < rec_c || free_w < rec_w) {
         fail(i, NURI_EBUDGET, "frontier budget exhausted");
@@ -2003,7 +2224,7 @@ struct Engine {
     if (!plan(nseg, nrseg, batch_ub, temp_need, mseg, mrseg)) return false;
     const uint64_t t1 = trace ? now_ns() : 0;
     step(nseg, nrseg, batch_ub, temp_need, mseg, mrseg);
-    if (trace) {
+    if (trace && ++trace_steps % trace == 0) {
       uint32_t live = 0;
       for (auto &Q : qh) live += Q.active && !Q.done;
       size_t depth = 0;
@@ -2062,8 +2283,10 @@ struct Engine {
     st.expand_ns = Q.expand_ns;
     st.wall_ns = now_ns() - Q.t_admit;
     st.ties_at_k = ties_at_k(res.score, Q.k);
+    st.spilled_bytes = Q.spilled_bytes;
     Q.active = false;
     Q.stack.clear();
+    Q.spill.clear();
     tk[i]->score.release();
     tk[i]->len.release();
     tk[i]->ids.release();

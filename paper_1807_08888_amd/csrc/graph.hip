@@ -181,7 +181,13 @@ uint64_t Graph::device_bytes() const {
          bm_off.bytes() + bm.bytes() + wplus.bytes() + best.bytes() +
          orow.bytes() + lcol.bytes() + lew.bytes() + loff.bytes() + lab_vert.bytes() +
          root_order[0].bytes() + root_order[1].bytes() + ooff.bytes() + oplus.bytes() +
-         wloc.bytes();
+         wloc.bytes() + hop_index_bytes();
+}
+
+uint64_t Graph::hop_index_bytes() const {
+  uint64_t b = 0;
+  for (const auto &h : hidx) b += h.bytes();
+  return b;
 }
 
 template <class T>

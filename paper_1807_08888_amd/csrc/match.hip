@@ -2,7 +2,8 @@
 //
 // The paper's basic computational model (Algorithm 1, Section 3.2) with the
 // subgraph-isomorphism user functions of Section 4.3, scored by the sum of
-// matched edge weights:
+// matched edge weights, or by the sum of the matched vertices' degrees (the
+// paper's example, bounded with its multi-hop index; see below):
 //
 //   targeted expansion  a partial match grows by one pattern vertex at a
 //                       time (in a fixed matching order), taking only data
@@ -16,6 +17,11 @@
 //   priority            (matched vertices, bound): the deepest level first,
 //                       highest bound first within it;
 //   dominated           bound < score of the k-th result (strict).
+//
+// Degree score: a unit subgraph {v} scores deg(v), a child adds the
+// degree of its new vertex, and the bound is the score plus, for every
+// unmatched pattern vertex u, the multi-hop index entry of the seed
+// mu(order[0]) for label(u) at hop(u), u's distance from order[0].
 //
 // Matches are non-induced.  Embeddings with the same image are one result:
 // symmetry-breaking constraints mu(i) < mu(j), for j in the orbit of i under
@@ -44,6 +50,12 @@ struct MRec {  // 64 B partial match
 };
 static_assert(sizeof(MRec) == 64, "match record must stay 64 bytes");
 
+// mu[b] for a pattern vertex b known only at run time.  Records being
+// expanded are read in place from the batch (one per wavefront, so the
+// reads are uniform): a register copy indexed at run time would live in
+// per-lane scratch memory.
+__device__ inline uint32_t mu_at(const MRec &r, uint32_t b) { return r.mu[b]; }
+
 struct MPlan {  // per query pattern plan
   uint32_t q, k;
   uint8_t label[QM];
@@ -53,6 +65,9 @@ struct MPlan {  // per query pattern plan
   uint8_t sb_lt[QM];  // sb_lt[a] bit b: a result needs mu(a) < mu(b)
   int32_t pmx[QM][QM];  // max data edge weight for the label pair of pattern edge {a,b}
   long long rest0;    // bound contribution of edges not touching order[0], all unmatched
+  uint8_t hop[QM];    // distance from order[0] in the pattern
+  uint32_t degree;    // 1: degree score, 0: edge-weight score
+  uint32_t max_hop;
 };
 
 struct MView {
@@ -62,7 +77,17 @@ struct MView {
   const uint32_t *loff;
   const int32_t *best;
   const uint32_t *lab_vert;
+  const int32_t *hidx[QM - 1];  // multi-hop index, per hop: [v * 16 + label]
 };
+
+__device__ inline long long vdeg(const MView &m, uint32_t v) {
+  return (long long)(m.orow[v + 1] - m.orow[v]);
+}
+
+// multi-hop index entry of seed v for label l within h >= 1 hops
+__device__ inline int32_t hop_entry(const MView &m, uint32_t h, uint32_t v, uint32_t l) {
+  return m.hidx[h - 1][(u64)v * NURI_MAX_LABELS + l];
+}
 
 struct MCfg {  // per query, per step
   MRec *hdr;
@@ -124,7 +149,7 @@ __device__ inline uint32_t child_bound(const MView &m, const MPlan &P, const MRe
   for (uint32_t i = 0; i < r.depth; ++i) {
     const uint32_t b = P.order[i];
     if (P.nbr[a] >> b & 1) {
-      uint32_t s = seg_len(m, r.mu[b], P.label[a]);
+      uint32_t s = seg_len(m, mu_at(r, b), P.label[a]);
       best = s < best ? s : best;
     }
   }
@@ -145,20 +170,31 @@ __global__ void k_match_roots(MView m, const MPlan *plans, const uint64_t *lab_o
   for (u64 i = b + blockIdx.x * (u64)blockDim.x + threadIdx.x; i < e;
        i += (u64)gridDim.x * blockDim.x) {
     const uint32_t v = m.lab_vert[i];
-    long long bound = P.rest0;
+    long long bound = P.rest0, score = 0;
     bool ok = true;
-    for (uint32_t u = 0; u < P.q; ++u)
-      if (P.nbr[a0] >> u & 1) {
-        int32_t w = m.best[(u64)v * NURI_MAX_LABELS + P.label[u]];
-        ok &= w > 0;
-        bound += w;
-      }
+    if (P.degree) {
+      score = vdeg(m, v);
+      bound = score;
+      for (uint32_t u = 0; u < P.q; ++u)
+        if (u != a0) {
+          const int32_t x = hop_entry(m, P.hop[u], v, P.label[u]);
+          ok &= x > 0;
+          bound += x;
+        }
+    } else {
+      for (uint32_t u = 0; u < P.q; ++u)
+        if (P.nbr[a0] >> u & 1) {
+          int32_t w = m.best[(u64)v * NURI_MAX_LABELS + P.label[u]];
+          ok &= w > 0;
+          bound += w;
+        }
+    }
     if (!ok) continue;
     MRec r;
-    r.score = 0;
+    r.score = score;
     r.bound = bound;
-    for (int t = 0; t < QM; ++t) r.mu[t] = 0;
-    r.mu[a0] = v;
+#pragma unroll
+    for (int t = 0; t < QM; ++t) r.mu[t] = (a0 == (uint32_t)t) ? v : 0u;
     r.qid = q;
     r.depth = 1;
     r.nchild = child_bound(m, P, r);
@@ -309,7 +345,7 @@ __device__ inline MWork match_work(const MView &m, const MPlan &P, const MRec &p
   for (uint32_t i = 0; i < p.depth; ++i) {
     const uint32_t b = P.order[i];
     if (P.nbr[w.a] >> b & 1) {
-      uint32_t s = seg_len(m, p.mu[b], w.la);
+      uint32_t s = seg_len(m, mu_at(p, b), w.la);
       if (s < w.alen) {
         w.alen = s;
         w.anchor = b;
@@ -317,14 +353,19 @@ __device__ inline MWork match_work(const MView &m, const MPlan &P, const MRec &p
     }
   }
   if (w.anchor == QM) w.alen = 0;  // cannot happen for a connected pattern
-  const uint32_t av = w.anchor == QM ? 0 : p.mu[w.anchor];
+  const uint32_t av = w.anchor == QM ? 0 : mu_at(p, w.anchor);
   w.base = m.orow[av] + m.loff[(u64)av * 17 + w.la];
   w.last = p.depth + 1 == P.q;
-  // the anchor's own bound term is replaced by the candidate's weight
   w.bound0 = p.bound;
+  if (P.degree) {
+    // a's index term is replaced by the candidate's degree
+    w.bound0 -= hop_entry(m, P.hop[w.a], mu_at(p, P.order[0]), w.la);
+    return w;
+  }
+  // the anchor's own bound term is replaced by the candidate's weight
   for (uint32_t i = 0; i < p.depth; ++i) {
     const uint32_t b = P.order[i];
-    if (P.nbr[w.a] >> b & 1) w.bound0 -= m.best[(u64)p.mu[b] * NURI_MAX_LABELS + w.la];
+    if (P.nbr[w.a] >> b & 1) w.bound0 -= m.best[(u64)mu_at(p, b) * NURI_MAX_LABELS + w.la];
   }
   for (uint32_t u = 0; u < P.q; ++u)
     if ((P.nbr[w.a] >> u & 1) && P.pos[u] > p.depth) w.bound0 -= P.pmx[w.a][u];
@@ -343,6 +384,7 @@ __device__ inline void match_walk(const MView &m, const MPlan &P, const MRec &p,
                                   const MCfg &cf, MStep *ms, StepHdr *hdr, Cand *cands,
                                   uint32_t *cand_ids, uint32_t cand_cap, int lane, MTally &st) {
   const uint32_t a = w.a, la = w.la, anchor = w.anchor;
+  const bool dg = P.degree != 0;
   for (uint32_t t0 = t_begin; t0 < t_end; t0 += 64) {
     const uint32_t t = t0 + lane;
     bool ok = t < t_end;
@@ -350,13 +392,13 @@ __device__ inline void match_walk(const MView &m, const MPlan &P, const MRec &p,
     long long score2 = p.score, bound2 = w.bound0;
     if (ok) {
       c = m.lcol[w.base + t];
-      const int32_t wa = m.lew[w.base + t];
+      const long long wa = dg ? vdeg(m, c) : (long long)m.lew[w.base + t];
       score2 += wa;
       bound2 += wa;
       // injectivity and symmetry breaking against every matched vertex
       for (uint32_t i = 0; i < p.depth && ok; ++i) {
         const uint32_t b = P.order[i];
-        const uint32_t mb = p.mu[b];
+        const uint32_t mb = mu_at(p, b);
         ok = c != mb;
         if ((P.sb_lt[a] >> b & 1) && !(c < mb)) ok = false;
         if ((P.sb_lt[b] >> a & 1) && !(mb < c)) ok = false;
@@ -365,21 +407,23 @@ __device__ inline void match_walk(const MView &m, const MPlan &P, const MRec &p,
       for (uint32_t i = 0; i < p.depth && ok; ++i) {
         const uint32_t b = P.order[i];
         if (b == anchor || !(P.nbr[a] >> b & 1)) continue;
-        long long at = seg_find(m, p.mu[b], la, c);
+        long long at = seg_find(m, mu_at(p, b), la, c);
         if (at < 0) {
           ok = false;
-        } else {
+        } else if (!dg) {
           const int32_t wt = m.lew[at];
           score2 += wt;
           bound2 += wt;
         }
       }
       // edges from a to unmatched pattern vertices: one-hop bound from c
+      // (under the degree score only the test that c has a neighbour of
+      // each needed label)
       for (uint32_t u = 0; u < P.q && ok; ++u)
         if ((P.nbr[a] >> u & 1) && P.pos[u] > p.depth) {
           const int32_t wt = m.best[(u64)c * NURI_MAX_LABELS + P.label[u]];
           if (wt <= 0) ok = false;
-          bound2 += wt;
+          if (!dg) bound2 += wt;
         }
     }
     const bool valid = t < t_end;
@@ -394,7 +438,8 @@ __device__ inline void match_walk(const MView &m, const MPlan &P, const MRec &p,
     uint32_t nch = 0;
     if (keep) {
       ch = p;
-      ch.mu[a] = c;
+#pragma unroll
+      for (int t = 0; t < QM; ++t) ch.mu[t] = (a == (uint32_t)t) ? c : p.mu[t];
       ch.score = score2;
       ch.bound = bound2;
       ch.depth = p.depth + 1;
@@ -442,7 +487,9 @@ __device__ inline void match_walk(const MView &m, const MPlan &P, const MRec &p,
           cd.len = P.q;
           cands[slot] = cd;
           uint32_t *dst = cand_ids + (u64)slot * QM;
-          for (uint32_t i = 0; i < P.q; ++i) dst[i] = (i == a) ? c : p.mu[i];
+#pragma unroll
+          for (int i = 0; i < QM; ++i)
+            if ((uint32_t)i < P.q) dst[i] = ((uint32_t)i == a) ? c : p.mu[i];
           st.offered++;
         } else {
           atomicAdd(&ms[q].overflow, 1u);
@@ -479,7 +526,7 @@ __global__ void __launch_bounds__(64 * kMatchWaves)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t rec = blockIdx.x * kMatchWaves + wv;
   if (rec >= hdr->batch_count) return;
-  const MRec p = batch[rec];
+  const MRec &p = batch[rec];
   const uint32_t q = p.qid;
   const MPlan &P = plans[q];
   const MCfg cf = cfg[q];
@@ -538,7 +585,7 @@ __global__ void __launch_bounds__(64 * kMatchWaves)
       if (big_base[mid] <= c) lo = mid;
       else hi = mid;
     }
-    const MRec p = batch[big_rec[lo]];
+    const MRec &p = batch[big_rec[lo]];
     const uint32_t q = p.qid;
     const MPlan &P = plans[q];
     const MCfg cf = cfg[q];
@@ -619,9 +666,11 @@ void plan_pattern(const Graph &g, const nuri_pattern &pt, uint32_t k, MPlan &P) 
   const uint32_t q = pt.q;
   if (q < 2 || q > (uint32_t)QM) throw Error{NURI_EINVAL, "pattern size must be 2..8"};
   if (k == 0) throw Error{NURI_EINVAL, "k must be >= 1"};
+  if (pt.score > NURI_MATCH_DEGREE) throw Error{NURI_EINVAL, "unknown match score"};
   memset(&P, 0, sizeof(P));
   P.q = q;
   P.k = k;
+  P.degree = pt.score == NURI_MATCH_DEGREE;
   uint8_t adj[QM][QM] = {};
   for (uint32_t a = 0; a < q; ++a) {
     if (pt.label[a] >= NURI_MAX_LABELS) throw Error{NURI_EINVAL, "pattern label out of range"};
@@ -692,6 +741,25 @@ void plan_pattern(const Graph &g, const nuri_pattern &pt, uint32_t k, MPlan &P) 
     used |= 1u << pick;
   }
   for (uint32_t i = 0; i < q; ++i) P.pos[P.order[i]] = (uint8_t)i;
+  // distances from order[0] (breadth-first over the pattern)
+  {
+    uint32_t reached = 1u << first, frontier = reached;
+    P.hop[first] = 0;
+    P.max_hop = 1;
+    for (uint32_t h = 1; frontier; ++h) {
+      uint32_t nxt = 0;
+      for (uint32_t a = 0; a < q; ++a)
+        if (frontier >> a & 1) nxt |= P.nbr[a];
+      nxt &= ~reached;
+      for (uint32_t a = 0; a < q; ++a)
+        if (nxt >> a & 1) {
+          P.hop[a] = (uint8_t)h;
+          P.max_hop = std::max(P.max_hop, h);
+        }
+      reached |= nxt;
+      frontier = nxt;
+    }
+  }
   // label-pair maxima of the pattern edges, and the bound part of the
   // edges that do not touch order[0]
   P.rest0 = 0;
@@ -728,6 +796,7 @@ struct MQHost {
   long long top_seen = LLONG_MIN;  // best score ever offered (bounds the top-k)
   uint32_t hdr_cap = 0;
   uint64_t t_admit = 0, steps = 0, launches = 0, expand_ns = 0, peak_bytes = 0;
+  uint64_t index_ns = 0;  // multi-hop index built for this query
   int plan = 0;
   uint32_t new_begin = 0;
   int seg = -1;
@@ -817,6 +886,7 @@ struct MatchEngine {
     v.loff = g.loff.p;
     v.best = g.best.p;
     v.lab_vert = g.lab_vert.p;
+    for (int h = 0; h < QM - 1; ++h) v.hidx[h] = g.hidx[h].p;
     return v;
   }
   StepHdr *sh() { return (StepHdr *)h_step.p; }
@@ -911,8 +981,15 @@ struct MatchEngine {
   void admit(uint32_t i, const nuri_pattern &pt, uint32_t k, u64 bytes = 0) {
     MPlan P;
     plan_pattern(g, pt, k, P);  // throws on an invalid pattern
+    uint64_t index_ns = 0;
+    if (P.degree) {
+      const uint64_t t0 = now_ns();
+      ensure_hop_index(g, P.max_hop, s);
+      index_ns = now_ns() - t0;
+    }
     MQHost &Q = qh[i];
     Q = MQHost{};
+    Q.index_ns = index_ns;
     Q.active = true;
     Q.k = k;
     const u64 cap = arena_records(bytes ? bytes : arena_bytes);
@@ -1300,6 +1377,7 @@ struct MatchEngine {
     st.expand_ns = Q.expand_ns;
     st.wall_ns = now_ns() - Q.t_admit;
     st.ties_at_k = ties_at_k(res.score, Q.k);
+    st.index_ns = Q.index_ns;
     Q.active = false;
     Q.stack.clear();
     tk[i]->score.release();

@@ -213,9 +213,19 @@ struct Graph {
   DevBuf<uint32_t> oplus;
   DevBuf<int32_t> wloc;
 
+  // multi-hop (label, hop) max-degree index for the degree score of
+  // matching, built on first use up to the hops a pattern needs:
+  // hidx[h-1][v * 16 + l] = largest degree of a label-l vertex 1..h hops
+  // from v (0: none).  Arrays of hops already built are never replaced.
+  std::mutex hidx_mu;
+  DevBuf<int32_t> hidx[NURI_MAX_PATTERN - 1];
+  uint32_t hidx_hops = 0;
+  uint64_t hidx_ns = 0;  // time spent building it
+
   MemPool pool;  // query workspaces kept between queries
 
   uint64_t device_bytes() const;
+  uint64_t hop_index_bytes() const;
   Graph() = default;
   Graph(const Graph &) = delete;
   Graph &operator=(const Graph &) = delete;
@@ -225,6 +235,10 @@ struct Graph {
 };
 
 Graph *load_graph(const nuri_csr *csr, hipStream_t stream);
+
+// builds the multi-hop index of g up to `hops` hops (1..NURI_MAX_PATTERN-1)
+// if it is not there yet; synchronous on stream s
+void ensure_hop_index(Graph &g, uint32_t hops, hipStream_t s);
 
 // ------------------------------------------------------------------
 // results

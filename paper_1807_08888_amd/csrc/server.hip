@@ -31,6 +31,7 @@ struct Served {
   int wf = 0;
   std::vector<uint8_t> labels;
   std::vector<uint32_t> edges;
+  uint32_t mscore = 0;  // nuri_match_score
   uint64_t t_submit = 0;
   uint64_t arena = 0;     // frontier bytes to admit it with (0: the base arena)
   uint32_t restarts = 0;  // times it outgrew its arena and was started again
@@ -122,7 +123,7 @@ struct Server {
           uint32_t i = 0;
           while (m_ticket[i]) ++i;
           nuri_pattern p{(uint32_t)q.labels.size(), (uint32_t)(q.edges.size() / 2),
-                         q.labels.data(), q.edges.data()};
+                         q.labels.data(), q.edges.data(), q.mscore};
           ms->admit(i, p, q.k, q.arena);
           m_ticket[i] = q.ticket;
           m_query[i] = q;
@@ -284,6 +285,7 @@ int nuri_server_submit(nuri_server *srv, const nuri_query *q, uint64_t *ticket) 
     }
     item.labels.assign(q->p->label, q->p->label + q->p->q);
     item.edges.assign(q->p->edges, q->p->edges + 2 * q->p->n_edges);
+    item.mscore = q->p->score;
   } else if (q->kind != 0) {
     set_error("query kind must be 0 (clique) or 1 (match)");
     return NURI_EINVAL;

@@ -19,6 +19,7 @@ ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EBUDGET", -4: "EDEVICE", -5: "ETIMEOU
 SCORE_SIZE = 0
 SCORE_VERTEX_WEIGHT = 1
 PRIORITY_DEPTH, PRIORITY_BOUND, PRIORITY_PAPER, PRIORITY_NONE = 0, 1, 2, 3
+MATCH_EDGE_WEIGHT, MATCH_DEGREE = 0, 1
 
 
 class NuriError(RuntimeError):
@@ -43,7 +44,8 @@ class _GraphInfo(ctypes.Structure):
 
 class _Pattern(ctypes.Structure):
     _fields_ = [("q", ctypes.c_uint32), ("n_edges", ctypes.c_uint32),
-                ("label", ctypes.c_void_p), ("edges", ctypes.c_void_p)]
+                ("label", ctypes.c_void_p), ("edges", ctypes.c_void_p),
+                ("score", ctypes.c_uint32)]
 
 
 class _Opts(ctypes.Structure):
@@ -67,7 +69,8 @@ class _View(ctypes.Structure):
 
 STAT_FIELDS = ("steps", "popped", "expanded", "children", "pruned_at_pop", "pruned_at_creation",
                "leaves", "offered", "frontier_peak_bytes", "logical_bytes", "expand_launches",
-               "expand_ns", "wall_ns", "ties_at_k", "restarts", "onchip_bytes")
+               "expand_ns", "wall_ns", "ties_at_k", "restarts", "onchip_bytes",
+               "spilled_bytes", "index_ns")
 
 
 class _Stats(ctypes.Structure):
@@ -80,6 +83,8 @@ SIGNATURES = {
     "nuri_load_graph": (ctypes.c_int, [ctypes.POINTER(_CSR), _VP, ctypes.POINTER(_VP)]),
     "nuri_free_graph": (None, [_VP]),
     "nuri_graph_get_info": (ctypes.c_int, [_VP, ctypes.POINTER(_GraphInfo)]),
+    "nuri_graph_hop_index": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP,
+                                            ctypes.POINTER(ctypes.c_uint64)]),
     "nuri_topk_cliques": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_int,
                                          ctypes.POINTER(_Opts), ctypes.POINTER(_VP)]),
     "nuri_topk_match": (ctypes.c_int, [_VP, ctypes.POINTER(_Pattern), ctypes.c_uint32,
@@ -202,6 +207,16 @@ class Graph:
         _check(lib().nuri_graph_get_info(self._h, ctypes.byref(i)))
         return {f: getattr(i, f) for f, _ in _GraphInfo._fields_}
 
+    def hop_index(self, hops: int, copy: bool = True):
+        """(int32 [hops, n, 16] multi-hop index or None when copy is False,
+        build ns of this call) (nuri_graph_hop_index)."""
+        n = int(self.info()["n"])
+        out = np.zeros((hops, n, 16), np.int32) if copy else None
+        ns = ctypes.c_uint64(0)
+        _check(lib().nuri_graph_hop_index(self._h, hops, out.ctypes.data if copy else None,
+                                          ctypes.byref(ns)))
+        return out, int(ns.value)
+
     def close(self):
         if getattr(self, "_h", None):
             lib().nuri_free_graph(self._h)
@@ -246,17 +261,28 @@ def topk_cliques_noalloc(graph: Graph, k: int, weight_fn: int = SCORE_SIZE, **op
     return items, {f: int(getattr(st, f)) for f in STAT_FIELDS}
 
 
-def _pattern(labels: Sequence[int], edges: Sequence[Tuple[int, int]]):
+def _match_score(score) -> int:
+    if score in ("edge", MATCH_EDGE_WEIGHT):
+        return MATCH_EDGE_WEIGHT
+    if score in ("degree", MATCH_DEGREE):
+        return MATCH_DEGREE
+    raise ValueError("match score must be 'edge' or 'degree'")
+
+
+def _pattern(labels: Sequence[int], edges: Sequence[Tuple[int, int]], score="edge"):
     lb = np.ascontiguousarray(labels, np.uint8)
     ed = np.ascontiguousarray(np.array(edges, dtype=np.uint32).reshape(-1), np.uint32)
-    p = _Pattern(len(lb), len(edges), lb.ctypes.data, ed.ctypes.data if len(edges) else None)
+    p = _Pattern(len(lb), len(edges), lb.ctypes.data, ed.ctypes.data if len(edges) else None,
+                 _match_score(score))
     return p, (lb, ed)
 
 
 def topk_match(graph: Graph, labels: Sequence[int], edges: Sequence[Tuple[int, int]], k: int,
-               **opts) -> Result:
-    """Top-k labelled matches (nuri_topk_match)."""
-    p, keep = _pattern(labels, edges)
+               score="edge", **opts) -> Result:
+    """Top-k labelled matches (nuri_topk_match).  score: "edge" (sum of the
+    matched edge weights) or "degree" (sum of the matched vertices'
+    degrees, bounded with the multi-hop index)."""
+    p, keep = _pattern(labels, edges, score)
     out = _VP()
     o = _opts(**opts)
     _check(lib().nuri_topk_match(graph._h, ctypes.byref(p), k, ctypes.byref(o), ctypes.byref(out)))
@@ -264,14 +290,15 @@ def topk_match(graph: Graph, labels: Sequence[int], edges: Sequence[Tuple[int, i
 
 
 def _queries(queries):
-    """queries: dicts {"kind": "clique", "k", "weight_fn"} or {"kind": "match", "k", "labels", "edges"}."""
+    """queries: dicts {"kind": "clique", "k", "weight_fn"} or
+    {"kind": "match", "k", "labels", "edges", optional "score"}."""
     qs = (_Query * len(queries))()
     keep = []
     for i, q in enumerate(queries):
         if q["kind"] == "clique":
             qs[i] = _Query(0, q["k"], q.get("weight_fn", SCORE_SIZE), None)
         else:
-            p, arrs = _pattern(q["labels"], q["edges"])
+            p, arrs = _pattern(q["labels"], q["edges"], q.get("score", "edge"))
             keep.append((p, arrs))
             qs[i] = _Query(1, q["k"], 0, ctypes.pointer(p))
     return qs, keep

@@ -379,3 +379,45 @@ def test_many_queries_with_the_smallest_arenas(nuri):
     for i in (0, 1, 2):
         want, _ = oracle.topk_cliques(g, ks[i], weighted=True)
         assert small[i].items == want, i
+
+
+def test_frontier_spill_to_host_is_exact(nuri):
+    """256 vertex-weighted queries share the smallest budget (64 MiB), so
+    each gets a 256 KiB arena, and run best-first (the BOUND order keeps
+    partly expanded levels around, as the paper's priority queue does), so
+    the searches with the largest frontiers outgrow their arenas: the bottom
+    levels go to host memory and come back when the levels above are done
+    (the paper's virtual priority queue).  Every result equals the same
+    batch under the default budget, and the oracle on three of them.  A
+    deadline bounds both runs."""
+    g = synth.rmat(13)
+    synth.add_vertex_weights(g)
+    nq = 256
+    ks = [synth.log_uniform_k(i, 300) for i in range(nq)]
+    qs = [{"kind": "clique", "k": k, "weight_fn": 1} for k in ks]
+    limit = 150 * 10 ** 9
+    G = nuri.Graph.from_synth(g)
+    try:
+        _case(f"{nq} weighted queries, R-MAT scale 13, best-first, default budget")
+        full = nuri.topk_batch(G, qs, priority=nuri.PRIORITY_BOUND, deadline_ns=limit)
+        peaks = sorted(r.stats["frontier_peak_bytes"] for r in full)
+        arena = (64 << 20) // nq
+        _case(f"frontier peaks: max {peaks[-1]}, median {peaks[nq // 2]}, "
+              f"above the {arena}-byte arena: {sum(p > arena for p in peaks)}")
+        assert peaks[-1] > arena, "no query outgrows its arena: the test would not spill"
+        _case(f"{nq} weighted queries, R-MAT scale 13, best-first, 64 MiB budget: spills")
+        small = nuri.topk_batch(G, qs, frontier_budget_bytes=64 << 20,
+                                priority=nuri.PRIORITY_BOUND, deadline_ns=limit)
+    finally:
+        G.close()
+    for i in range(len(qs)):
+        assert small[i].items == full[i].items, i
+    # (the default budget spills too under this order: an arena's header
+    # and word parts fill at different rates, and either one spills)
+    _case(f"spilled bytes: {sum(r.stats['spilled_bytes'] for r in small)} "
+          f"over {sum(r.stats['spilled_bytes'] > 0 for r in small)} queries; default budget: "
+          f"{sum(r.stats['spilled_bytes'] for r in full)}")
+    assert sum(r.stats["spilled_bytes"] > 0 for r in small) > nq // 2
+    for i in (0, 1, 2):
+        want, _ = oracle.topk_cliques(g, ks[i], weighted=True)
+        assert small[i].items == want, i
