@@ -1,8 +1,9 @@
 """CPU oracle for top-k subgraph discovery -- test infrastructure only.
 
 A plain, slow rendering of the paper's Algorithm 1 (Section 3.2) for top-k
-maximal cliques and top-k labelled subgraph matching, in oracle.c, plus this
-ctypes loader.  Only the tests, the smoke check and the benchmark's
+maximal cliques and top-k labelled subgraph matching, and of Algorithm 2
+(Section 3.3) and its definition for top-k frequent patterns, in oracle.c,
+plus this ctypes loader.  Only the tests, the smoke check and the benchmark's
 CPU-baseline leg may import it; the GPU engine never does, and the two share
 no code.
 """
@@ -49,6 +50,14 @@ def _load():
     lib.oracle_hop_index.argtypes = [u32, vp, vp, vp, u32, u32, vp]
     lib.oracle_match_root_bounds.restype = ctypes.c_int64
     lib.oracle_match_root_bounds.argtypes = [u32, vp, vp, vp, vp, u32, u32, vp, u32, vp, i32, vp]
+    lib.oracle_topk_patterns.restype = ctypes.c_int64
+    lib.oracle_topk_patterns.argtypes = [u32, vp, vp, vp, u32, u32, vp, vp, vp]
+    lib.oracle_topk_patterns_definition.restype = ctypes.c_int64
+    lib.oracle_topk_patterns_definition.argtypes = [u32, vp, vp, vp, u32, u32, vp, vp]
+    lib.oracle_pattern_support.restype = ctypes.c_int64
+    lib.oracle_pattern_support.argtypes = [u32, vp, vp, vp, u32, vp]
+    lib.oracle_min_dfs_code.restype = ctypes.c_int64
+    lib.oracle_min_dfs_code.argtypes = [u32, vp, u32, vp, vp]
     lib.oracle_vertex_order.argtypes = [u32, vp, vp, i32, vp]
     lib.oracle_core_numbers.argtypes = [u32, vp, vp, vp]
     lib.oracle_set_work_limit.argtypes = [u64]
@@ -209,6 +218,76 @@ def match_root_bounds(g, labels, edges, n_labels: int = 16, score: str = "edge")
     if first < 0:
         raise ValueError("invalid pattern")
     return int(first), out
+
+
+PATTERN_STATS = ("popped", "expanded", "children", "pruned_at_creation", "pruned_at_pop",
+                 "non_minimal", "groups")
+
+
+def _codes(codes, count, M):
+    return [tuple(tuple(int(x) for x in codes[(r * M + t) * 4:(r * M + t) * 4 + 4])
+                  for t in range(M)) for r in range(count)]
+
+
+def topk_patterns(g, n_edges: int, k: int):
+    """Top-k frequent patterns with n_edges edges by Algorithm 2.
+
+    Returns ([(support, code)], stats); code = ((i, j, L(i), L(j)), ...),
+    the pattern's minimum DFS code.
+    """
+    lib = _load()
+    rp, col = _arr(g.row_ptr, np.uint64), _arr(g.col, np.uint32)
+    lab = _arr(g.vertex_label, np.uint8)
+    sup = np.zeros(k, np.uint64)
+    codes = np.zeros(k * n_edges * 4, np.uint32)
+    stats = np.zeros(8, np.uint64)
+    c = lib.oracle_topk_patterns(g.n, rp.ctypes.data, col.ctypes.data, lab.ctypes.data, n_edges,
+                                 k, sup.ctypes.data, codes.ctypes.data, stats.ctypes.data)
+    if c < 0:
+        raise ValueError("bad arguments")
+    res = [(int(sup[r]), code) for r, code in enumerate(_codes(codes, c, n_edges))]
+    return res, dict(zip(PATTERN_STATS, (int(x) for x in stats[:7])))
+
+
+def topk_patterns_definition(g, n_edges: int, k: int):
+    """The same top-k from the definition (every connected set of n_edges
+    data edges); graphs of at most 64 edges."""
+    lib = _load()
+    rp, col = _arr(g.row_ptr, np.uint64), _arr(g.col, np.uint32)
+    lab = _arr(g.vertex_label, np.uint8)
+    sup = np.zeros(k, np.uint64)
+    codes = np.zeros(k * n_edges * 4, np.uint32)
+    c = lib.oracle_topk_patterns_definition(g.n, rp.ctypes.data, col.ctypes.data, lab.ctypes.data,
+                                            n_edges, k, sup.ctypes.data, codes.ctypes.data)
+    if c < 0:
+        raise ValueError("bad arguments or graph too large")
+    return [(int(sup[r]), code) for r, code in enumerate(_codes(codes, c, n_edges))]
+
+
+def pattern_support(g, code) -> int:
+    """Minimum image-based support of the pattern given by a DFS code."""
+    lib = _load()
+    rp, col = _arr(g.row_ptr, np.uint64), _arr(g.col, np.uint32)
+    lab = _arr(g.vertex_label, np.uint8)
+    flat = _arr(np.array(code, dtype=np.uint32).reshape(-1), np.uint32)
+    f = lib.oracle_pattern_support(g.n, rp.ctypes.data, col.ctypes.data, lab.ctypes.data,
+                                   len(code), flat.ctypes.data)
+    if f < 0:
+        raise ValueError("bad code")
+    return int(f)
+
+
+def min_dfs_code(labels, edges):
+    """Minimum DFS code of a small connected labelled graph."""
+    lib = _load()
+    pl = _arr(labels, np.uint8)
+    pe = _arr(np.array(edges, dtype=np.uint32).reshape(-1), np.uint32)
+    out = np.zeros(len(edges) * 4, np.uint32)
+    r = lib.oracle_min_dfs_code(len(labels), pl.ctypes.data, len(edges), pe.ctypes.data,
+                                out.ctypes.data)
+    if r < 0:
+        raise ValueError("bad or disconnected pattern")
+    return _codes(out, 1, len(edges))[0]
 
 
 def vertex_order(g, order: int = 1) -> np.ndarray:

@@ -10,7 +10,10 @@
  *   - top-k labelled subgraph matching (Section 2.1 "Subgraph Isomorphism",
  *     Section 4.3), scored by the sum of matched edge weights, or by the
  *     sum of the degrees of the matched vertices with the multi-hop
- *     (label, hop) max-degree index of Section 4.3 (Listing 3).
+ *     (label, hop) max-degree index of Section 4.3 (Listing 3), and
+ *   - top-k frequent pattern mining (Section 2.1 "Pattern Mining",
+ *     Section 3.3 Algorithm 2 with pattern-oriented expansion, Listing 2):
+ *     by its definition on tiny graphs, and by Algorithm 2.
  *
  * It exists to check the GPU engine.  It shares no code with it: no
  * headers, helpers or tables.  Only the tests, the smoke check and the
@@ -1198,4 +1201,569 @@ void oracle_core_numbers(uint32_t n, const uint64_t *row_ptr, const uint32_t *co
   }
   free(by_pos);
   free(pi);
+}
+
+/* ------------------------------------------------------------------ */
+/* top-k frequent pattern mining                                       */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Patterns are connected, vertex-labelled, with no edge labels.  A pattern
+ * is written as its minimum DFS code (Section 3.3, pattern-oriented
+ * expansion, after gSpan): a sequence of edges (i, j, L(i), L(j)) over
+ * DFS discovery ids, forward when i < j (j is a new vertex), backward when
+ * i > j.  Code edges compare by the key
+ *   backward: (0, j, 0, 0)      forward: (1, -i, L(i), L(j))
+ * (backward before forward; among backward edges the smaller target
+ * first; among forward edges the one leaving the deeper vertex first, then
+ * by labels), and codes compare edge by edge.  For two codes that agree up
+ * to some edge this is the DFS lexicographic order of gSpan; results with
+ * equal support are ranked by it too.
+ *
+ * Support (Section 2.1): minimum image-based support, the smallest number
+ * of distinct data vertices any one pattern vertex is mapped to over all
+ * embeddings (injective, label-preserving maps sending every pattern edge
+ * to a data edge).
+ */
+
+#define PM_MAXE 8
+#define PM_MAXV (PM_MAXE + 1)
+
+typedef struct { uint8_t i, j, li, lj; } pm_edge;
+typedef struct { uint32_t ne, nv; pm_edge e[PM_MAXE]; } pm_code;
+
+static void pm_key(const pm_edge *e, int k[4]) {
+  if (e->i > e->j) { k[0] = 0; k[1] = e->j; k[2] = 0; k[3] = 0; }
+  else { k[0] = 1; k[1] = -(int)e->i; k[2] = e->li; k[3] = e->lj; }
+}
+
+static int pm_edge_cmp(const pm_edge *a, const pm_edge *b) {
+  int ka[4], kb[4];
+  pm_key(a, ka);
+  pm_key(b, kb);
+  for (int t = 0; t < 4; ++t)
+    if (ka[t] != kb[t]) return ka[t] < kb[t] ? -1 : 1;
+  return 0;
+}
+
+/* codes edge by edge; a proper prefix is smaller */
+static int pm_code_cmp(const pm_code *a, const pm_code *b) {
+  uint32_t n = a->ne < b->ne ? a->ne : b->ne;
+  for (uint32_t t = 0; t < n; ++t) {
+    int c = pm_edge_cmp(&a->e[t], &b->e[t]);
+    if (c) return c;
+  }
+  return a->ne < b->ne ? -1 : (a->ne > b->ne);
+}
+
+/* a small labelled graph (the pattern behind a code) */
+typedef struct {
+  uint32_t nv, ne;
+  uint8_t lab[PM_MAXV];
+  uint8_t adj[PM_MAXV][PM_MAXV];
+} pm_graph;
+
+static void pm_graph_of(const pm_code *c, pm_graph *p) {
+  memset(p, 0, sizeof(*p));
+  p->nv = c->nv;
+  p->ne = c->ne;
+  for (uint32_t t = 0; t < c->ne; ++t) {
+    p->lab[c->e[t].i] = c->e[t].li;
+    p->lab[c->e[t].j] = c->e[t].lj;
+    p->adj[c->e[t].i][c->e[t].j] = p->adj[c->e[t].j][c->e[t].i] = 1;
+  }
+}
+
+/*
+ * Every DFS code of p: a depth-first traversal from any start vertex, with
+ * every choice of the next unvisited neighbour; a vertex's edges to
+ * vertices already visited (other than its discoverer) follow the forward
+ * edge that discovers it, by ascending id.  The smallest is kept in *best.
+ */
+typedef struct {
+  const pm_graph *p;
+  int id[PM_MAXV];        /* discovery id per pattern vertex, -1 unvisited */
+  uint32_t who[PM_MAXV];  /* pattern vertex per discovery id */
+  uint32_t nvis;
+  pm_code cur, best;
+  int have;
+} pm_dfs;
+
+/* path[0..sp) is the current DFS path (the rightmost path), root first */
+static void pm_dfs_rec(pm_dfs *D, const uint32_t *path, uint32_t sp) {
+  const pm_graph *p = D->p;
+  if (D->cur.ne == p->ne) {
+    if (!D->have || pm_code_cmp(&D->cur, &D->best) < 0) { D->best = D->cur; D->have = 1; }
+    return;
+  }
+  /* the deepest vertex on the path with an unvisited neighbour */
+  while (sp > 0) {
+    uint32_t u = path[sp - 1], any = 0;
+    for (uint32_t w = 0; w < p->nv; ++w) if (p->adj[u][w] && D->id[w] < 0) { any = 1; break; }
+    if (any) break;
+    --sp;
+  }
+  if (sp == 0) return; /* cannot happen for a connected pattern */
+  uint32_t u = path[sp - 1];
+  uint32_t next[PM_MAXV];
+  memcpy(next, path, sp * sizeof(uint32_t));
+  uint32_t saved_ne = D->cur.ne;
+  for (uint32_t w = 0; w < p->nv; ++w) {
+    if (!p->adj[u][w] || D->id[w] >= 0) continue;
+    uint32_t nid = D->nvis;
+    D->id[w] = (int)nid;
+    D->who[nid] = w;
+    D->nvis++;
+    pm_edge f = {(uint8_t)D->id[u], (uint8_t)nid, p->lab[u], p->lab[w]};
+    D->cur.e[D->cur.ne++] = f;
+    for (uint32_t k = 0; k < nid; ++k) {
+      uint32_t x = D->who[k];
+      if (x != u && p->adj[w][x]) {
+        pm_edge b = {(uint8_t)nid, (uint8_t)k, p->lab[w], p->lab[x]};
+        D->cur.e[D->cur.ne++] = b;
+      }
+    }
+    D->cur.nv = D->nvis;
+    next[sp] = w;
+    pm_dfs_rec(D, next, sp + 1);
+    D->cur.ne = saved_ne;
+    D->nvis--;
+    D->id[w] = -1;
+  }
+}
+
+static void pm_min_code(const pm_graph *p, pm_code *out) {
+  pm_dfs D;
+  memset(&D, 0, sizeof(D));
+  D.p = p;
+  for (uint32_t s = 0; s < p->nv; ++s) {
+    for (uint32_t v = 0; v < PM_MAXV; ++v) D.id[v] = -1;
+    D.id[s] = 0;
+    D.who[0] = s;
+    D.nvis = 1;
+    D.cur.ne = 0;
+    D.cur.nv = 1;
+    uint32_t path[1] = {s};
+    pm_dfs_rec(&D, path, 1);
+  }
+  *out = D.best;
+  out->nv = p->nv;
+}
+
+static int pm_is_min(const pm_code *c) {
+  pm_graph p;
+  pm_code m;
+  pm_graph_of(c, &p);
+  pm_min_code(&p, &m);
+  return pm_code_cmp(&m, c) == 0;
+}
+
+/* support by definition: every embedding of the code's pattern */
+typedef struct {
+  const graph_t *g;
+  const pm_code *c;
+  uint32_t par[PM_MAXV];   /* discoverer of each code vertex */
+  uint32_t phi[PM_MAXV];
+  uint8_t *seen;           /* nv x n image marks */
+  uint64_t count[PM_MAXV];
+} pm_sup;
+
+static void pm_sup_rec(pm_sup *S, uint32_t x) {
+  const pm_code *c = S->c;
+  const graph_t *g = S->g;
+  if (x == c->nv) {
+    for (uint32_t v = 0; v < c->nv; ++v) {
+      uint8_t *m = &S->seen[(uint64_t)v * g->n + S->phi[v]];
+      if (!*m) { *m = 1; S->count[v]++; }
+    }
+    return;
+  }
+  /* candidates: neighbours of the discoverer's image (all vertices for 0) */
+  uint8_t lx = 0;
+  for (uint32_t t = 0; t < c->ne; ++t) {
+    if (c->e[t].i == x) lx = c->e[t].li;
+    if (c->e[t].j == x) lx = c->e[t].lj;
+  }
+  uint64_t b = 0, e = g->n;
+  if (x > 0) { b = g->row_ptr[S->phi[S->par[x]]]; e = g->row_ptr[S->phi[S->par[x]] + 1]; }
+  for (uint64_t it = b; it < e; ++it) {
+    uint32_t w = x > 0 ? g->col[it] : (uint32_t)it;
+    if (g->lab[w] != lx) continue;
+    int ok = 1;
+    for (uint32_t v = 0; v < x && ok; ++v) if (S->phi[v] == w) ok = 0;
+    /* every code edge between x and an earlier vertex must be a data edge */
+    for (uint32_t t = 0; t < c->ne && ok; ++t) {
+      uint32_t a = c->e[t].i, d = c->e[t].j;
+      if (a == x && d < x) ok = is_adjacent(g, w, S->phi[d]);
+      else if (d == x && a < x) ok = is_adjacent(g, w, S->phi[a]);
+    }
+    if (!ok) continue;
+    S->phi[x] = w;
+    pm_sup_rec(S, x + 1);
+  }
+}
+
+static uint64_t pm_support(const graph_t *g, const pm_code *c) {
+  pm_sup S;
+  memset(&S, 0, sizeof(S));
+  S.g = g;
+  S.c = c;
+  for (uint32_t t = 0; t < c->ne; ++t)
+    if (c->e[t].i < c->e[t].j) S.par[c->e[t].j] = c->e[t].i;
+  S.seen = (uint8_t *)calloc((uint64_t)c->nv * g->n, 1);
+  pm_sup_rec(&S, 0);
+  free(S.seen);
+  uint64_t f = UINT64_MAX;
+  for (uint32_t v = 0; v < c->nv; ++v) if (S.count[v] < f) f = S.count[v];
+  return c->nv ? f : 0;
+}
+
+/* result set of patterns: support descending, then code ascending */
+typedef struct { uint64_t f; pm_code c; } pm_res;
+
+static int pm_res_before(const pm_res *a, const pm_res *b) {
+  if (a->f != b->f) return a->f > b->f;
+  return pm_code_cmp(&a->c, &b->c) < 0;
+}
+
+static void pm_offer(pm_res *R, uint32_t *n, uint32_t k, const pm_res *x) {
+  if (*n == k && !pm_res_before(x, &R[k - 1])) return;
+  uint32_t at = *n < k ? (*n)++ : k - 1;
+  while (at > 0 && pm_res_before(x, &R[at - 1])) { R[at] = R[at - 1]; --at; }
+  R[at] = *x;
+}
+
+static void pm_write(const pm_res *R, uint32_t n, uint32_t M, uint64_t *support_out,
+                     uint32_t *code_out) {
+  for (uint32_t r = 0; r < n; ++r) {
+    support_out[r] = R[r].f;
+    for (uint32_t t = 0; t < M; ++t) {
+      uint32_t *o = &code_out[((uint64_t)r * M + t) * 4];
+      o[0] = R[r].c.e[t].i; o[1] = R[r].c.e[t].j; o[2] = R[r].c.e[t].li; o[3] = R[r].c.e[t].lj;
+    }
+  }
+}
+
+/*
+ * The definition, for tiny graphs: every connected set of M data edges
+ * gives a pattern (its minimum DFS code); each distinct pattern is scored
+ * by its support over all embeddings; the top k are returned.  Returns the
+ * count, or -2 for bad arguments / a graph too large to enumerate.
+ */
+int64_t oracle_topk_patterns_definition(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                                        const uint8_t *lab, uint32_t M, uint32_t k,
+                                        uint64_t *support_out, uint32_t *code_out) {
+  graph_t G = {n, row_ptr, col, NULL, lab, NULL, NULL};
+  if (M < 1 || M > PM_MAXE || k == 0) return -2;
+  uint32_t m = 0;
+  for (uint32_t u = 0; u < n; ++u)
+    for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) if (u < col[e]) m++;
+  if (m > 64) return -2;
+  uint32_t *eu = (uint32_t *)xmalloc(m * 4), *ev = (uint32_t *)xmalloc(m * 4);
+  m = 0;
+  for (uint32_t u = 0; u < n; ++u)
+    for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e)
+      if (u < col[e]) { eu[m] = u; ev[m] = col[e]; m++; }
+  pm_code *seen = NULL;
+  uint64_t nseen = 0, cap = 0;
+  uint32_t pick[PM_MAXE];
+  /* every M-subset of the edges, in lexicographic order */
+  if (M <= m) {
+    for (uint32_t t = 0; t < M; ++t) pick[t] = t;
+    for (;;) {
+      /* the subset's vertices, relabelled 0..nv-1 */
+      uint32_t vs[2 * PM_MAXE], nv = 0;
+      pm_graph p;
+      memset(&p, 0, sizeof(p));
+      for (uint32_t t = 0; t < M; ++t) {
+        uint32_t ends[2] = {eu[pick[t]], ev[pick[t]]}, id[2];
+        for (int s = 0; s < 2; ++s) {
+          uint32_t q = 0;
+          while (q < nv && vs[q] != ends[s]) ++q;
+          if (q == nv) vs[nv++] = ends[s];
+          id[s] = q;
+        }
+        if (nv <= PM_MAXV) p.adj[id[0]][id[1]] = p.adj[id[1]][id[0]] = 1;
+      }
+      if (nv <= PM_MAXV) {
+        p.nv = nv;
+        p.ne = M;
+        for (uint32_t q = 0; q < nv; ++q) p.lab[q] = lab[vs[q]];
+        /* connected? */
+        uint32_t reach = 1, grow = 1;
+        while (grow) {
+          grow = 0;
+          for (uint32_t a = 0; a < nv; ++a)
+            if (reach >> a & 1)
+              for (uint32_t b = 0; b < nv; ++b)
+                if (p.adj[a][b] && !(reach >> b & 1)) { reach |= 1u << b; grow = 1; }
+        }
+        if (reach == (1u << nv) - 1) {
+          pm_code c;
+          pm_min_code(&p, &c);
+          int dup = 0;
+          for (uint64_t s = 0; s < nseen && !dup; ++s) dup = pm_code_cmp(&seen[s], &c) == 0;
+          if (!dup) {
+            if (nseen == cap) {
+              cap = cap ? 2 * cap : 64;
+              seen = (pm_code *)realloc(seen, cap * sizeof(pm_code));
+            }
+            seen[nseen++] = c;
+          }
+        }
+      }
+      /* next subset */
+      int t = (int)M - 1;
+      while (t >= 0 && pick[t] == m - M + (uint32_t)t) --t;
+      if (t < 0) break;
+      pick[t]++;
+      for (uint32_t s = (uint32_t)t + 1; s < M; ++s) pick[s] = pick[s - 1] + 1;
+    }
+  }
+  pm_res *R = (pm_res *)xmalloc((uint64_t)k * sizeof(pm_res));
+  uint32_t nr = 0;
+  for (uint64_t s = 0; s < nseen; ++s) {
+    pm_res x;
+    x.c = seen[s];
+    x.f = pm_support(&G, &seen[s]);
+    pm_offer(R, &nr, k, &x);
+  }
+  pm_write(R, nr, M, support_out, code_out);
+  free(R);
+  free(seen);
+  free(eu);
+  free(ev);
+  return nr;
+}
+
+/* support of one pattern given as a code (4 u32 per edge), by definition */
+int64_t oracle_pattern_support(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                               const uint8_t *lab, uint32_t ne, const uint32_t *code) {
+  graph_t G = {n, row_ptr, col, NULL, lab, NULL, NULL};
+  if (ne < 1 || ne > PM_MAXE) return -2;
+  pm_code c;
+  memset(&c, 0, sizeof(c));
+  c.ne = ne;
+  for (uint32_t t = 0; t < ne; ++t) {
+    c.e[t].i = (uint8_t)code[4 * t]; c.e[t].j = (uint8_t)code[4 * t + 1];
+    c.e[t].li = (uint8_t)code[4 * t + 2]; c.e[t].lj = (uint8_t)code[4 * t + 3];
+    if (c.e[t].i + 1u > c.nv) c.nv = c.e[t].i + 1u;
+    if (c.e[t].j + 1u > c.nv) c.nv = c.e[t].j + 1u;
+  }
+  return (int64_t)pm_support(&G, &c);
+}
+
+/* minimum DFS code of a small labelled graph (nv vertices, edges as pairs) */
+int64_t oracle_min_dfs_code(uint32_t nv, const uint8_t *plab, uint32_t ne, const uint32_t *pedges,
+                            uint32_t *code_out) {
+  if (nv < 2 || nv > PM_MAXV || ne < 1 || ne > PM_MAXE) return -2;
+  pm_graph p;
+  memset(&p, 0, sizeof(p));
+  p.nv = nv;
+  p.ne = ne;
+  for (uint32_t v = 0; v < nv; ++v) p.lab[v] = plab[v];
+  for (uint32_t t = 0; t < ne; ++t) {
+    uint32_t a = pedges[2 * t], b = pedges[2 * t + 1];
+    if (a >= nv || b >= nv || a == b || p.adj[a][b]) return -2;
+    p.adj[a][b] = p.adj[b][a] = 1;
+  }
+  pm_code c;
+  pm_min_code(&p, &c);
+  if (c.ne != ne) return -2; /* not connected */
+  for (uint32_t t = 0; t < ne; ++t) {
+    code_out[4 * t] = c.e[t].i; code_out[4 * t + 1] = c.e[t].j;
+    code_out[4 * t + 2] = c.e[t].li; code_out[4 * t + 3] = c.e[t].lj;
+  }
+  return ne;
+}
+
+/*
+ * Algorithm 2 (Section 3.3) for top-k frequent patterns, in the paper's
+ * order: one-edge subgraphs grouped by pattern (lines 1-8), then groups
+ * taken by priority (number of edges, support) (line 10); a group whose
+ * pattern has M edges is relevant and offered to R (lines 11-15); a group
+ * with support below the k-th result's is dominated (line 16; minimum
+ * image-based support never grows when a pattern grows); otherwise every
+ * subgraph of the group grows by one edge by pattern-oriented expansion
+ * (lines 17-24): rightmost-path extensions of its DFS code, kept only when
+ * the new code is minimal, grouped by the new code; groups that are not
+ * dominated enter Q (lines 25-27).
+ */
+typedef struct {
+  pm_code c;
+  uint64_t f;
+  uint32_t *emb; /* count x c.nv data vertices, by code vertex */
+  uint64_t count, cap;
+} pm_group;
+
+static pm_group *pm_group_new(const pm_code *c) {
+  pm_group *G = (pm_group *)calloc(1, sizeof(pm_group));
+  G->c = *c;
+  return G;
+}
+
+static void pm_group_add(pm_group *G, const uint32_t *phi) {
+  if (G->count == G->cap) {
+    G->cap = G->cap ? 2 * G->cap : 16;
+    G->emb = (uint32_t *)realloc(G->emb, G->cap * G->c.nv * sizeof(uint32_t));
+    if (!G->emb) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+  }
+  memcpy(&G->emb[G->count * G->c.nv], phi, G->c.nv * sizeof(uint32_t));
+  G->count++;
+}
+
+static void pm_group_free(pm_group *G) {
+  free(G->emb);
+  free(G);
+}
+
+/* minimum image-based support over the group's subgraphs (Listing 2) */
+static uint64_t pm_group_support(const pm_group *G, uint32_t n, uint8_t *mark) {
+  uint64_t f = UINT64_MAX;
+  for (uint32_t v = 0; v < G->c.nv; ++v) {
+    uint64_t distinct = 0;
+    for (uint64_t s = 0; s < G->count; ++s) {
+      uint32_t x = G->emb[s * G->c.nv + v];
+      if (!mark[x]) { mark[x] = 1; distinct++; }
+    }
+    for (uint64_t s = 0; s < G->count; ++s) mark[G->emb[s * G->c.nv + v]] = 0;
+    if (distinct < f) f = distinct;
+  }
+  (void)n;
+  return f;
+}
+
+int64_t oracle_topk_patterns(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                             const uint8_t *lab, uint32_t M, uint32_t k, uint64_t *support_out,
+                             uint32_t *code_out, uint64_t *stats_out) {
+  graph_t G = {n, row_ptr, col, NULL, lab, NULL, NULL};
+  const graph_t *g = &G;
+  if (M < 1 || M > PM_MAXE || k == 0) return -2;
+  uint8_t *mark = (uint8_t *)calloc(n ? n : 1, 1);
+  pm_res *R = (pm_res *)xmalloc((uint64_t)k * sizeof(pm_res));
+  uint32_t nr = 0;
+  uint64_t st_popped = 0, st_expanded = 0, st_children = 0, st_pruned_pop = 0,
+           st_pruned_new = 0, st_nonmin = 0, st_groups = 0;
+  pq_t Q = {0};
+
+  /* lines 1-8: one-edge subgraphs (u, v), kept when (0, 1, L(u), L(v)) is
+     minimal, i.e. L(u) <= L(v); one group per label pair */
+  pm_group **first = (pm_group **)calloc(256 * 256, sizeof(pm_group *));
+  for (uint32_t u = 0; u < n; ++u)
+    for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+      uint32_t v = col[e];
+      if (lab[u] > lab[v]) continue;
+      uint32_t key = lab[u] * 256u + lab[v];
+      if (!first[key]) {
+        pm_code c;
+        memset(&c, 0, sizeof(c));
+        c.ne = 1;
+        c.nv = 2;
+        pm_edge e0 = {0, 1, lab[u], lab[v]};
+        c.e[0] = e0;
+        first[key] = pm_group_new(&c);
+      }
+      uint32_t phi[2] = {u, v};
+      pm_group_add(first[key], phi);
+      st_children++;
+    }
+  for (uint32_t key = 0; key < 256 * 256; ++key)
+    if (first[key]) {
+      first[key]->f = pm_group_support(first[key], n, mark);
+      int64_t pk[3] = {1, (int64_t)first[key]->f, 0};
+      pq_insert(&Q, pk, first[key]);
+      st_groups++;
+    }
+  free(first);
+
+  /* lines 9-27 */
+  pm_group **kids = NULL;
+  uint32_t nkids = 0;
+  while (Q.n > 0) {
+    pm_group *S = (pm_group *)pq_remove_max(&Q);
+    st_popped++;
+    if (S->c.ne == M) {
+      pm_res x;
+      x.f = S->f;
+      x.c = S->c;
+      pm_offer(R, &nr, k, &x);
+    }
+    if (nr == k && S->f < R[k - 1].f) { st_pruned_pop++; pm_group_free(S); continue; }
+    if (S->c.ne == M) { pm_group_free(S); continue; } /* expandable() is false at M edges */
+    st_expanded++;
+    const pm_code *c = &S->c;
+    const uint32_t nv = c->nv, rm = nv - 1;
+    /* the rightmost path: rm and its discoverers back to 0 */
+    uint32_t par[PM_MAXV], onpath[PM_MAXV] = {0}, path[PM_MAXV], np = 0;
+    for (uint32_t t = 0; t < c->ne; ++t) if (c->e[t].i < c->e[t].j) par[c->e[t].j] = c->e[t].i;
+    for (uint32_t x = rm;; x = par[x]) { path[np++] = x; onpath[x] = 1; if (x == 0) break; }
+    uint8_t has[PM_MAXV][PM_MAXV] = {{0}};
+    for (uint32_t t = 0; t < c->ne; ++t) has[c->e[t].i][c->e[t].j] = has[c->e[t].j][c->e[t].i] = 1;
+    /* child groups by the new code edge: backward to x -> x; forward from
+       path vertex x with label l -> nv + x * 256 + l */
+    uint32_t nk = nv + nv * 256;
+    if (nk > nkids) { kids = (pm_group **)realloc(kids, nk * sizeof(pm_group *)); nkids = nk; }
+    memset(kids, 0, nk * sizeof(pm_group *));
+    for (uint64_t s = 0; s < S->count; ++s) {
+      const uint32_t *phi = &S->emb[s * nv];
+      uint32_t child[PM_MAXV];
+      memcpy(child, phi, nv * sizeof(uint32_t));
+      /* backward edges from the rightmost vertex */
+      for (uint32_t x = 0; x < rm; ++x) {
+        if (!onpath[x] || has[rm][x]) continue;
+        if (!is_adjacent(g, phi[rm], phi[x])) continue;
+        if (!kids[x]) {
+          pm_code c2 = *c;
+          pm_edge b = {(uint8_t)rm, (uint8_t)x, lab[phi[rm]], lab[phi[x]]};
+          c2.e[c2.ne++] = b;
+          kids[x] = pm_group_new(&c2);
+        }
+        pm_group_add(kids[x], child);
+        st_children++;
+      }
+      /* forward edges from every vertex of the rightmost path */
+      for (uint32_t q = 0; q < np; ++q) {
+        uint32_t x = path[q], dx = phi[x];
+        for (uint64_t e = row_ptr[dx]; e < row_ptr[dx + 1]; ++e) {
+          uint32_t w = col[e];
+          int used = 0;
+          for (uint32_t y = 0; y < nv && !used; ++y) used = phi[y] == w;
+          if (used) continue;
+          uint32_t key = nv + x * 256u + lab[w];
+          if (!kids[key]) {
+            pm_code c2 = *c;
+            pm_edge f = {(uint8_t)x, (uint8_t)nv, lab[dx], lab[w]};
+            c2.e[c2.ne++] = f;
+            c2.nv = nv + 1;
+            kids[key] = pm_group_new(&c2);
+          }
+          child[nv] = w;
+          pm_group_add(kids[key], child);
+          st_children++;
+        }
+      }
+    }
+    for (uint32_t key = 0; key < nk; ++key) {
+      pm_group *C = kids[key];
+      if (!C) continue;
+      if (!pm_is_min(&C->c)) { st_nonmin++; pm_group_free(C); continue; }
+      C->f = pm_group_support(C, n, mark);
+      if (nr == k && C->f < R[k - 1].f) { st_pruned_new++; pm_group_free(C); continue; }
+      int64_t pk[3] = {(int64_t)C->c.ne, (int64_t)C->f, 0};
+      pq_insert(&Q, pk, C);
+      st_groups++;
+    }
+    pm_group_free(S);
+  }
+  free(kids);
+  free(Q.a);
+  free(mark);
+  pm_write(R, nr, M, support_out, code_out);
+  free(R);
+  if (stats_out) {
+    stats_out[0] = st_popped; stats_out[1] = st_expanded; stats_out[2] = st_children;
+    stats_out[3] = st_pruned_new; stats_out[4] = st_pruned_pop; stats_out[5] = st_nonmin;
+    stats_out[6] = st_groups;
+  }
+  return nr;
 }

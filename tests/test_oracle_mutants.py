@@ -18,6 +18,10 @@ import oracle
 import synth
 from tests import bruteforce
 from tests.test_oracle_match_degree import _index_from_distances as index_from_distances
+from tests.test_oracle_patterns import _all_dfs_codes as all_dfs_codes
+from tests.test_oracle_patterns import _key as dfs_key
+from tests.test_oracle_patterns import _nx_support as pattern_support_nx
+from tests.test_oracle_patterns import _random_labelled_connected as random_pattern_graph
 
 ORACLE_C = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -96,6 +100,22 @@ MUTANTS = [
     ("degree score leaves out the seed",
      "r->score = S->degree ? degree_of(g, v) : 0;",
      "r->score = 0;"),
+    ("pattern support takes the largest image count",
+     ("if (distinct < f) f = distinct;", "if (S.count[v] < f) f = S.count[v];"),
+     ("if (f == UINT64_MAX || distinct > f) f = distinct;",
+      "if (f == UINT64_MAX || S.count[v] > f) f = S.count[v];")),
+    ("pattern groups pruned at equal support",
+     ("if (nr == k && S->f < R[k - 1].f)", "if (nr == k && C->f < R[k - 1].f)"),
+     ("if (nr == k && S->f <= R[k - 1].f)", "if (nr == k && C->f <= R[k - 1].f)")),
+    ("non-minimal DFS codes kept",
+     "if (!pm_is_min(&C->c)) { st_nonmin++; pm_group_free(C); continue; }",
+     "(void)0;"),
+    ("forward extensions only from the rightmost vertex",
+     "for (uint32_t q = 0; q < np; ++q) {\n        uint32_t x = path[q], dx = phi[x];",
+     "for (uint32_t q = 0; q < 1; ++q) {\n        uint32_t x = path[q], dx = phi[x];"),
+    ("DFS code order prefers the shallower vertex",
+     "else { k[0] = 1; k[1] = -(int)e->i; k[2] = e->li; k[3] = e->lj; }",
+     "else { k[0] = 1; k[1] = (int)e->i; k[2] = e->li; k[3] = e->lj; }"),
 ]
 
 MATCH_PATTERNS = [
@@ -142,6 +162,32 @@ def _battery():
                 got, _ = oracle.topk_match(g, labels, edges, k, n_labels=2, score="degree")
                 if got != want:
                     failed.append(f"degree match pattern {pi} seed {seed} k={k}")
+    for seed in (1, 2, 3):
+        g = synth.gnp(11, 0.35, 80 + seed)
+        synth.add_zipf_labels(g, n_labels=seed, s=0.5, master=80 + seed)
+        for M in (1, 2, 3):
+            want = oracle.topk_patterns_definition(g, M, 10 ** 6)
+            for k in (1, 3, 10 ** 6):
+                if oracle.topk_patterns(g, M, k)[0] != want[:k]:
+                    failed.append(f"patterns seed {seed} M={M} k={k}")
+            for f, code in want[:6]:
+                if pattern_support_nx(g, code) != f:
+                    failed.append(f"pattern support seed {seed} M={M}")
+    for seed, M in ((13, 2), (81, 3), (135, 2)):
+        g = synth.gnp(8 + seed % 5, 0.4, 1000 + seed)
+        synth.add_zipf_labels(g, n_labels=1 + seed % 2, s=0.5, master=1000 + seed)
+        want = oracle.topk_patterns_definition(g, M, 10 ** 6)
+        for k in (1, 2, 3):
+            if oracle.topk_patterns(g, M, k)[0] != want[:k]:
+                failed.append(f"pattern ties seed {seed} M={M} k={k}")
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        nv = int(rng.integers(2, 6))
+        ne = int(rng.integers(nv - 1, min(nv * (nv - 1) // 2, 6) + 1))
+        labels, edges = random_pattern_graph(rng, nv, ne, 3)
+        codes = all_dfs_codes(labels, edges)
+        if oracle.min_dfs_code(labels, edges) != min(codes, key=lambda c: [dfs_key(e) for e in c]):
+            failed.append("min dfs code")
     for seed in (1, 2):
         g = synth.gnp(40, 0.08, 60 + seed)
         synth.add_zipf_labels(g, n_labels=3, s=0.5, master=60 + seed)
