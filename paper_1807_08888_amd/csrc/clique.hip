@@ -1534,6 +1534,7 @@ struct Engine {
   std::unique_ptr<StepLayout> L;
   // NURI_TRACE=n: one line on stderr every n steps (1: every step)
   uint64_t trace = 0, trace_steps = 0;
+  bool theta_pending = false;  // h_res holds k-th scores not yet taken
   uint32_t rr = 0;     // round-robin start of the per-step planning
   std::vector<int> level_order;  // scratch of plan()
 
@@ -1708,6 +1709,13 @@ struct Engine {
   // start query (k, score kind) in a free slot with a frontier arena of
   // `bytes` (0: the slot default)
   void admit(uint32_t i, uint32_t k, int kind, u64 bytes = 0) {
+    // the copy of every query's k-th score still in flight would land on
+    // top of this slot's new entry: let it land and take it while the slot
+    // still holds the old query (which no longer counts), before resetting it
+    if (theta_pending) {
+      NURI_HIP(hipStreamSynchronize(s));
+      take_theta();
+    }
     QHost &Q = qh[i];
     Q = QHost{};
     Q.active = true;
@@ -2106,6 +2114,7 @@ struct Engine {
     }
     NURI_HIP(hipMemcpyAsync(h_step.p, d_step.p, L->readback(), hipMemcpyDeviceToHost, s));
     NURI_HIP(hipStreamSynchronize(s));
+    take_theta();
     if (o.profile && batch_ub) {
       float ms = 0;
       NURI_HIP(hipEventElapsedTime(&ms, ev0, ev1));
@@ -2170,8 +2179,18 @@ struct Engine {
       NURI_HIP(hipGetLastError());
       launch_merge(cands.p, dh, cand_ids.p, lmax, d_res.p, d_k.p, mbuf, nq, kmax, cnt, s);
     }
+    // the k-th scores come back with the next step's read-back: the host
+    // plans one step with the previous ones, which are never above the
+    // current ones, so it prunes less, never wrongly (the kernels read the
+    // current ones from device memory)
     NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
-    NURI_HIP(hipStreamSynchronize(s));
+    theta_pending = true;
+  }
+
+  // after a synchronisation: take the k-th scores copied back last
+  void take_theta() {
+    if (!theta_pending) return;
+    theta_pending = false;
     for (uint32_t i = 0; i < nq; ++i)
       if (qh[i].active) qh[i].theta = h_res.p[i].theta;
   }

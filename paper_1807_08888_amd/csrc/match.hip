@@ -50,10 +50,7 @@ struct MRec {  // 64 B partial match
 };
 static_assert(sizeof(MRec) == 64, "match record must stay 64 bytes");
 
-// mu[b] for a pattern vertex b known only at run time.  Records being
-// expanded are read in place from the batch (one per wavefront, so the
-// reads are uniform): a register copy indexed at run time would live in
-// per-lane scratch memory.
+// mu[b] for a pattern vertex b known only at run time
 __device__ inline uint32_t mu_at(const MRec &r, uint32_t b) { return r.mu[b]; }
 
 struct MPlan {  // per query pattern plan
@@ -193,8 +190,8 @@ __global__ void k_match_roots(MView m, const MPlan *plans, const uint64_t *lab_o
     MRec r;
     r.score = score;
     r.bound = bound;
-#pragma unroll
-    for (int t = 0; t < QM; ++t) r.mu[t] = (a0 == (uint32_t)t) ? v : 0u;
+    for (int t = 0; t < QM; ++t) r.mu[t] = 0;
+    r.mu[a0] = v;
     r.qid = q;
     r.depth = 1;
     r.nchild = child_bound(m, P, r);
@@ -438,8 +435,7 @@ __device__ inline void match_walk(const MView &m, const MPlan &P, const MRec &p,
     uint32_t nch = 0;
     if (keep) {
       ch = p;
-#pragma unroll
-      for (int t = 0; t < QM; ++t) ch.mu[t] = (a == (uint32_t)t) ? c : p.mu[t];
+      ch.mu[a] = c;
       ch.score = score2;
       ch.bound = bound2;
       ch.depth = p.depth + 1;
@@ -487,9 +483,7 @@ __device__ inline void match_walk(const MView &m, const MPlan &P, const MRec &p,
           cd.len = P.q;
           cands[slot] = cd;
           uint32_t *dst = cand_ids + (u64)slot * QM;
-#pragma unroll
-          for (int i = 0; i < QM; ++i)
-            if ((uint32_t)i < P.q) dst[i] = ((uint32_t)i == a) ? c : p.mu[i];
+          for (uint32_t i = 0; i < P.q; ++i) dst[i] = (i == a) ? c : p.mu[i];
           st.offered++;
         } else {
           atomicAdd(&ms[q].overflow, 1u);
@@ -526,7 +520,7 @@ __global__ void __launch_bounds__(64 * kMatchWaves)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const uint32_t rec = blockIdx.x * kMatchWaves + wv;
   if (rec >= hdr->batch_count) return;
-  const MRec &p = batch[rec];
+  const MRec p = batch[rec];
   const uint32_t q = p.qid;
   const MPlan &P = plans[q];
   const MCfg cf = cfg[q];
@@ -585,7 +579,7 @@ __global__ void __launch_bounds__(64 * kMatchWaves)
       if (big_base[mid] <= c) lo = mid;
       else hi = mid;
     }
-    const MRec &p = batch[big_rec[lo]];
+    const MRec p = batch[big_rec[lo]];
     const uint32_t q = p.qid;
     const MPlan &P = plans[q];
     const MCfg cf = cfg[q];
@@ -857,7 +851,8 @@ struct MatchEngine {
   PoolBuf<CPre> d_pre;
   PinBuf<CPre> h_pre;
   PoolBuf<unsigned int> d_chist, d_ccount;
-  PinBuf<unsigned int> h_ccount;
+  PinBuf<unsigned int> h_ccount;  // [0] candidates kept; [1..] merge chunk sizes
+  bool theta_pending = false;     // h_res holds k-th scores not yet taken
   PoolBuf<unsigned int> d_hist;
   PoolBuf<u64> d_hcost;
   PoolBuf<unsigned char> d_step;
@@ -958,7 +953,7 @@ struct MatchEngine {
     d_chist.alloc(g.pool, (u64)nq * kBins);
     NURI_HIP(hipMemsetAsync(d_chist.p, 0, d_chist.bytes(), s));
     d_ccount.alloc(g.pool, 1);
-    h_ccount.alloc(1);
+    h_ccount.alloc(1 + (cand_cap + kCandChunk - 1) / kCandChunk);
     d_hist.alloc(g.pool, (u64)nq * kBins);
     d_hcost.alloc(g.pool, (u64)nq * kBins);
     NURI_HIP(hipMemsetAsync(d_hist.p, 0, d_hist.bytes(), s));
@@ -979,6 +974,14 @@ struct MatchEngine {
   // start a query in a free slot (its unit subgraphs are made on the next
   // step) with a frontier arena of `bytes` (0: the slot default)
   void admit(uint32_t i, const nuri_pattern &pt, uint32_t k, u64 bytes = 0) {
+    // the copy of every query's k-th score still in flight would land on
+    // top of this slot's new entry: let it land and take it while the slot
+    // still holds the old query (which no longer counts), before resetting it
+    if (theta_pending) {
+      NURI_HIP(hipStreamSynchronize(s));
+      take_theta();
+    }
+
     MPlan P;
     plan_pattern(g, pt, k, P);  // throws on an invalid pattern
     uint64_t index_ns = 0;
@@ -1045,6 +1048,15 @@ struct MatchEngine {
   void read_step() {
     NURI_HIP(hipMemcpyAsync(h_step.p, d_step.p, L->readback(), hipMemcpyDeviceToHost, s));
     NURI_HIP(hipStreamSynchronize(s));
+    take_theta();
+  }
+
+  // after a synchronisation: take the k-th scores copied back last
+  void take_theta() {
+    if (!theta_pending) return;
+    theta_pending = false;
+    for (uint32_t i = 0; i < nq; ++i)
+      if (qh[i].active) qh[i].theta = h_res.p[i].theta;
   }
 
   // unit subgraphs of newly admitted queries become their first level,
@@ -1312,18 +1324,18 @@ struct MatchEngine {
       for (uint32_t i = 0; i < nq; ++i)
         if (sms()[i].cand_n) qh[i].top_seen = std::max(qh[i].top_seen, sms()[i].cand_max);
     }
-    for (uint32_t f = 0; f < ncand; f += kCandChunk) {
-      h_ccount.p[0] = std::min<uint32_t>(kCandChunk, ncand - f);
-      // the merge kernels read the chunk size through StepHdr::cand_count
-      NURI_HIP(hipMemcpyAsync(&dh->cand_count, h_ccount.p, 4, hipMemcpyHostToDevice, s));
+    for (uint32_t f = 0, c = 1; f < ncand; f += kCandChunk, ++c) {
+      // the merge kernels read the chunk size through StepHdr::cand_count;
+      // each chunk's size has its own pinned slot, so nothing waits here
+      h_ccount.p[c] = std::min<uint32_t>(kCandChunk, ncand - f);
+      NURI_HIP(hipMemcpyAsync(&dh->cand_count, &h_ccount.p[c], 4, hipMemcpyHostToDevice, s));
       launch_merge(mc + f, dh, mids + (u64)f * QM, (uint32_t)QM, d_res.p, d_k.p, mbuf, nq, kmax,
-                   h_ccount.p[0], s);
-      NURI_HIP(hipStreamSynchronize(s));  // the pinned chunk size is rewritten next round
+                   h_ccount.p[c], s);
     }
+    // the k-th scores come back with the next step's read-back (the host
+    // plans one step with the previous ones, which only prunes less)
     NURI_HIP(hipMemcpyAsync(h_res.p, d_res.p, nq * sizeof(QRes), hipMemcpyDeviceToHost, s));
-    NURI_HIP(hipStreamSynchronize(s));
-    for (uint32_t i = 0; i < nq; ++i)
-      if (qh[i].active) qh[i].theta = h_res.p[i].theta;
+    theta_pending = true;
   }
 
   bool step_all() {

@@ -55,8 +55,11 @@ def _alone(nuri, G, q):
 
 def _wait(nuri, S, tickets, timeout=90.0):
     out = {}
-    t0 = time.time()
+    t0 = last = time.time()
     while len(out) < len(tickets):
+        if time.time() - last > 10:
+            last = time.time()
+            print(f"[wait] {len(tickets) - len(out)} pending after {last - t0:.0f} s", flush=True)
         for t in tickets:
             if t in out:
                 continue
@@ -197,7 +200,8 @@ def test_query_that_outgrows_its_arena_restarts_exactly(nuri):
     _case("server: a query larger than its first arena")
     G = nuri.Graph.from_synth(g)
     try:
-        alone = nuri.topk_match(G, labels, pedges, 20).items
+        alone = nuri.topk_match(G, labels, pedges, 20, deadline_ns=90 * 10 ** 9).items
+        _case("server: the same query served")
         S = nuri.Server(G, frontier_budget_bytes=64 << 20, max_slots=4096)
         try:
             t = S.submit({"kind": "match", "k": 20, "labels": labels, "edges": pedges})
