@@ -250,6 +250,26 @@ int nuri_topk_cliques(nuri_graph *g, uint32_t k, nuri_weight_fn wf, const nuri_o
 int nuri_topk_match(nuri_graph *g, const nuri_pattern *p, uint32_t k, const nuri_opts *o,
                     nuri_result **out);
 
+/*
+ * Top-k frequent patterns (Section 2.1 "Pattern Mining"; Section 3.3,
+ * Algorithm 2, with pattern-oriented expansion; Section 4.2, Listing 2):
+ * the k connected vertex-labelled patterns with exactly n_edges edges
+ * (1..8) of highest minimum image-based support -- for a pattern, the
+ * smallest number of distinct data vertices any one of its vertices is
+ * mapped to over all its embeddings (injective, label-preserving maps that
+ * send every pattern edge to a data edge).  Needs vertex labels.  k >= 1.
+ * Results, best first: score = support; ids = the pattern's minimum DFS
+ * code, 4 values per edge (i, j, label of i, label of j) over DFS discovery
+ * ids (forward edge when i < j, backward when i > j).  Ties on support are
+ * ranked by code: code edges compare backward-before-forward, backward
+ * edges by j, forward edges by the larger i first and then by labels.
+ * nuri_opts.frontier_budget_bytes bounds the device bytes of the
+ * embeddings held at once (NURI_EBUDGET beyond it); priority and the step
+ * sizes do not apply.
+ */
+int nuri_topk_patterns(nuri_graph *g, uint32_t n_edges, uint32_t k, const nuri_opts *o,
+                       nuri_result **out);
+
 /* One query of a batch. kind 0 = clique (uses k, wf), 1 = match (uses k, p). */
 typedef struct {
   uint32_t kind;

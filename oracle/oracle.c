@@ -1719,7 +1719,6 @@ int64_t oracle_topk_patterns(uint32_t n, const uint64_t *row_ptr, const uint32_t
           kids[x] = pm_group_new(&c2);
         }
         pm_group_add(kids[x], child);
-        st_children++;
       }
       /* forward edges from every vertex of the rightmost path */
       for (uint32_t q = 0; q < np; ++q) {
@@ -1739,7 +1738,6 @@ int64_t oracle_topk_patterns(uint32_t n, const uint64_t *row_ptr, const uint32_t
           }
           child[nv] = w;
           pm_group_add(kids[key], child);
-          st_children++;
         }
       }
     }
@@ -1747,6 +1745,8 @@ int64_t oracle_topk_patterns(uint32_t n, const uint64_t *row_ptr, const uint32_t
       pm_group *C = kids[key];
       if (!C) continue;
       if (!pm_is_min(&C->c)) { st_nonmin++; pm_group_free(C); continue; }
+      /* subgraphs are constructed only for minimal codes: count those */
+      st_children += C->count;
       C->f = pm_group_support(C, n, mark);
       if (nr == k && C->f < R[k - 1].f) { st_pruned_new++; pm_group_free(C); continue; }
       int64_t pk[3] = {(int64_t)C->c.ne, (int64_t)C->f, 0};

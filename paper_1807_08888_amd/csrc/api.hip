@@ -5,6 +5,8 @@
 #include <exception>
 #include <new>
 
+#include <memory>
+
 #include "nuri_internal.h"
 
 
@@ -144,6 +146,20 @@ int nuri_topk_cliques(nuri_graph *g, uint32_t k, nuri_weight_fn wf, const nuri_o
     auto *r = new nuri_result;
     r->r = std::move(res[0]);
     *out = r;
+  });
+}
+
+int nuri_topk_patterns(nuri_graph *g, uint32_t n_edges, uint32_t k, const nuri_opts *o,
+                       nuri_result **out) {
+  if (!g || !out) {
+    set_error("NULL argument");
+    return NURI_EINVAL;
+  }
+  return guarded([&] {
+    QueryOpts qo = resolve_opts(*g->g, o);
+    std::unique_ptr<nuri_result> r(new nuri_result);
+    run_patterns(*g->g, n_edges, k, qo, r->r);
+    *out = r.release();
   });
 }
 

@@ -180,6 +180,7 @@ uint64_t Graph::device_bytes() const {
          hcol.bytes() + orig.bytes() + vw.bytes() +
          bm_off.bytes() + bm.bytes() + wplus.bytes() + best.bytes() +
          orow.bytes() + lcol.bytes() + lew.bytes() + loff.bytes() + lab_vert.bytes() +
+         vlab.bytes() +
          root_order[0].bytes() + root_order[1].bytes() + ooff.bytes() + oplus.bytes() +
          wloc.bytes() + hop_index_bytes();
 }
@@ -379,6 +380,7 @@ Graph *load_graph(const nuri_csr *csr, hipStream_t stream) {
     upload(g.loff, loff.data(), loff.size(), s);
     upload(g.best, best.data(), best.size(), s);
     upload(g.lab_vert, lab_vert.data(), lab_vert.size(), s);
+    upload(g.vlab, c.vertex_label, (size_t)n, s);
   }
   for (int kind = 0; kind < 2; ++kind)
     upload(g.root_order[kind], g.h_root_order[kind].data(), n, s);

@@ -192,6 +192,7 @@ struct Graph {
   DevBuf<uint32_t> loff;      // [n * 17] label l of row v: lcol[orow[v] + loff[17v+l] .. 17v+l+1)
   DevBuf<int32_t> best;       // [n * 16] max edge weight from v to a label-l vertex (0: none)
   DevBuf<uint32_t> lab_vert;  // vertices grouped by label, ascending ids within a label
+  DevBuf<uint8_t> vlab;       // [n] vertex labels
   std::vector<uint64_t> h_lab_off;  // [17] offsets of the label groups in lab_vert
 
   // host mirrors used to plan queries
@@ -318,6 +319,9 @@ struct MatchSlots {
   void harvest(uint32_t i, Result &r);
   uint64_t min_arena_bytes() const;
 };
+
+// top-k frequent patterns with n_edges edges (Algorithm 2)
+void run_patterns(Graph &g, uint32_t n_edges, uint32_t k, const QueryOpts &o, Result &out);
 
 // matching engine
 void run_matches(Graph &g, const std::vector<const nuri_pattern *> &ps,

@@ -83,6 +83,8 @@ SIGNATURES = {
     "nuri_load_graph": (ctypes.c_int, [ctypes.POINTER(_CSR), _VP, ctypes.POINTER(_VP)]),
     "nuri_free_graph": (None, [_VP]),
     "nuri_graph_get_info": (ctypes.c_int, [_VP, ctypes.POINTER(_GraphInfo)]),
+    "nuri_topk_patterns": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_uint32, _VP,
+                                          ctypes.POINTER(_VP)]),
     "nuri_graph_hop_index": (ctypes.c_int, [_VP, ctypes.c_uint32, _VP,
                                             ctypes.POINTER(ctypes.c_uint64)]),
     "nuri_topk_cliques": (ctypes.c_int, [_VP, ctypes.c_uint32, ctypes.c_int,
@@ -287,6 +289,20 @@ def topk_match(graph: Graph, labels: Sequence[int], edges: Sequence[Tuple[int, i
     o = _opts(**opts)
     _check(lib().nuri_topk_match(graph._h, ctypes.byref(p), k, ctypes.byref(o), ctypes.byref(out)))
     return Result(out)
+
+
+def topk_patterns(graph: Graph, n_edges: int, k: int, **opts):
+    """Top-k frequent patterns with n_edges edges (nuri_topk_patterns).
+
+    Returns ([(support, code)], stats); code = ((i, j, L(i), L(j)), ...),
+    the pattern's minimum DFS code."""
+    out = _VP()
+    o = _opts(**opts)
+    _check(lib().nuri_topk_patterns(graph._h, n_edges, k, ctypes.byref(o), ctypes.byref(out)))
+    r = Result(out)
+    items = [(int(s), tuple(tuple(int(x) for x in ids[4 * t:4 * t + 4])
+                           for t in range(len(ids) // 4))) for s, ids in r.items]
+    return items, r.stats
 
 
 def _queries(queries):
