@@ -20,6 +20,8 @@ Other workloads (--workload), each printing one JSON line of its own:
                         continuous-batching server: p50/p99 latency, queries/s
   protocols             the paper's densification series (Nuri vs Nuri-NP)
                         and k sweeps on synthetic stand-ins
+  hop_index             building the multi-hop (label, hop) max-degree index
+                        of the degree score on a labelled R-MAT graph
   patterns              top-k frequent M-edge patterns (minimum image-based
                         support) on a citation-graph stand-in, with the CPU
                         oracle (Algorithm 2) timed on the same query
@@ -194,7 +196,8 @@ def bench_rmat_match(args, nuri, stream) -> dict:
     t = time.perf_counter()
     singles = []
     for i, p in enumerate(pats[:ns]):
-        singles.append(nuri.topk_match(G, p.labels, p.edges, 50, stream=stream).items)
+        singles.append(nuri.topk_match(G, p.labels, p.edges, 50, score=args.match_score,
+                                       stream=stream).items)
         if i % 16 == 15:
             _log(f"single {i}: {time.perf_counter() - t:.2f} s so far")
     ts = time.perf_counter() - t
@@ -218,6 +221,34 @@ def bench_rmat_match(args, nuri, stream) -> dict:
                          "traffic": None, "expand_ms": ens / 1e6,
                          "algorithmic_bytes": lbytes},
             "children_total": sum(o.stats["children"] for o in outs)}
+
+
+def bench_hop_index(args, nuri, stream) -> dict:
+    """The multi-hop index (Section 4.3, Listing 3) of a labelled R-MAT graph
+    (16 Zipf labels), built from scratch on a freshly loaded graph each
+    step; the paper reports this construction time apart from the queries."""
+    g = _rmat(args.scale, weights=False)
+    hops = args.hops
+    times = []
+    for i in range(args.warmup + args.steps):
+        G = nuri.Graph.from_synth(g, stream=stream)
+        _, ns = G.hop_index(hops, copy=False)
+        G.close()
+        if i >= args.warmup:
+            times.append(ns)
+        _log(f"build {i}: {ns / 1e6:.1f} ms")
+    ns = sum(times) / len(times)
+    b = hop_index_bytes(g.n, len(g.col), hops)
+    return {"metric": "multi-hop index build time", "value": ns / 1e6, "unit": "ms",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ns / 1e6,
+            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+            "data": "synthetic",
+            "config": {"workload": f"rmat{args.scale}_16labels_hop_index_{hops}hops",
+                       "n": g.n, "m": g.m, "hops": hops},
+            "roofline": {"bound": "hbm", "kernel": "k_hop_small + k_hop_chunk + k_hop_merge",
+                         "achieved": b / ns, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": b / ns / HBM_PEAK_GBS, "traffic": None,
+                         "algorithmic_bytes_per_build": b}}
 
 
 def bench_patterns(args, nuri, stream) -> dict:
@@ -417,7 +448,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--workload", default="power_law",
                     choices=["power_law", "rmat_cliques_batched", "rmat_match_batched",
-                             "served_mix", "protocols", "patterns"])
+                             "served_mix", "protocols", "patterns", "hop_index"])
     ap.add_argument("--scale", type=int, default=16)
     ap.add_argument("--queries", type=int, default=64)
     ap.add_argument("--k-max", type=int, default=1000)
@@ -433,6 +464,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--single-sample", type=int, default=0,
                     help="batched workloads: time only the first N queries one at a time")
+    ap.add_argument("--hops", type=int, default=4, help="hop_index: hops to build")
     ap.add_argument("--pm-edges", type=int, default=4, help="patterns: edges per pattern")
     ap.add_argument("--pm-labels", type=int, default=6, help="patterns: vertex labels")
     ap.add_argument("--k-patterns", type=int, default=10, help="patterns: k")
@@ -458,7 +490,7 @@ def main() -> int:
     stream = torch.cuda.current_stream()
     other = {"rmat_cliques_batched": bench_rmat_cliques, "rmat_match_batched": bench_rmat_match,
              "served_mix": bench_served, "protocols": bench_protocols,
-             "patterns": bench_patterns}
+             "patterns": bench_patterns, "hop_index": bench_hop_index}
     if args.workload in other:
         print(json.dumps(other[args.workload](args, nuri, stream)), flush=True)
         return 0
