@@ -129,6 +129,8 @@ def bench_rmat_cliques(args, nuri, stream) -> dict:
         tuned["batch_B"] = args.batch_B
     if args.root_batch:
         tuned["root_batch"] = args.root_batch
+    if args.priority:
+        tuned["priority"] = args.priority
     t = time.perf_counter()
     outs = nuri.topk_batch(G, qs, stream=stream, **tuned)
     tb = time.perf_counter() - t
@@ -148,6 +150,7 @@ def bench_rmat_cliques(args, nuri, stream) -> dict:
             "n_gpus": 1, "higher_is_better": True, "dtype": "int64", "data": "synthetic",
             "config": {"workload": f"rmat{args.scale}_weighted_cliques_{len(ks)}q_k1-{args.k_max}",
                        "n": g.n, "m": g.m, **tuned},
+            "children_per_query": sum(o.stats["children"] for o in outs) / len(outs),
             "one_at_a_time_queries_per_s": ns / ts, "one_at_a_time_sample": ns,
             "batch_equals_single": same,
             "children_total": sum(o.stats["children"] for o in outs)}
@@ -464,6 +467,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--single-sample", type=int, default=0,
                     help="batched workloads: time only the first N queries one at a time")
+    ap.add_argument("--priority", type=int, default=0,
+                    help="rmat_cliques_batched: expansion order (NURI_PRIORITY_*)")
     ap.add_argument("--hops", type=int, default=4, help="hop_index: hops to build")
     ap.add_argument("--pm-edges", type=int, default=4, help="patterns: edges per pattern")
     ap.add_argument("--pm-labels", type=int, default=6, help="patterns: vertex labels")

@@ -341,7 +341,7 @@ typedef struct {
   uint64_t onchip_bytes;       /* cliques: local adjacency rows read by expansion (a
                                   working set that stays in the L2 caches), kept apart
                                   from logical_bytes */
-  uint64_t spilled_bytes;      /* cliques: frontier bytes moved to host memory when the
+  uint64_t spilled_bytes;      /* frontier bytes moved to host memory when the
                                   query's arena filled up (the bottom levels of its
                                   stack, brought back when the levels above are done) */
   uint64_t index_ns;           /* matching, degree score: time this query spent building

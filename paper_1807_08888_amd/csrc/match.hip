@@ -778,6 +778,15 @@ struct MLevel {
   long long max_bound = LLONG_MIN;
 };
 
+// Bottom levels of a query's stack moved to host memory (the paper's
+// virtual priority queue, Section 5): the records of the arena range
+// [0, n) they occupied, returned to the same offsets when the levels above
+// have drained.
+struct MSpill {
+  std::vector<MLevel> levels;
+  std::vector<MRec> recs;
+};
+
 struct MQHost {
   bool active = false;  // the slot holds a query
   bool done = true;     // the query needs no more steps
@@ -795,6 +804,8 @@ struct MQHost {
   uint32_t new_begin = 0;
   int seg = -1;
   int lvl = -1;  // stack index of the level this step takes from
+  std::vector<std::shared_ptr<MSpill>> spill;  // spilled chunks, the last spilled last
+  uint64_t spilled_bytes = 0;
 };
 
 // per-slot top-k buffers and frontier arena, taken at admission
@@ -1102,6 +1113,58 @@ struct MatchEngine {
     }
   }
 
+  // When a query's arena is nearly full its bottom levels -- at least half
+  // of the used records, never the top level -- are copied to host memory
+  // and the levels above moved down.  Returns false when there is nothing
+  // to spill.
+  bool spill_bottom(uint32_t i) {
+    MQHost &Q = qh[i];
+    if (Q.stack.size() < 2) return false;
+    const MLevel &T = Q.stack.back();
+    const u64 used = (u64)T.begin + T.count;
+    size_t m = 1;  // levels [0, m) go to the host
+    while (m + 1 < Q.stack.size() && (u64)Q.stack[m].begin * 2 < used) ++m;
+    const u64 shift = Q.stack[m].begin;
+    if (shift == 0) return false;
+    auto C = std::make_shared<MSpill>();
+    C->levels.assign(Q.stack.begin(), Q.stack.begin() + m);
+    C->recs.resize(shift);
+    MRec *arena = cfg[i].hdr;
+    NURI_HIP(hipMemcpyAsync(C->recs.data(), arena, shift * sizeof(MRec), hipMemcpyDeviceToHost,
+                            s));
+    const u64 rest = used - shift;
+    if (rest) {
+      if (shift >= rest) {
+        NURI_HIP(hipMemcpyAsync(arena, arena + shift, rest * sizeof(MRec),
+                                hipMemcpyDeviceToDevice, s));
+      } else {
+        PoolBuf<MRec> tmp;  // the ranges overlap: through a scratch copy
+        tmp.alloc(g.pool, rest);
+        NURI_HIP(hipMemcpyAsync(tmp.p, arena + shift, rest * sizeof(MRec),
+                                hipMemcpyDeviceToDevice, s));
+        NURI_HIP(hipMemcpyAsync(arena, tmp.p, rest * sizeof(MRec), hipMemcpyDeviceToDevice, s));
+        NURI_HIP(hipStreamSynchronize(s));  // before the scratch returns to the pool
+      }
+    }
+    NURI_HIP(hipStreamSynchronize(s));
+    Q.stack.erase(Q.stack.begin(), Q.stack.begin() + m);
+    for (MLevel &L : Q.stack) L.begin -= (uint32_t)shift;
+    Q.spilled_bytes += shift * sizeof(MRec);
+    Q.spill.push_back(C);
+    return true;
+  }
+
+  // the stack is empty: the last spilled chunk comes back to its offsets
+  void reload(uint32_t i) {
+    MQHost &Q = qh[i];
+    std::shared_ptr<MSpill> C = Q.spill.back();
+    Q.spill.pop_back();
+    NURI_HIP(hipMemcpyAsync(cfg[i].hdr, C->recs.data(), C->recs.size() * sizeof(MRec),
+                            hipMemcpyHostToDevice, s));
+    NURI_HIP(hipStreamSynchronize(s));  // the host copy is freed below
+    Q.stack = C->levels;
+  }
+
   bool plan(uint32_t &nseg, uint32_t &batch_ub, u64 &temp_need, uint32_t &max_count,
             bool &any_sel) {
     nseg = 0;
@@ -1133,9 +1196,20 @@ struct MatchEngine {
         continue;
       }
       while (!Q.stack.empty() && Q.stack.back().count == 0) Q.stack.pop_back();
+      while (Q.stack.empty() && !Q.spill.empty()) {
+        reload(i);
+        while (!Q.stack.empty() && Q.stack.back().count == 0) Q.stack.pop_back();
+      }
       if (Q.stack.empty()) {
         Q.done = true;
         continue;
+      }
+      // with less than an eighth of the arena free, the bottom levels go to
+      // host memory
+      {
+        const MLevel &T0 = Q.stack.back();
+        const u64 f0 = Q.hdr_cap - (u64)(T0.begin + T0.count);
+        if (f0 < std::max<u64>(Q.hdr_cap / 8, std::max<u64>(1, T0.maxcost))) spill_bottom(i);
       }
       // the level to take from: the deepest, or (best-first) the one with the
       // highest bound (ties: the deeper)
@@ -1384,6 +1458,7 @@ struct MatchEngine {
     st.leaves = c.leaves;
     st.offered = c.offered;
     st.frontier_peak_bytes = Q.peak_bytes;
+    st.spilled_bytes = Q.spilled_bytes;
     st.logical_bytes = c.logical_bytes;
     st.expand_launches = Q.launches;
     st.expand_ns = Q.expand_ns;

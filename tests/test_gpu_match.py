@@ -261,3 +261,40 @@ def test_match_result_independent_of_priority(nuri, priority):
                     assert got.stats["children"] >= ref.stats["children"]
     finally:
         G.close()
+
+
+def test_matching_frontier_spill_is_exact(nuri):
+    """128 labelled patterns share the smallest budget (64 MiB), so each gets
+    a 512 KiB arena (8,192 records), and run best-first; the
+    searches whose frontiers outgrow it move their bottom levels to host
+    memory and take them back when the levels above are done.  Every
+    result equals the same batch under the default budget, and the oracle
+    on four of them.  A deadline bounds both runs."""
+    g = synth.rmat(13)
+    synth.add_zipf_labels(g)
+    synth.add_edge_weights(g)
+    pats = [synth.random_pattern(300 + i) for i in range(128)]
+    qs = [{"kind": "match", "k": 50, "labels": p.labels, "edges": p.edges} for p in pats]
+    limit = 150 * 10 ** 9
+    G = nuri.Graph.from_synth(g)
+    try:
+        _case("128 patterns, R-MAT 13, best-first, default budget")
+        full = nuri.topk_batch(G, qs, priority=nuri.PRIORITY_BOUND, deadline_ns=limit)
+        peaks = sorted(r.stats["frontier_peak_bytes"] for r in full)
+        arena = (64 << 20) // len(qs)
+        _case(f"frontier peaks: max {peaks[-1]}, median {peaks[len(peaks) // 2]}, above "
+              f"{arena} bytes: {sum(p > arena for p in peaks)}")
+        assert peaks[-1] > arena, "no query outgrows its arena: the test would not spill"
+        _case("128 patterns, R-MAT 13, best-first, 64 MiB budget: spills")
+        small = nuri.topk_batch(G, qs, frontier_budget_bytes=64 << 20,
+                                priority=nuri.PRIORITY_BOUND, deadline_ns=limit)
+    finally:
+        G.close()
+    for i in range(len(qs)):
+        assert small[i].items == full[i].items, i
+    _case(f"spilled bytes: {sum(r.stats['spilled_bytes'] for r in small)} over "
+          f"{sum(r.stats['spilled_bytes'] > 0 for r in small)} queries")
+    assert sum(r.stats["spilled_bytes"] for r in small) > 0
+    for i in (0, 1, 2, 3):
+        want, _ = oracle.topk_match(g, pats[i].labels, pats[i].edges, 50)
+        assert small[i].items == want, i
