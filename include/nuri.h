@@ -9,7 +9,10 @@
  *     of vertex weights, and
  *   - top-k labelled subgraph matching (Section 2.1 "Subgraph
  *     Isomorphism", Section 4.3), scored by the sum of matched edge
- *     weights or by the sum of the degrees of the matched vertices.
+ *     weights or by the sum of the degrees of the matched vertices, and
+ *   - top-k frequent pattern mining (Section 2.1 "Pattern Mining"), by the
+ *     aggregate computation of Section 3.3 (Algorithm 2) with
+ *     pattern-oriented expansion and minimum image-based support.
  * The user functions of Table 1 are fixed specialisations selected by the
  * arguments below; no user code runs on the device.
  *
