@@ -157,3 +157,26 @@ def test_pattern_edge_cases(nuri):
         assert nuri.topk_patterns(G, 1, 3)[0] == []
     finally:
         G.close()
+
+
+def test_pattern_budget_and_deadline_fail_loudly(nuri):
+    """The embeddings of 4-edge patterns on the 6-label stand-in held at
+    once exceed 64 MiB: under the smallest budget (64 MiB) the query fails with
+    EBUDGET; a deadline that has passed at the first group fails with
+    ETIMEOUT; the graph still answers exactly afterwards."""
+    g = _citeseer_like(6)
+    _case("pattern mining budget and deadline")
+    G = nuri.Graph.from_synth(g)
+    try:
+        _, st = nuri.topk_patterns(G, 4, 10)
+        assert st["frontier_peak_bytes"] > 64 << 20, st["frontier_peak_bytes"]
+        with pytest.raises(nuri.NuriError) as e:
+            nuri.topk_patterns(G, 4, 10, frontier_budget_bytes=64 << 20)
+        assert "EBUDGET" in str(e.value)
+        with pytest.raises(nuri.NuriError) as e:
+            nuri.topk_patterns(G, 3, 10, deadline_ns=1)
+        assert "ETIMEOUT" in str(e.value)
+        want, _ = oracle.topk_patterns(g, 2, 10)
+        assert nuri.topk_patterns(G, 2, 10)[0] == want
+    finally:
+        G.close()
