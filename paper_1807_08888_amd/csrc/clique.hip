@@ -104,7 +104,8 @@ struct QStep {  // per query, this step's counters (zeroed by the step upload)
   unsigned int out_max_w, overflow;
 };
 
-struct QCtr {  // per query, cumulative counters
+// per query, cumulative counters (kCtrSlots copies, one cache line each)
+struct alignas(128) QCtr {
   u64 popped, expanded, children, pruned_pop, pruned_new, leaves, offered, logical_bytes;
   u64 onchip_bytes;  // adjacency rows read (cache-resident), apart from logical_bytes
 };
@@ -244,8 +245,9 @@ __global__ void k_sel_part(const SelSeg *segs, const QCfg *cfg, const QRes *res,
     else ++pruned;
   }
   if (pruned) {
-    atomicAdd(&ctr[sg.qid].popped, (u64)pruned);
-    atomicAdd(&ctr[sg.qid].pruned_pop, (u64)pruned);
+    QCtr &C = ctr[sg.qid * kCtrSlots + (blockIdx.x & (kCtrSlots - 1))];
+    atomicAdd(&C.popped, (u64)pruned);
+    atomicAdd(&C.pruned_pop, (u64)pruned);
   }
 }
 
@@ -376,12 +378,13 @@ __global__ void __launch_bounds__(256)
 // score + (weight of candidates idx, idx+1, ...), so every child past the
 // first idx where that falls below the k-th score is dominated before it
 // is built (the Carraghan-Pardalos cutoff); those are counted as created
-// and pruned without touching memory.  The remaining children are
-// processed 64/G at a time, G = the power of two >= W lanes per child,
-// each lane ANDing one word of the parent's bitmaps with one word of the
-// child vertex's local adjacency row.  Group reductions give |P'| (or
-// w(P')); survivors of a round are compacted with a ballot, placed with
-// one atomic per wave and written with coalesced stores.
+// and pruned without touching memory.  The remaining children are built
+// one per lane, 64 at a time: a lane ANDs the parent's bitmap words with
+// its child vertex's local adjacency row, word by word (all of a row's
+// loads in flight together), and gets |P'| (or w(P')), the first vertex
+// of X' and the witness test without reductions between lanes; the
+// survivors of a round are compacted with a ballot, placed with one atomic
+// per wave and written by their lanes.
 //
 // Whole records: when at most one candidate may be left out and the k-th
 // score still be reached, the subtree's only possible results are V + P
@@ -404,6 +407,42 @@ constexpr int kExpandWaves = 4;
 // an unbounded chain (hundreds of links down a near-clique) leaves most of
 // the device idle at the end of every launch
 constexpr uint32_t kMaxLinks = 32;
+
+// f(w, row[w]) for the W words of a local adjacency row, in order.  Rows
+// of up to 16 words (1,024 local positions) are loaded whole before the
+// first word is used, so that all their loads are in flight together
+// instead of in dependent groups.
+template <class F>
+__device__ inline void row_words(const u64 *row, uint32_t W, F &&f) {
+  if (W <= 16) {
+    u64 v[16];
+#pragma unroll
+    for (uint32_t w = 0; w < 16; ++w) v[w] = w < W ? row[w] : 0ull;
+#pragma unroll
+    for (uint32_t w = 0; w < 16; ++w)
+      if (w < W) f(w, v[w]);
+  } else {
+    for (uint32_t w = 0; w < W; ++w) f(w, row[w]);
+  }
+}
+
+// f(w, r1[w], r2[w]) for two rows of W words, loaded the same way
+template <class F>
+__device__ inline void row_words2(const u64 *r1, const u64 *r2, uint32_t W, F &&f) {
+  if (W <= 16) {
+    u64 v1[16], v2[16];
+#pragma unroll
+    for (uint32_t w = 0; w < 16; ++w) {
+      v1[w] = w < W ? r1[w] : 0ull;
+      v2[w] = w < W ? r2[w] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t w = 0; w < 16; ++w)
+      if (w < W) f(w, v1[w], v2[w]);
+  } else {
+    for (uint32_t w = 0; w < W; ++w) f(w, r1[w], r2[w]);
+  }
+}
 
 __device__ inline void put_crec(CRec *hdr, u64 slot, long long score, long long bound, u64 woff,
                                 uint32_t np, uint32_t root, int j, uint32_t q) {
@@ -474,8 +513,6 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   while (G < W) G <<= 1;
   const uint32_t per = 64 / G;
   const int wi = lane & (G - 1);
-  const int gl = lane & ~(int)(G - 1);  // lane of this group's leader
-  const u64 below = gl ? ((1ull << gl) - 1ull) : 0ull;
   bool carried = false;  // p is a kept child carried over from the previous link
   u64 credit = 0;        // leaf slots reserved for chained links, not yet used (lane 0)
   uint32_t links = 0;    // chained links expanded by this wave
@@ -694,20 +731,28 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       // adjacent to all of P extends V + P, which is then not maximal.
       u64 xacc = (wi < (int)W) ? s_xw[wi] : 0ull;
       uint32_t zc = 0, msum = 0, zlo = 0xFFFFFFFFu, zhi = 0, mbest = 0, mpos = 0;
+      // With slack 1, V + P - {x} needs every non-adjacent pair of P to
+      // contain x (the pairs form a star around x), so two candidates with
+      // two or more misses each rule out every x: the pass stops there,
+      // as it stops with slack 0 at the first miss.
+      uint32_t n2 = 0;     // candidates seen with two or more misses
+      bool dead = false;   // no result is possible
+      u64 rows_read = 0;   // candidates whose rows were read
       if (W >= 2) {
         // one candidate per lane, its W words in sequence (independent
         // loads): 64 candidates per round and no group reductions
         for (uint32_t b0 = 0; b0 < nchild; b0 += 64) {
           const uint32_t ci = b0 + lane;
+          uint32_t miss = 0;
+          rows_read += nchild - b0 < 64 ? nchild - b0 : 64;
           if (ci < nchild) {
             const uint32_t j = s_list[ci];
             const uint32_t jw = j >> 6;
             const u64 jb = 1ull << (j & 63);
             const u64 *rj = rows + (u64)j * W;
-            uint32_t miss = 0;
-#pragma unroll 4
-            for (uint32_t w = 0; w < W; ++w)
-              miss += __popcll(s_pw[w] & ~(w == jw ? jb : 0ull) & ~rj[w]);
+            row_words(rj, W, [&](uint32_t w, u64 rw) {
+              miss += __popcll(s_pw[w] & ~(w == jw ? jb : 0ull) & ~rw);
+            });
             if (miss) {
               ++zc;
               msum += miss;
@@ -720,10 +765,16 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
             }
           }
           if (wslack == 0 && __ballot(zc != 0)) break;  // P is not a clique
+          n2 += __popcll(__ballot(miss >= 2));
+          if (n2 >= 2) {
+            dead = true;
+            break;
+          }
         }
         xacc = 0;  // X is tested below, only if P is a clique
       } else
       for (uint32_t b0 = 0; b0 < nchild; b0 += 8 * per) {
+        rows_read += nchild - b0 < 8 * per ? nchild - b0 : 8 * per;
         for (uint32_t u = 0; u < 8; ++u) {
           const uint32_t ci = b0 + u * per + lane / G;
           const bool valid = ci < nchild;
@@ -736,6 +787,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
             xacc &= row;
           }
           for (uint32_t o2 = 1; o2 < G; o2 <<= 1) miss += __shfl_xor(miss, o2, 64);
+          n2 += __popcll(__ballot(valid && wi == 0 && miss >= 2));
           if (valid && wi == 0 && miss) {
             ++zc;
             msum += miss;
@@ -748,8 +800,12 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
           }
         }
         if (wslack == 0 && __ballot(zc != 0)) break;  // P is not a clique
+        if (n2 >= 2) {
+          dead = true;
+          break;
+        }
       }
-      stat(ST_ONCHIP, 8ull * W * nchild);
+      stat(ST_ONCHIP, 8ull * W * rows_read);
       zc = (uint32_t)wave_sum((u64)zc);
       msum = (uint32_t)wave_sum((u64)msum);
       zlo = wave_min_u32(zlo);
@@ -782,8 +838,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
           if (b0 + lane < nx) {
             const u64 *rx = rows + (u64)s_list[b0 + lane] * W;
             u64 out = 0;
-#pragma unroll 4
-            for (uint32_t w = 0; w < W; ++w) out |= s_pw[w] & ~rx[w];
+            row_words(rx, W, [&](uint32_t w, u64 rxw) { out |= s_pw[w] & ~rxw; });
             all = out == 0;
           }
           ext = __ballot(all) != 0;
@@ -792,7 +847,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         if (!ext) drop0 = -1;
       } else if (zc == 0) {
         if (!__ballot(wi < (int)W && xacc != 0ull)) drop0 = -1;
-      } else if (wslack >= 1 && msum / 2 == mbest) {
+      } else if (!dead && wslack >= 1 && msum / 2 == mbest) {
         if (mbest == 1) {
           drop0 = (int)zlo;
           drop1 = (int)zhi;
@@ -846,15 +901,15 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       if (lane == 0) st[ST_MARK] = st[ST_PRUNED_NEW];
       stat(ST_PRUNED_NEW, nchild - n_eff);
     }
-    // Screening, for records with more children than one round of lane
-    // groups builds: one child per lane, its W words in sequence
-    // (independent loads, 64 children per round, no group reductions),
-    // gives |P'| -- with vertex weights an upper bound of w(P'): the bits
-    // of each word times the heaviest candidate in that word -- and the
-    // first vertex of X' with the test whether it is adjacent to all of P'.
+    // Screening, for records with more than 64/G children (G = the power
+    // of two >= W): one child per lane, as in the build below but without
+    // writing anything, gives |P'| -- with vertex weights an upper bound of
+    // w(P'): the bits of each word times the heaviest candidate in that
+    // word, which spares the exact sum for most children -- and the first
+    // vertex of X' with the test whether it is adjacent to all of P'.
     // Children that this bound or the witness rule out are counted as
-    // pruned here; the others, in order, replace the list and are built by
-    // the lane groups below, which repeat the exact test.
+    // pruned here; the others, in order, replace the list and are built
+    // below, where the exact test is repeated.
     // A run of first candidates each adjacent to all the others is in every
     // maximal clique below the record (any clique of the subtree extends by
     // them), and a chain would add them one link at a time; the screening's
@@ -882,9 +937,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         long long wub = 0;
         int x0 = -1;
         if (valid) {
-#pragma unroll 4
-          for (uint32_t w = 0; w < W; ++w) {
-            const u64 row = rj[w];
+          row_words(rj, W, [&](uint32_t w, u64 row) {
             const u64 pv = s_pw[w];
             const u64 a = pv & row & gt_mask((int)w, (int)j);
             const uint32_t c = __popcll(a);
@@ -892,7 +945,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
             if (weighted) wub += (long long)c * __builtin_amdgcn_readlane(wmx, (int)w);
             const u64 xc = (s_xw[w] | (pv & ~gt_mask((int)w, (int)j - 1))) & row;
             if (x0 < 0 && xc) x0 = (int)w * 64 + __ffsll((long long)xc) - 1;
-          }
+          });
         }
         if (b0 == 0) uni0 = valid && cnt == nchild - 1 - ci;
         const long long score2 = p.score + (weighted ? (long long)wl[j] : 1ll);
@@ -900,9 +953,9 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         if (pass && x0 >= 0) {
           const u64 *rx = rows + (u64)x0 * W;
           u64 out = 0;
-#pragma unroll 4
-          for (uint32_t w = 0; w < W; ++w)
-            out |= s_pw[w] & rj[w] & gt_mask((int)w, (int)j) & ~rx[w];
+          row_words2(rj, rx, W, [&](uint32_t w, u64 rjw, u64 rxw) {
+            out |= s_pw[w] & rjw & gt_mask((int)w, (int)j) & ~rxw;
+          });
           pass = out != 0;  // covered when x0 is adjacent to all of P'
         }
         const u64 pm = __ballot(pass);
@@ -973,8 +1026,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         if (b0 + lane < nx) {
           const u64 *rx = rows + (u64)s_list[b0 + lane] * W;
           u64 out = 0;
-#pragma unroll 4
-          for (uint32_t w = 0; w < W; ++w) out |= s_cx[w] & ~rx[w];
+          row_words(rx, W, [&](uint32_t w, u64 rxw) { out |= s_cx[w] & ~rxw; });
           all = out == 0;
         }
         ext = __ballot(all) != 0;
@@ -1007,74 +1059,73 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     // kept children: the first is held back (in s_cv/s_cx) in case it
     // stays the only one; `spilled` once it has been written out
     bool held = absorb_keep, spilled = false;
-    // the first vertex of X is the witness of most children (X' = X and the
-    // earlier candidates, both adjacent to the child): its row is loaded
-    // once per record, beside the children's rows instead of after them
-    const int xf = n_eff ? wave_lowest_bit((lane < (int)W) ? s_xw[lane] : 0ull) : -1;
-    const u64 rowxf = (xf >= 0 && wi < (int)W) ? rows[(u64)xf * W + wi] : 0ull;
-    for (uint32_t base = 0; base < n_eff; base += per) {
-      const uint32_t ci = base + lane / G;
+    // One child per lane, its W words in sequence: 64 children per round,
+    // independent loads and no reductions between lanes.  A kept child's
+    // words (V + P' and X') are recomputed from its row (a cache hit) as
+    // they are stored rather than held in registers.
+    const u64 lanes_below = (1ull << lane) - 1ull;
+    for (uint32_t base = 0; base < n_eff; base += 64) {
+      const uint32_t ci = base + (uint32_t)lane;
       const bool valid = ci < n_eff;
       const uint32_t j = valid ? s_list[ci] : 0;
-      u64 a = 0, xc = 0;
-      if (valid && wi < (int)W) {
-        const u64 row = rows[(u64)j * W + wi];
-        const u64 pv = s_pw[wi];
-        a = pv & row & gt_mask(wi, (int)j);                        // P'
-        xc = (s_xw[wi] | (pv & ~gt_mask(wi, (int)j - 1))) & row;  // X'
-      }
-      // extension witness: the first vertex of X'; if it is adjacent to all
-      // of P', no clique below this child is maximal
-      int x0 = xc ? wi * 64 + __ffsll((long long)xc) - 1 : 0x7FFFFFFF;
-      for (uint32_t o2 = 1; o2 < G; o2 <<= 1) {
-        int y = __shfl_xor(x0, o2, 64);
-        x0 = y < x0 ? y : x0;
-      }
-      bool covered = false;
-      if (x0 != 0x7FFFFFFF) {
-        const u64 rx = x0 == xf ? rowxf : ((wi < (int)W) ? rows[(u64)x0 * W + wi] : 0ull);
-        int miss = (wi < (int)W) ? ((a & ~rx) != 0ull) : 0;
-        for (uint32_t o2 = 1; o2 < G; o2 <<= 1) miss |= __shfl_xor(miss, o2, 64);
-        covered = miss == 0;
-      }
-      uint32_t cnt = __popcll(a);
+      const uint32_t jw = j >> 6;
+      const u64 jb = 1ull << (j & 63);
+      const u64 *rj = rows + (u64)j * W;
+      uint32_t cnt = 0;
       long long wsum = 0;
-      if (weighted)
-        for (u64 t = a; t; t &= t - 1) wsum += wl[wi * 64 + __ffsll((long long)t) - 1];
-      for (uint32_t o2 = 1; o2 < G; o2 <<= 1) {
-        cnt += __shfl_xor(cnt, o2, 64);
-        if (weighted) wsum += __shfl_xor(wsum, o2, 64);
+      int x0 = -1;  // extension witness: the first vertex of X'
+      if (valid) {
+        row_words(rj, W, [&](uint32_t w, u64 row) {
+          const u64 pv = s_pw[w];
+          const u64 a = pv & row & gt_mask((int)w, (int)j);  // P'
+          cnt += __popcll(a);
+          if (weighted)
+            for (u64 t = a; t; t &= t - 1) wsum += wl[w * 64 + __ffsll((long long)t) - 1];
+          const u64 xc = (s_xw[w] | (pv & ~gt_mask((int)w, (int)j - 1))) & row;  // X'
+          if (x0 < 0 && xc) x0 = (int)w * 64 + __ffsll((long long)xc) - 1;
+        });
+      }
+      // the child is covered when the witness is adjacent to all of P':
+      // then no clique below it is maximal
+      bool covered = false;
+      if (x0 >= 0) {
+        const u64 *rx = rows + (u64)x0 * W;
+        u64 out = 0;
+        row_words2(rj, rx, W, [&](uint32_t w, u64 rjw, u64 rxw) {
+          out |= s_pw[w] & rjw & gt_mask((int)w, (int)j) & ~rxw;
+        });
+        covered = out == 0;
       }
       const long long score2 = p.score + (weighted ? (long long)wl[j] : 1ll);
       const long long bound2 = score2 + (weighted ? wsum : (long long)cnt);
-      const bool leader = valid && wi == 0;
-      const bool prune = bound2 < theta || covered;
+      const bool prune = valid && (bound2 < theta || covered);
       const bool leaf = valid && !prune && cnt == 0;
       const bool keep = valid && !prune && cnt > 0;
       const bool offer = leaf && score2 >= theta;
-      const u64 lm = __ballot(leader);
-      const u64 km = __ballot(leader && keep);
-      const u64 fm = __ballot(leader && offer);
-      stat(ST_PRUNED_NEW, __popcll(__ballot(leader && prune)));
-      stat(ST_LEAVES, __popcll(__ballot(leader && leaf)));
-      stat(ST_ONCHIP, 8ull * W * __popcll(lm));  // adjacency rows read
-      stat(ST_ONCHIP, 8ull * W * __popcll(__ballot(wi == 0 && valid && x0 != 0x7FFFFFFF)));  // witness
-      const u64 jbit = (wi == (int)(j >> 6)) ? (1ull << (j & 63)) : 0ull;
+      const u64 km = __ballot(keep);
+      const u64 fm = __ballot(offer);
+      stat(ST_PRUNED_NEW, __popcll(__ballot(prune)));
+      stat(ST_LEAVES, __popcll(__ballot(leaf)));
+      // adjacency rows read: the children's and the witnesses'
+      stat(ST_ONCHIP, 8ull * W * (__popcll(__ballot(valid)) + __popcll(__ballot(x0 >= 0))));
+      // this lane's child: V + P' to vo[0..W), X' to xo[0..W)
+      auto put_child = [&](u64 *vo, u64 *xo) {
+        row_words(rj, W, [&](uint32_t w, u64 row) {
+          const u64 pv = s_pw[w];
+          vo[w] = s_vw[w] | (pv & row & gt_mask((int)w, (int)j)) | (w == jw ? jb : 0ull);
+          xo[w] = (s_xw[w] | (pv & ~gt_mask((int)w, (int)j - 1))) & row;
+        });
+      };
       if (km) {
         if (!held && __popcll(km) == 1) {
           // the first kept child: hold it back
           held = true;
           if (keep) {
-            if (wi < (int)W) {
-              s_cv[wi] = s_vw[wi] | a | jbit;
-              s_cx[wi] = xc;
-            }
-            if (wi == 0) {
-              s_cscore[wv] = score2;
-              s_cbound[wv] = bound2;
-              s_cj[wv] = (int)j;
-              s_ccnt[wv] = cnt;
-            }
+            put_child(s_cv, s_cx);
+            s_cscore[wv] = score2;
+            s_cbound[wv] = bound2;
+            s_cj[wv] = (int)j;
+            s_ccnt[wv] = cnt;
           }
           wave_sync();
         } else {
@@ -1099,20 +1150,14 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
               spilled = true;
             }
             if (keep) {
-              const uint32_t rk = extra + __popcll(km & below);
+              const uint32_t rk = extra + __popcll(km & lanes_below);
               const u64 slot_w = cf.out_word + w0 + (u64)rk * 2 * W;
-              if (wi < (int)W) {
-                cf.words[slot_w + wi] = s_vw[wi] | a | jbit;
-                cf.words[slot_w + W + wi] = xc;
-              }
-              if (wi == 0) {
-                put_crec(cf.hdr, (u64)cf.out_hdr + h0 + rk, score2, bound2, slot_w, cnt, r, (int)j,
-                         q);
-                const u64 cc = (u64)(d - j - 1);
-                atomicAdd(&s_cost[wv], cc);
-                atomicMax(&s_maxcc[wv], cc);
-                atomicMax(&s_maxb[wv], bound2);
-              }
+              put_child(cf.words + slot_w, cf.words + slot_w + W);
+              put_crec(cf.hdr, (u64)cf.out_hdr + h0 + rk, score2, bound2, slot_w, cnt, r, (int)j, q);
+              const u64 cc = (u64)(d - j - 1);
+              atomicAdd(&s_cost[wv], cc);
+              atomicMax(&s_maxcc[wv], cc);
+              atomicMax(&s_maxb[wv], bound2);
             }
             stat(ST_BYTES, (32 + 16ull * W) * __popcll(km));
           }
@@ -1132,21 +1177,19 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         l0 = __shfl(l0, 0, 64);
         w0 = __shfl(w0, 0, 64);
         if (offer) {
-          const uint32_t rk = __popcll(fm & below);
+          const uint32_t rk = __popcll(fm & lanes_below);
           const u64 slot_l = (u64)l0 + rk;
           const u64 slot_w = w0 + (u64)rk * W;
           if (slot_l < leaf_cap && slot_w + W <= leaf_word_cap) {
-            if (wi < (int)W) leaf_words[slot_w + wi] = s_vw[wi] | jbit;
-            if (wi == 0) {
-              LRec l;
-              l.score = score2;
-              l.woff = slot_w;
-              l.root = r;
-              l.last = (int16_t)j;
-              l.qid = (uint16_t)q;
-              leaves[slot_l] = l;
-            }
-          } else if (wi == 0) {
+            for (uint32_t w = 0; w < W; ++w) leaf_words[slot_w + w] = s_vw[w] | (w == jw ? jb : 0ull);
+            LRec l;
+            l.score = score2;
+            l.woff = slot_w;
+            l.root = r;
+            l.last = (int16_t)j;
+            l.qid = (uint16_t)q;
+            leaves[slot_l] = l;
+          } else {
             atomicAdd(&qs[q].overflow, 1u);
           }
         }
@@ -1207,7 +1250,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   // flush per-wave statistics with one atomic each
   wave_sync();
   if (lane == 0) {
-    QCtr &C = ctr[q];
+    QCtr &C = ctr[q * kCtrSlots + ((blockIdx.x * kExpandWaves + wv) & (kCtrSlots - 1))];
     atomicAdd(&C.popped, st[ST_POPPED]);
     if (st[ST_PRUNED_POP]) atomicAdd(&C.pruned_pop, st[ST_PRUNED_POP]);
     if (st[ST_EXPANDED]) atomicAdd(&C.expanded, st[ST_EXPANDED]);
@@ -1392,7 +1435,7 @@ __global__ void __launch_bounds__(64 * kLeafWaves)
     cd.qid = q;
     cd.len = nc;
     cands[slot] = cd;
-    atomicAdd(&ctr[q].offered, 1ull);
+    atomicAdd(&ctr[q * kCtrSlots + (blockIdx.x & (kCtrSlots - 1))].offered, 1ull);
   }
   slot = __shfl(slot, 0, 64);
   for (uint32_t t = lane; t < nc; t += 64) cand_ids[(u64)slot * lmax + t] = s_sorted[t];
@@ -1642,7 +1685,7 @@ struct Engine {
     }
     arena_bytes = budget / nq;
     h_res.alloc(nq);
-    h_ctr.alloc(nq);
+    h_ctr.alloc((u64)nq * kCtrSlots);
     h_k.alloc(nq);
     for (uint32_t i = 0; i < nq; ++i) {
       QRes &R = h_res.p[i];
@@ -1650,12 +1693,12 @@ struct Engine {
       R.theta = LLONG_MIN;
       h_k.p[i] = 1;
     }
-    d_ctr.alloc(*mp, nq);
+    d_ctr.alloc(*mp, (u64)nq * kCtrSlots);
     d_res.alloc(*mp, nq);
     d_k.alloc(*mp, nq);
     NURI_HIP(hipMemcpyAsync(d_res.p, h_res.p, nq * sizeof(QRes), hipMemcpyHostToDevice, s));
     NURI_HIP(hipMemcpyAsync(d_k.p, h_k.p, nq * sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    NURI_HIP(hipMemsetAsync(d_ctr.p, 0, nq * sizeof(QCtr), s));
+    NURI_HIP(hipMemsetAsync(d_ctr.p, 0, (u64)nq * kCtrSlots * sizeof(QCtr), s));
     if (!fixed) {
       step_words = std::max<u64>(1ull << 20, std::min<u64>(budget / 16 / 8, 64ull << 20));
       step_children = std::max<u64>(1ull << 16, std::min<u64>(step_words, 32ull << 20));
@@ -1756,7 +1799,7 @@ struct Engine {
     h_k.p[i] = k;
     NURI_HIP(hipMemcpyAsync(&d_res.p[i], &h_res.p[i], sizeof(QRes), hipMemcpyHostToDevice, s));
     NURI_HIP(hipMemcpyAsync(&d_k.p[i], &h_k.p[i], sizeof(uint32_t), hipMemcpyHostToDevice, s));
-    NURI_HIP(hipMemsetAsync(&d_ctr.p[i], 0, sizeof(QCtr), s));
+    NURI_HIP(hipMemsetAsync(&d_ctr.p[(u64)i * kCtrSlots], 0, kCtrSlots * sizeof(QCtr), s));
   }
 
   bool slot_free(uint32_t i) const { return !qh[i].active; }
@@ -2261,7 +2304,8 @@ struct Engine {
   void harvest(uint32_t i, Result &res) {
     QHost &Q = qh[i];
     NURI_HIP(hipMemcpyAsync(&h_res.p[i], &d_res.p[i], sizeof(QRes), hipMemcpyDeviceToHost, s));
-    NURI_HIP(hipMemcpyAsync(&h_ctr.p[i], &d_ctr.p[i], sizeof(QCtr), hipMemcpyDeviceToHost, s));
+    NURI_HIP(hipMemcpyAsync(&h_ctr.p[(u64)i * kCtrSlots], &d_ctr.p[(u64)i * kCtrSlots],
+                            kCtrSlots * sizeof(QCtr), hipMemcpyDeviceToHost, s));
     NURI_HIP(hipStreamSynchronize(s));
     const QRes &R = h_res.p[i];
     const uint32_t n = Q.error ? 0 : R.tk_n;
@@ -2284,7 +2328,20 @@ struct Engine {
                      ids.begin() + (u64)t * lmax + ln[t]);
       res.offset.push_back(res.ids.size());
     }
-    const QCtr &c = h_ctr.p[i];
+    QCtr c;
+    memset(&c, 0, sizeof(c));
+    for (uint32_t t = 0; t < kCtrSlots; ++t) {
+      const QCtr &e = h_ctr.p[(u64)i * kCtrSlots + t];
+      c.popped += e.popped;
+      c.expanded += e.expanded;
+      c.children += e.children;
+      c.pruned_pop += e.pruned_pop;
+      c.pruned_new += e.pruned_new;
+      c.leaves += e.leaves;
+      c.offered += e.offered;
+      c.logical_bytes += e.logical_bytes;
+      c.onchip_bytes += e.onchip_bytes;
+    }
     nuri_stats &st = res.stats;
     memset(&st, 0, sizeof(st));
     st.steps = Q.steps;

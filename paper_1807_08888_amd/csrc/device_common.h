@@ -4,6 +4,7 @@
 #pragma once
 
 #include <climits>
+#include <new>
 
 #include "nuri_internal.h"
 
@@ -436,14 +437,14 @@ struct PinBuf {
   void release() {
     if (p) {
       if (pinned) (void)hipHostFree(p);
-      else ::operator delete(p);
+      else ::operator delete(p, std::align_val_t(alignof(T)));
     }
     p = nullptr;
   }
   void alloc(size_t count) {
     release();
     if (pinned) NURI_HIP(hipHostMalloc((void **)&p, count * sizeof(T), 0));
-    else p = static_cast<T *>(::operator new(count * sizeof(T)));
+    else p = static_cast<T *>(::operator new(count * sizeof(T), std::align_val_t(alignof(T))));
     n = count;
   }
 };

@@ -111,7 +111,8 @@ struct CPre {  // per query: score histogram window for the candidate prefilter
   int tbin;  // candidates in bins >= tbin are kept
 };
 
-struct MCtr {
+// per query, cumulative counters (kCtrSlots copies, one cache line each)
+struct alignas(128) MCtr {
   u64 popped, expanded, children, pruned_pop, pruned_new, leaves, offered, logical_bytes;
 };
 
@@ -290,8 +291,9 @@ __global__ void k_msel_part(const MSeg *segs, const MCfg *cfg, const QRes *res, 
     else ++pruned;
   }
   if (pruned) {
-    atomicAdd(&ctr[sg.qid].popped, (u64)pruned);
-    atomicAdd(&ctr[sg.qid].pruned_pop, (u64)pruned);
+    MCtr &C = ctr[sg.qid * kCtrSlots + (blockIdx.x & (kCtrSlots - 1))];
+    atomicAdd(&C.popped, (u64)pruned);
+    atomicAdd(&C.pruned_pop, (u64)pruned);
   }
 }
 
@@ -545,9 +547,9 @@ __global__ void __launch_bounds__(64 * kMatchWaves)
     match_walk(m, P, p, w, 0, min(w.alen, kMatchChunk), theta, q, cf, ms, hdr, cands, cand_ids,
                cand_cap, lane, st);
   }
-  match_flush(st, ctr[q], ms[q], lane);
+  MCtr &C = ctr[q * kCtrSlots + (rec & (kCtrSlots - 1))];
+  match_flush(st, C, ms[q], lane);
   if (lane == 0) {
-    MCtr &C = ctr[q];
     atomicAdd(&C.popped, 1ull);
     if (pruned_pop) atomicAdd(&C.pruned_pop, 1ull);
     if (children) {
@@ -589,7 +591,7 @@ __global__ void __launch_bounds__(64 * kMatchWaves)
     MTally st;
     match_walk(m, P, p, w, t0, min(w.alen, t0 + kMatchChunk), theta, q, cf, ms, hdr, cands,
                cand_ids, cand_cap, lane, st);
-    match_flush(st, ctr[q], ms[q], lane);
+    match_flush(st, ctr[q * kCtrSlots + (c & (kCtrSlots - 1))], ms[q], lane);
   }
 }
 
@@ -931,7 +933,7 @@ struct MatchEngine {
                             hipMemcpyHostToDevice, s));
     NURI_HIP(hipStreamSynchronize(s));  // the host vector is not pinned
     h_res.alloc(nq);
-    h_ctr.alloc(nq);
+    h_ctr.alloc((u64)nq * kCtrSlots);
     h_k.alloc(nq);
     h_rootq.alloc(nq);
     for (uint32_t i = 0; i < nq; ++i) {
@@ -939,13 +941,13 @@ struct MatchEngine {
       h_res.p[i].theta = LLONG_MIN;
       h_k.p[i] = 1;
     }
-    d_ctr.alloc(g.pool, nq);
+    d_ctr.alloc(g.pool, (u64)nq * kCtrSlots);
     d_res.alloc(g.pool, nq);
     d_k.alloc(g.pool, nq);
     d_rootq.alloc(g.pool, nq);
     NURI_HIP(hipMemcpyAsync(d_res.p, h_res.p, nq * sizeof(QRes), hipMemcpyHostToDevice, s));
     NURI_HIP(hipMemcpyAsync(d_k.p, h_k.p, nq * 4, hipMemcpyHostToDevice, s));
-    NURI_HIP(hipMemsetAsync(d_ctr.p, 0, nq * sizeof(MCtr), s));
+    NURI_HIP(hipMemsetAsync(d_ctr.p, 0, (u64)nq * kCtrSlots * sizeof(MCtr), s));
     B = o.batch_B ? o.batch_B : 16384;
     step_children = std::max<u64>(1ull << 16, std::min<u64>(o.frontier_budget / 8 / sizeof(MRec),
                                                             8ull << 20));
@@ -1033,7 +1035,7 @@ struct MatchEngine {
     h_k.p[i] = k;
     NURI_HIP(hipMemcpyAsync(&d_res.p[i], &h_res.p[i], sizeof(QRes), hipMemcpyHostToDevice, s));
     NURI_HIP(hipMemcpyAsync(&d_k.p[i], &h_k.p[i], 4, hipMemcpyHostToDevice, s));
-    NURI_HIP(hipMemsetAsync(&d_ctr.p[i], 0, sizeof(MCtr), s));
+    NURI_HIP(hipMemsetAsync(&d_ctr.p[(u64)i * kCtrSlots], 0, kCtrSlots * sizeof(MCtr), s));
     NURI_HIP(hipStreamSynchronize(s));  // h_plan is reused by the next admission
   }
 
@@ -1425,7 +1427,8 @@ struct MatchEngine {
   void harvest(uint32_t i, Result &res) {
     MQHost &Q = qh[i];
     NURI_HIP(hipMemcpyAsync(&h_res.p[i], &d_res.p[i], sizeof(QRes), hipMemcpyDeviceToHost, s));
-    NURI_HIP(hipMemcpyAsync(&h_ctr.p[i], &d_ctr.p[i], sizeof(MCtr), hipMemcpyDeviceToHost, s));
+    NURI_HIP(hipMemcpyAsync(&h_ctr.p[(u64)i * kCtrSlots], &d_ctr.p[(u64)i * kCtrSlots],
+                            kCtrSlots * sizeof(MCtr), hipMemcpyDeviceToHost, s));
     NURI_HIP(hipStreamSynchronize(s));
     const QRes &R = h_res.p[i];
     const uint32_t n = Q.error ? 0 : R.tk_n, q = plans[i].q;
@@ -1446,7 +1449,19 @@ struct MatchEngine {
       res.ids.insert(res.ids.end(), ids.begin() + (u64)t * QM, ids.begin() + (u64)t * QM + q);
       res.offset.push_back(res.ids.size());
     }
-    const MCtr &c = h_ctr.p[i];
+    MCtr c;
+    memset(&c, 0, sizeof(c));
+    for (uint32_t t = 0; t < kCtrSlots; ++t) {
+      const MCtr &e = h_ctr.p[(u64)i * kCtrSlots + t];
+      c.popped += e.popped;
+      c.expanded += e.expanded;
+      c.children += e.children;
+      c.pruned_pop += e.pruned_pop;
+      c.pruned_new += e.pruned_new;
+      c.leaves += e.leaves;
+      c.offered += e.offered;
+      c.logical_bytes += e.logical_bytes;
+    }
     nuri_stats &st = res.stats;
     memset(&st, 0, sizeof(st));
     st.steps = Q.steps;

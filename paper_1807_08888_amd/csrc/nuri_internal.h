@@ -18,6 +18,11 @@ namespace nuri {
 // of a 64-wide wavefront.
 constexpr uint32_t kMaxLocal = 4096;
 constexpr uint32_t kMaxWords = kMaxLocal / 64;
+// copies of each query's work counters, one cache line apiece: every
+// wavefront of an expansion launch adds its counts when it ends, and
+// thousands of atomics on one line serialise; a kernel adds to the copy
+// its workgroup picks and the host sums the copies
+constexpr uint32_t kCtrSlots = 64;
 constexpr uint32_t kHeavy = 32;
 
 // ------------------------------------------------------------------
