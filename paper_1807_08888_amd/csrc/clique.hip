@@ -104,6 +104,15 @@ struct QStep {  // per query, this step's counters (zeroed by the step upload)
   unsigned int out_max_w, overflow;
 };
 
+// per query, this step's totals over the children written (kCtrSlots
+// copies, one cache line each, added to when wavefronts end); k_qflush
+// folds them into the QStep after the expansion and resets them
+struct alignas(128) QFlush {
+  u64 cost_children, cost_words, max_cc;
+  long long max_bound;
+  unsigned int max_w;
+};
+
 // per query, cumulative counters (kCtrSlots copies, one cache line each)
 struct alignas(128) QCtr {
   u64 popped, expanded, children, pruned_pop, pruned_new, leaves, offered, logical_bytes;
@@ -117,6 +126,7 @@ struct GView {
   const int32_t *wloc, *vw;
   const int64_t *wplus;
   const uint32_t *root_order[2];
+  uint32_t *wit;  // [n] a vertex u was found not adjacent to (~0u: none)
 };
 
 struct SelSeg {  // one query's level to take records from this step
@@ -458,7 +468,8 @@ __device__ inline void put_crec(CRec *hdr, u64 slot, long long score, long long 
 
 __global__ void __launch_bounds__(64 * kExpandWaves)
     k_expand(GView g, const CRec *__restrict__ batch, StepHdr *hdr, const QCfg *__restrict__ cfg,
-             QStep *qs, QCtr *ctr, const QRes *__restrict__ res, LRec *leaves, u64 *leaf_words,
+             QStep *qs, QCtr *ctr, QFlush *flush, const QRes *__restrict__ res, LRec *leaves,
+             u64 *leaf_words,
              uint32_t leaf_cap, u64 leaf_word_cap, uint32_t wst, uint32_t lst, u64 chain_cap,
              uint32_t max_links) {
   extern __shared__ u64 s_dyn[];
@@ -1250,7 +1261,8 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   // flush per-wave statistics with one atomic each
   wave_sync();
   if (lane == 0) {
-    QCtr &C = ctr[q * kCtrSlots + ((blockIdx.x * kExpandWaves + wv) & (kCtrSlots - 1))];
+    const uint32_t slot = (blockIdx.x * kExpandWaves + wv) & (kCtrSlots - 1);
+    QCtr &C = ctr[q * kCtrSlots + slot];
     atomicAdd(&C.popped, st[ST_POPPED]);
     if (st[ST_PRUNED_POP]) atomicAdd(&C.pruned_pop, st[ST_PRUNED_POP]);
     if (st[ST_EXPANDED]) atomicAdd(&C.expanded, st[ST_EXPANDED]);
@@ -1259,15 +1271,39 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
     if (st[ST_LEAVES]) atomicAdd(&C.leaves, st[ST_LEAVES]);
     if (st[ST_BYTES]) atomicAdd(&C.logical_bytes, st[ST_BYTES]);
     if (st[ST_ONCHIP]) atomicAdd(&C.onchip_bytes, st[ST_ONCHIP]);
-    QStep &S = qs[q];
+    QFlush &F = flush[q * kCtrSlots + slot];
     const u64 cost = s_cost[wv];
     if (cost) {
-      atomicAdd(&S.out_cost_children, cost);
-      atomicAdd(&S.out_cost_words, cost * 2 * W);
-      atomicMax(&S.out_max_cc, s_maxcc[wv]);
-      atomicMax(&S.out_max_w, W);
+      atomicAdd(&F.cost_children, cost);
+      atomicAdd(&F.cost_words, cost * 2 * W);
+      atomicMax(&F.max_cc, s_maxcc[wv]);
+      atomicMax(&F.max_w, W);
     }
-    if (s_maxb[wv] != LLONG_MIN) atomicMax(&S.out_max_bound, s_maxb[wv]);
+    if (s_maxb[wv] != LLONG_MIN) atomicMax(&F.max_bound, s_maxb[wv]);
+  }
+}
+
+// the QFlush copies of query blockIdx.x into its QStep, then back to
+// their neutral values.  grid: (queries), one wavefront
+static_assert(kCtrSlots == 64, "one QFlush copy per lane");
+__global__ void __launch_bounds__(64) k_qflush(QFlush *flush, QStep *qs) {
+  const int lane = threadIdx.x;
+  QFlush &e = flush[(u64)blockIdx.x * kCtrSlots + lane];
+  const u64 cc = wave_sum(e.cost_children), cw = wave_sum(e.cost_words);
+  const u64 mc = wave_max_u64(e.max_cc), mw = wave_max_u64(e.max_w);
+  const long long mb = wave_max(e.max_bound);
+  e.cost_children = 0;
+  e.cost_words = 0;
+  e.max_cc = 0;
+  e.max_bound = LLONG_MIN;
+  e.max_w = 0;
+  if (lane == 0) {
+    QStep &S = qs[blockIdx.x];
+    S.out_cost_children = cc;
+    S.out_cost_words = cw;
+    S.out_max_cc = mc;
+    S.out_max_bound = mb;
+    S.out_max_w = (unsigned int)mw;
   }
 }
 
@@ -1281,10 +1317,16 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
 //  (b) no vertex u ranked below r adjacent to all of C: u is scanned in
 //      the lower neighbour list N-(c*) of the member with the shortest one
 //      and tested against every other member by binary search in N+(u).
+// A vertex of C that u is not adjacent to rules u out; the first one a
+// test finds is kept in a per-graph table (wit[u]), and later checks try
+// it first: leaves of one dense region share most members, so most u are
+// ruled out by one lookup instead of a search.  Any entry is a fact about
+// the graph, so concurrent writers cannot make it wrong.
 constexpr int kLeafCap = kMaxLocal + 1;
-// wavefronts per leaf: (a) and the output are done by wave 0, the
-// candidates of (b) are shared out between all of them
+// wavefronts per leaf: (a) is done by wave 0, the candidates of (b) are
+// shared out between all of them, and all of them sort the output
 constexpr int kLeafWaves = 8;
+constexpr uint32_t kNoWit = 0xFFFFFFFFu;
 
 __global__ void __launch_bounds__(64 * kLeafWaves)
     k_leaf_check(GView g, const LRec *leaves, uint32_t first, const u64 *leaf_words,
@@ -1324,22 +1366,43 @@ __global__ void __launch_bounds__(64 * kLeafWaves)
     wave_sync();
     const uint32_t nc = nm + 1;  // clique size
     int ext = 0;
-    // (a) local extension: groups of G lanes AND the members' rows, 64/G
-    // members per round (independent loads), then the groups are combined
+    // (a) local extension: the AND of the members' rows.  Rows of up to 16
+    // words: one member per lane, a whole row's loads in flight together,
+    // then one reduction per word; wider rows: groups of G lanes, one word
+    // per lane, 64/G members per round.
     if (d) {
       const u64 *rows = g.bm + g.bm_off[r];
-      uint32_t G = 1;
-      while (G < W) G <<= 1;
-      const uint32_t per = 64 / G;
-      const int wi = lane & (G - 1);
-      u64 acc = ~0ull;
+      u64 accw = ~0ull;  // lane w < W: word w of the AND
+      if (W <= 16) {
+        u64 acc[16];
+#pragma unroll
+        for (int w = 0; w < 16; ++w) acc[w] = ~0ull;
+        for (uint32_t b0 = 0; b0 < nm; b0 += 64) {
+          if (b0 + lane < nm)
+            row_words(rows + (u64)s_sorted[b0 + lane] * W, W,
+                      [&](uint32_t w, u64 rw) { acc[w] &= rw; });
+        }
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+          if ((uint32_t)w < W) {
+            u64 a = acc[w];
+            for (int o2 = 32; o2 > 0; o2 >>= 1) a &= __shfl_xor(a, o2, 64);
+            if (lane == w) accw = a;
+          }
+        }
+      } else {
+        uint32_t G = 1;
+        while (G < W) G <<= 1;
+        const uint32_t per = 64 / G;
+        const int wi = lane & (G - 1);
 #pragma unroll 8
-      for (uint32_t b0 = 0; b0 < nm; b0 += per) {
-        const uint32_t ci = b0 + lane / G;
-        if (ci < nm && wi < (int)W) acc &= rows[(u64)s_sorted[ci] * W + wi];
+        for (uint32_t b0 = 0; b0 < nm; b0 += per) {
+          const uint32_t ci = b0 + lane / G;
+          if (ci < nm && wi < (int)W) accw &= rows[(u64)s_sorted[ci] * W + wi];
+        }
+        for (uint32_t o2 = G; o2 < 64; o2 <<= 1) accw &= __shfl_xor(accw, o2, 64);
       }
-      for (uint32_t o2 = G; o2 < 64; o2 <<= 1) acc &= __shfl_xor(acc, o2, 64);
-      const u64 x = (lane < (int)W) ? (~v & lt_mask(lane, d) & acc) : 0ull;
+      const u64 x = (lane < (int)W) ? (~v & lt_mask(lane, d) & accw) : 0ull;
       ext = __ballot(x != 0) != 0;
     }
     // (b) set-up: an extender u ranked below r has |N+(u)| >= nc; for
@@ -1381,11 +1444,27 @@ __global__ void __launch_bounds__(64 * kLeafWaves)
     // (b): |N+(u)| >= nc rejects almost every u with one load.  Each
     // remaining u is tested by a whole wave, 64 members at a time; the
     // waves take turns over the list and stop once one finds an extender.
+    const uint32_t nmem = nc - 1;  // s_rank[0 .. nmem): members above r, ascending
     for (uint32_t b0 = wv * 64; b0 < nu; b0 += 64 * kLeafWaves) {
       if (*(volatile int *)&s_ext) break;
       const uint32_t t = b0 + lane;
       const uint32_t u = t < nu ? lo_list[t] : 0u;
-      u64 cand = __ballot(t < nu && g.dplus[u] >= nc);
+      bool live = t < nu && g.dplus[u] >= nc;
+      const uint32_t xw = live ? g.wit[u] : kNoWit;
+      if (xw != kNoWit) {
+        // is the stored non-neighbour of u in C?
+        bool inc = xw == r;
+        if (!inc) {
+          uint32_t a = 0, z = nmem;
+          while (a < z) {
+            const uint32_t mid = (a + z) >> 1;
+            if (s_rank[mid] < xw) a = mid + 1; else z = mid;
+          }
+          inc = a < nmem && s_rank[a] == xw;
+        }
+        live = !inc;
+      }
+      u64 cand = __ballot(live);
       bool found = false;
       while (cand && !found) {
         const int src = __ffsll((long long)cand) - 1;
@@ -1406,7 +1485,9 @@ __global__ void __launch_bounds__(64 * kLeafWaves)
             }
             miss = !(a < du && up[a] == x);
           }
-          all = __ballot(miss) == 0;
+          const u64 mm = __ballot(miss);
+          all = mm == 0;
+          if (!all && lane == __ffsll((long long)mm) - 1) g.wit[uu] = s_rank[m];
         }
         found = all;
       }
@@ -1417,16 +1498,19 @@ __global__ void __launch_bounds__(64 * kLeafWaves)
     }
   }
   __syncthreads();
-  if (s_ext || wv != 0) return;
-  // maximal: emit (score, ascending original ids)
-  for (uint32_t t = lane; t < nc; t += 64) s_id[t] = g.orig[s_rank[t]];
-  wave_sync();
-  for (uint32_t t = lane; t < nc; t += 64) {
-    uint32_t x = s_id[t], rk = 0;
+  if (s_ext) return;
+  // maximal: emit (score, ascending original ids), ranked by counting
+  // (ids are distinct) over all the block's threads
+  for (uint32_t t = threadIdx.x; t < nc; t += 64 * kLeafWaves) s_id[t] = g.orig[s_rank[t]];
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < nc; t += 64 * kLeafWaves) {
+    const uint32_t x = s_id[t];
+    uint32_t rk = 0;
     for (uint32_t u = 0; u < nc; ++u) rk += s_id[u] < x;
     s_sorted[rk] = x;
   }
-  wave_sync();
+  __syncthreads();
+  if (wv != 0) return;
   unsigned int slot = 0;
   if (lane == 0) {
     slot = atomicAdd(cand_count, 1u);
@@ -1545,6 +1629,7 @@ struct Engine {
 
   u64 arena_bytes = 0;  // frontier arena of a slot unless admit() is given one
   PoolBuf<QCtr> d_ctr;
+  PoolBuf<QFlush> d_flush;
   PoolBuf<QRes> d_res;
   PoolBuf<uint32_t> d_k;
   PoolBuf<CRec> batch, temp;
@@ -1616,6 +1701,7 @@ struct Engine {
     v.wplus = g.wplus.p;
     v.root_order[0] = g.root_order[0].p;
     v.root_order[1] = g.root_order[1].p;
+    v.wit = g.leaf_wit.p;
     return v;
   }
 
@@ -1726,6 +1812,13 @@ struct Engine {
     NURI_HIP(hipMemsetAsync(d_hchild.p, 0, d_hchild.bytes(), s));
     d_step.alloc(*mp, L->total);
     h_step.alloc(L->total);
+    // k_qflush leaves the copies neutral; a first pass over the zeroed
+    // buffer sets them so (what it writes to the QSteps is overwritten by
+    // every step's upload)
+    d_flush.alloc(*mp, (u64)nq * kCtrSlots);
+    NURI_HIP(hipMemsetAsync(d_flush.p, 0, (u64)nq * kCtrSlots * sizeof(QFlush), s));
+    hipLaunchKernelGGL(k_qflush, dim3(nq), dim3(64), 0, s, d_flush.p, dev<QStep>(L->qs));
+    NURI_HIP(hipGetLastError());
     if (o.profile) {
       NURI_HIP(hipEventCreate(&ev0));
       NURI_HIP(hipEventCreate(&ev1));
@@ -1759,6 +1852,12 @@ struct Engine {
       NURI_HIP(hipStreamSynchronize(s));
       take_theta();
     }
+    // the maximality checks' table of non-neighbours starts empty whenever
+    // the engine takes work with no query in flight, so that a query run
+    // on its own does not gain from the ones before it
+    bool busy = false;
+    for (const auto &O : qh) busy |= O.active;
+    if (!busy) NURI_HIP(hipMemsetAsync(g.leaf_wit.p, 0xFF, g.leaf_wit.bytes(), s));
     QHost &Q = qh[i];
     Q = QHost{};
     Q.active = true;
@@ -2147,13 +2246,16 @@ struct Engine {
       if (o.profile) NURI_HIP(hipEventRecord(ev0, s));
       const uint32_t blocks = (batch_ub + kExpandWaves - 1) / kExpandWaves;
       hipLaunchKernelGGL(k_expand, dim3(blocks), dim3(64 * kExpandWaves), expand_lds, s, gv,
-                         batch.p, dh, dcfg, dqs, d_ctr.p, d_res.p, leaves.p, leaf_words.p,
+                         batch.p, dh, dcfg, dqs, d_ctr.p, d_flush.p, d_res.p, leaves.p,
+                         leaf_words.p,
                          leaf_cap, leaf_word_cap, ex_wst, ex_lst,
                          std::min<u64>((u64)leaf_cap - plan_c - batch_ub,
                                        (leaf_word_cap - plan_w) / ex_wst),
                          o.chain_links ? o.chain_links : kMaxLinks);
       NURI_HIP(hipGetLastError());
       if (o.profile) NURI_HIP(hipEventRecord(ev1, s));
+      hipLaunchKernelGGL(k_qflush, dim3(nq), dim3(64), 0, s, d_flush.p, dqs);
+      NURI_HIP(hipGetLastError());
     }
     NURI_HIP(hipMemcpyAsync(h_step.p, d_step.p, L->readback(), hipMemcpyDeviceToHost, s));
     NURI_HIP(hipStreamSynchronize(s));

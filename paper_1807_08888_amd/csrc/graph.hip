@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(256) k_build_bitmaps(
 
 uint64_t Graph::device_bytes() const {
   return rrow.bytes() + rcol.bytes() + split.bytes() + dplus.bytes() + hrow.bytes() +
-         hcol.bytes() + orig.bytes() + vw.bytes() +
+         hcol.bytes() + leaf_wit.bytes() + orig.bytes() + vw.bytes() +
          bm_off.bytes() + bm.bytes() + wplus.bytes() + best.bytes() +
          orow.bytes() + lcol.bytes() + lew.bytes() + loff.bytes() + lab_vert.bytes() +
          vlab.bytes() +
@@ -366,6 +366,8 @@ Graph *load_graph(const nuri_csr *csr, hipStream_t stream) {
   upload(g.hrow, hrow.data(), n + 1, s);
   if (hcol.empty()) hcol.push_back(0);  // keep the device pointer valid
   upload(g.hcol, hcol.data(), hcol.size(), s);
+  g.leaf_wit.alloc(n);
+  NURI_HIP(hipMemsetAsync(g.leaf_wit.p, 0xFF, (size_t)n * sizeof(uint32_t), s));
   upload(g.orig, g.h_orig.data(), n, s);
   upload(g.vw, vwr.data(), n, s);
   upload(g.bm_off, bm_off.data(), n + 1, s);

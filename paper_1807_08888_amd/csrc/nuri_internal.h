@@ -183,6 +183,9 @@ struct Graph {
   // ranked above it has |N+(u)| >= c)
   DevBuf<uint64_t> hrow;
   DevBuf<uint32_t> hcol;
+  // [n] maximality checks of cliques: a vertex that u was found not to be
+  // adjacent to (~0u: none yet); filled as queries run
+  DevBuf<uint32_t> leaf_wit;
   DevBuf<uint32_t> orig;      // rank -> original id
   DevBuf<int32_t> vw;         // vertex weight by rank
   DevBuf<uint64_t> bm_off;    // [n+1] word offset of r's local bitmap
