@@ -96,9 +96,12 @@ __device__ inline long long sel_key(const QCfg &c, const CRec &r) {
   return c.prio == NURI_PRIORITY_PAPER ? (long long)rec_np(r) : r.bound;
 }
 
-struct QStep {  // per query, this step's counters (zeroed by the step upload)
-  unsigned int n_out, pad;
-  u64 out_words, out_cost_children, out_cost_words;
+// per query, this step's counters (zeroed by the step upload); the two
+// that wavefronts reserve child slots with have a cache line each
+struct QStep {
+  alignas(128) unsigned int n_out, pad;
+  alignas(128) u64 out_words;
+  alignas(128) u64 out_cost_children, out_cost_words;
   long long out_max_bound;
   u64 out_max_cc;  // largest children bound of one appended record
   unsigned int out_max_w, overflow;

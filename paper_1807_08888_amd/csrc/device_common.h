@@ -19,12 +19,17 @@ struct Cand {  // a result offered to the result set (its ids are stored apart)
   uint32_t len;
 };
 
-struct StepHdr {  // global counters of one step (zeroed by the step upload)
-  unsigned int batch_count, leaf_count, cand_count, big_next;
-  u64 leaf_word_count;
-  u64 chain_c;     // leaf slots reserved by chained expansion (each with the widest row)
-  u64 big_packed;  // matching: records with long candidate lists (high 32 bits) and
-                   // their extra chunks (low 32 bits)
+// Global counters of one step (zeroed by the step upload).  The ones that
+// every wavefront of an expansion launch reserves space with get a cache
+// line each: atomics on one line are serialised.
+struct StepHdr {
+  alignas(128) unsigned int batch_count;
+  unsigned int cand_count, big_next;
+  alignas(128) unsigned int leaf_count;
+  alignas(128) u64 leaf_word_count;
+  alignas(128) u64 chain_c;     // leaf slots reserved by chained expansion (each with the widest row)
+  alignas(128) u64 big_packed;  // matching: records with long candidate lists (high 32 bits)
+                                // and their extra chunks (low 32 bits)
 };
 
 struct QRes {  // per query result state
@@ -427,6 +432,8 @@ inline void launch_merge(const Cand *cands, const StepHdr *hdr, const uint32_t *
 // allocation-free entry point) ordinary pageable host memory
 template <class T>
 struct PinBuf {
+  // byte buffers hold structures with cache-line aligned members
+  static constexpr size_t kAlign = alignof(T) > 128 ? alignof(T) : 128;
   T *p = nullptr;
   size_t n = 0;
   bool pinned = true;
@@ -437,14 +444,14 @@ struct PinBuf {
   void release() {
     if (p) {
       if (pinned) (void)hipHostFree(p);
-      else ::operator delete(p, std::align_val_t(alignof(T)));
+      else ::operator delete(p, std::align_val_t(kAlign));
     }
     p = nullptr;
   }
   void alloc(size_t count) {
     release();
     if (pinned) NURI_HIP(hipHostMalloc((void **)&p, count * sizeof(T), 0));
-    else p = static_cast<T *>(::operator new(count * sizeof(T), std::align_val_t(alignof(T))));
+    else p = static_cast<T *>(::operator new(count * sizeof(T), std::align_val_t(kAlign)));
     n = count;
   }
 };
