@@ -393,11 +393,10 @@ __global__ void __launch_bounds__(256)
 // is built (the Carraghan-Pardalos cutoff); those are counted as created
 // and pruned without touching memory.  The remaining children are built
 // one per lane, 64 at a time: a lane ANDs the parent's bitmap words with
-// its child vertex's local adjacency row, word by word (all of a row's
-// loads in flight together), and gets |P'| (or w(P')), the first vertex
-// of X' and the witness test without reductions between lanes; the
-// survivors of a round are compacted with a ballot, placed with one atomic
-// per wave and written by their lanes.
+// its child vertex's local adjacency row, word by word, and gets |P'|
+// (or w(P')), the first vertex of X' and the witness test without
+// reductions between lanes; the survivors of a round are compacted with a
+// ballot, placed with one atomic per wave and written by their lanes.
 //
 // Whole records: when at most one candidate may be left out and the k-th
 // score still be reached, the subtree's only possible results are V + P
@@ -414,7 +413,9 @@ __global__ void __launch_bounds__(256)
 // LDS per wave (dynamic, sized by the largest local row of the graph):
 // five bitmaps of wst words (parent P, parent V, parent X, carried child
 // V+P, carried child X) and a candidate list of lst u16 positions.
-constexpr int kExpandWaves = 4;
+// one wavefront per workgroup: a record's wavefront frees its slot as soon
+// as it ends, instead of waiting for the slowest of its group
+constexpr int kExpandWaves = 1;
 // links one wavefront chains (by default) before it writes the held child
 // to the frontier instead: a launch lasts as long as its longest chain, and
 // an unbounded chain (hundreds of links down a near-clique) leaves most of
@@ -439,22 +440,19 @@ __device__ inline void row_words(const u64 *row, uint32_t W, F &&f) {
   }
 }
 
-// f(w, r1[w], r2[w]) for two rows of W words, loaded the same way
+// f(w, row[w]) and f(w, r1[w], r2[w]) in a plain loop: the expansion
+// kernel's occupancy is bound by its registers, and there these keep
+// fewer of them live than row_words
 template <class F>
-__device__ inline void row_words2(const u64 *r1, const u64 *r2, uint32_t W, F &&f) {
-  if (W <= 16) {
-    u64 v1[16], v2[16];
-#pragma unroll
-    for (uint32_t w = 0; w < 16; ++w) {
-      v1[w] = w < W ? r1[w] : 0ull;
-      v2[w] = w < W ? r2[w] : 0ull;
-    }
-#pragma unroll
-    for (uint32_t w = 0; w < 16; ++w)
-      if (w < W) f(w, v1[w], v2[w]);
-  } else {
-    for (uint32_t w = 0; w < W; ++w) f(w, r1[w], r2[w]);
-  }
+__device__ inline void row_loop(const u64 *row, uint32_t W, F &&f) {
+#pragma unroll 4
+  for (uint32_t w = 0; w < W; ++w) f(w, row[w]);
+}
+
+template <class F>
+__device__ inline void row_loop2(const u64 *r1, const u64 *r2, uint32_t W, F &&f) {
+#pragma unroll 4
+  for (uint32_t w = 0; w < W; ++w) f(w, r1[w], r2[w]);
 }
 
 __device__ inline void put_crec(CRec *hdr, u64 slot, long long score, long long bound, u64 woff,
@@ -469,7 +467,8 @@ __device__ inline void put_crec(CRec *hdr, u64 slot, long long score, long long 
   hdr[slot] = ch;
 }
 
-__global__ void __launch_bounds__(64 * kExpandWaves)
+// three wavefronts per SIMD (at most 168 registers; a few spill)
+__global__ void __launch_bounds__(64 * kExpandWaves) __attribute__((amdgpu_waves_per_eu(3)))
     k_expand(GView g, const CRec *__restrict__ batch, StepHdr *hdr, const QCfg *__restrict__ cfg,
              QStep *qs, QCtr *ctr, QFlush *flush, const QRes *__restrict__ res, LRec *leaves,
              u64 *leaf_words,
@@ -764,7 +763,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
             const uint32_t jw = j >> 6;
             const u64 jb = 1ull << (j & 63);
             const u64 *rj = rows + (u64)j * W;
-            row_words(rj, W, [&](uint32_t w, u64 rw) {
+            row_loop(rj, W, [&](uint32_t w, u64 rw) {
               miss += __popcll(s_pw[w] & ~(w == jw ? jb : 0ull) & ~rw);
             });
             if (miss) {
@@ -852,7 +851,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
           if (b0 + lane < nx) {
             const u64 *rx = rows + (u64)s_list[b0 + lane] * W;
             u64 out = 0;
-            row_words(rx, W, [&](uint32_t w, u64 rxw) { out |= s_pw[w] & ~rxw; });
+            row_loop(rx, W, [&](uint32_t w, u64 rxw) { out |= s_pw[w] & ~rxw; });
             all = out == 0;
           }
           ext = __ballot(all) != 0;
@@ -951,7 +950,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         long long wub = 0;
         int x0 = -1;
         if (valid) {
-          row_words(rj, W, [&](uint32_t w, u64 row) {
+          row_loop(rj, W, [&](uint32_t w, u64 row) {
             const u64 pv = s_pw[w];
             const u64 a = pv & row & gt_mask((int)w, (int)j);
             const uint32_t c = __popcll(a);
@@ -967,7 +966,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         if (pass && x0 >= 0) {
           const u64 *rx = rows + (u64)x0 * W;
           u64 out = 0;
-          row_words2(rj, rx, W, [&](uint32_t w, u64 rjw, u64 rxw) {
+          row_loop2(rj, rx, W, [&](uint32_t w, u64 rjw, u64 rxw) {
             out |= s_pw[w] & rjw & gt_mask((int)w, (int)j) & ~rxw;
           });
           pass = out != 0;  // covered when x0 is adjacent to all of P'
@@ -1040,7 +1039,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
         if (b0 + lane < nx) {
           const u64 *rx = rows + (u64)s_list[b0 + lane] * W;
           u64 out = 0;
-          row_words(rx, W, [&](uint32_t w, u64 rxw) { out |= s_cx[w] & ~rxw; });
+          row_loop(rx, W, [&](uint32_t w, u64 rxw) { out |= s_cx[w] & ~rxw; });
           all = out == 0;
         }
         ext = __ballot(all) != 0;
@@ -1089,7 +1088,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       long long wsum = 0;
       int x0 = -1;  // extension witness: the first vertex of X'
       if (valid) {
-        row_words(rj, W, [&](uint32_t w, u64 row) {
+        row_loop(rj, W, [&](uint32_t w, u64 row) {
           const u64 pv = s_pw[w];
           const u64 a = pv & row & gt_mask((int)w, (int)j);  // P'
           cnt += __popcll(a);
@@ -1105,7 +1104,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       if (x0 >= 0) {
         const u64 *rx = rows + (u64)x0 * W;
         u64 out = 0;
-        row_words2(rj, rx, W, [&](uint32_t w, u64 rjw, u64 rxw) {
+        row_loop2(rj, rx, W, [&](uint32_t w, u64 rjw, u64 rxw) {
           out |= s_pw[w] & rjw & gt_mask((int)w, (int)j) & ~rxw;
         });
         covered = out == 0;
@@ -1124,7 +1123,7 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
       stat(ST_ONCHIP, 8ull * W * (__popcll(__ballot(valid)) + __popcll(__ballot(x0 >= 0))));
       // this lane's child: V + P' to vo[0..W), X' to xo[0..W)
       auto put_child = [&](u64 *vo, u64 *xo) {
-        row_words(rj, W, [&](uint32_t w, u64 row) {
+        row_loop(rj, W, [&](uint32_t w, u64 row) {
           const u64 pv = s_pw[w];
           vo[w] = s_vw[w] | (pv & row & gt_mask((int)w, (int)j)) | (w == jw ? jb : 0ull);
           xo[w] = (s_xw[w] | (pv & ~gt_mask((int)w, (int)j - 1))) & row;
