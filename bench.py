@@ -223,7 +223,9 @@ def bench_rmat_match(args, nuri, stream) -> dict:
                          "unit": "GB/s", "frac": lbytes / ens / HBM_PEAK_GBS if ens else 0.0,
                          "traffic": None, "expand_ms": ens / 1e6,
                          "algorithmic_bytes": lbytes},
-            "children_total": sum(o.stats["children"] for o in outs)}
+            "children_total": sum(o.stats["children"] for o in outs),
+            "spilled_bytes_total": sum(o.stats["spilled_bytes"] for o in outs),
+            "steps_max": max(o.stats["steps"] for o in outs)}
 
 
 def bench_hop_index(args, nuri, stream) -> dict:

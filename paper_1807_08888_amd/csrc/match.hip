@@ -1206,12 +1206,16 @@ struct MatchEngine {
         Q.done = true;
         continue;
       }
-      // with less than an eighth of the arena free, the bottom levels go to
-      // host memory
+      // when the children of one record of some level no longer fit, the
+      // bottom levels go to host memory (spilling earlier, while smaller
+      // steps still fit, copied gigabytes through the host for nothing)
       {
+        u64 need = 1;
+        for (const MLevel &Lx : Q.stack)
+          if (Lx.count) need = std::max<u64>(need, Lx.maxcost);
         const MLevel &T0 = Q.stack.back();
         const u64 f0 = Q.hdr_cap - (u64)(T0.begin + T0.count);
-        if (f0 < std::max<u64>(Q.hdr_cap / 8, std::max<u64>(1, T0.maxcost))) spill_bottom(i);
+        if (f0 < need) spill_bottom(i);
       }
       // the level to take from: the deepest, or (best-first) the one with the
       // highest bound (ties: the deeper)
