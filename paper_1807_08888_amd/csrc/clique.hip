@@ -467,8 +467,7 @@ __device__ inline void put_crec(CRec *hdr, u64 slot, long long score, long long 
   hdr[slot] = ch;
 }
 
-// three wavefronts per SIMD (at most 168 registers; a few spill)
-__global__ void __launch_bounds__(64 * kExpandWaves) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(64 * kExpandWaves)
     k_expand(GView g, const CRec *__restrict__ batch, StepHdr *hdr, const QCfg *__restrict__ cfg,
              QStep *qs, QCtr *ctr, QFlush *flush, const QRes *__restrict__ res, LRec *leaves,
              u64 *leaf_words,
