@@ -412,7 +412,8 @@ __global__ void __launch_bounds__(256)
 //
 // LDS per wave (dynamic, sized by the largest local row of the graph):
 // five bitmaps of wst words (parent P, parent V, parent X, carried child
-// V+P, carried child X) and a candidate list of lst u16 positions.
+// V+P, carried child X), a candidate list of lst u16 positions and, for
+// vertex-weight scores, the root's lst local weights.
 // one wavefront per workgroup: a record's wavefront frees its slot as soon
 // as it ends, instead of waiting for the slowest of its group
 constexpr int kExpandWaves = 1;
@@ -487,6 +488,9 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   u64 *s_cv = s_xw + wst;  // carried child: V + P bitmap
   u64 *s_cx = s_cv + wst;  // carried child: X bitmap
   uint16_t *s_list = (uint16_t *)(s_dyn + (u64)kExpandWaves * 5 * wst) + (u64)wv * lst;
+  // the root's local vertex weights (vertex-weight scores only)
+  int32_t *s_wl = (int32_t *)((uint16_t *)(s_dyn + (u64)kExpandWaves * 5 * wst) +
+                              (u64)kExpandWaves * lst) + (u64)wv * lst;
   const uint32_t rec = blockIdx.x * kExpandWaves + wv;
   if (rec >= hdr->batch_count) return;
   CRec p = batch[rec];
@@ -519,7 +523,18 @@ __global__ void __launch_bounds__(64 * kExpandWaves)
   const uint32_t r = p.root;
   const uint32_t d = g.dplus[r];
   const uint32_t W = words_of(d);
-  const int32_t *wl = g.wloc + g.ooff[r];
+  // every record and chained link of this wavefront has root r: with vertex
+  // weights, the root's local weights are read into LDS once, so that the
+  // per-child sums over P' (one lane per child, a bit at a time) read LDS.
+  // Not for a record pruned when popped (or without later neighbours): the
+  // wavefront ends with it.
+  if (weighted && p.bound >= theta && d) {
+    const int32_t *gwl = g.wloc + g.ooff[r];
+#pragma unroll 8
+    for (uint32_t t = lane; t < d; t += 64) s_wl[t] = gwl[t];
+    wave_sync();
+  }
+  const int32_t *wl = s_wl;
   const u64 *rows = g.bm + g.bm_off[r];
   uint32_t G = 1;
   while (G < W) G <<= 1;
@@ -1738,8 +1753,8 @@ struct Engine {
     const bool fixed = mp->fixed_base != nullptr;
     B = o.batch_B ? o.batch_B : 16384;
     root_B = o.root_batch ? o.root_batch : 8192;
-    // LDS of k_expand: five bitmaps of the widest local row and a candidate
-    // list as long as the largest out-degree, per wave
+    // LDS of k_expand: five bitmaps of the widest local row, a candidate
+    // list and the local weights as long as the largest out-degree, per wave
     ex_wst = std::max<uint32_t>(1, (g.degeneracy + 63) / 64);
     ex_lst = (g.degeneracy + 8) & ~7u;
     u64 budget = o.frontier_budget;
@@ -1799,7 +1814,8 @@ struct Engine {
     }
     batch.alloc(*mp, batch_cap);
     if (fixed) temp.alloc(*mp, arena_caps(arena_bytes).first);  // every level fits
-    expand_lds = (size_t)kExpandWaves * (5ull * 8 * ex_wst + 2ull * ex_lst);
+    // per wavefront: five bitmaps, the candidate list and the root's weights
+    expand_lds = (size_t)kExpandWaves * (5ull * 8 * ex_wst + 2ull * ex_lst + 4ull * ex_lst);
     leaves.alloc(*mp, leaf_cap);
     leaf_words.alloc(*mp, leaf_word_cap);
     cands.alloc(*mp, kCandChunk);
