@@ -524,8 +524,10 @@ def main() -> int:
         tuned = {"batch_B": args.batch_B, "root_batch": args.root_batch}
         _log(f"step sizes given: {tuned}")
     else:
+        # the fastest of two runs per candidate: one run's noise is as large
+        # as the differences between neighbouring step sizes
         tuned = nuri.autotune(G, [{"kind": "clique", "k": args.k, "weight_fn": nuri.SCORE_SIZE}],
-                              rounds=1, stream=stream)
+                              rounds=2, stream=stream)
         _log(f"autotuned step sizes: {tuned}")
 
     if args.chain_links:

@@ -295,7 +295,7 @@ int nuri_topk_batch(nuri_graph *g, const nuri_query *qs, uint32_t nq, const nuri
  * of every step change how the frontier is cut into launches, never the
  * result).  Runs the queries qs[nq] as one batch once to warm up, then
  * `rounds` times (rounds >= 1) for each candidate pair (batch_B in {4096,
- * 16384, 65536}) x (root_batch in {2048, 8192}), with the other options
+ * 16384, 32768, 65536}) x (root_batch in {2048, 8192}), with the other options
  * of *o (NULL = defaults), and writes into *best those options with the
  * pair of the smallest wall time.  Results are computed and discarded.
  * Errors: as nuri_topk_batch; *best is untouched on error.

@@ -242,7 +242,7 @@ int nuri_autotune(nuri_graph *g, const nuri_query *qs, uint32_t nq, const nuri_o
   uint64_t ns = 0;
   int rc = run(base, ns);  // warm-up (workspace pool, caches)
   if (rc != NURI_OK) return rc;
-  static const uint32_t kB[] = {4096, 16384, 65536};
+  static const uint32_t kB[] = {4096, 16384, 32768, 65536};
   static const uint32_t kRoot[] = {2048, 8192};
   uint64_t best_ns = UINT64_MAX;
   nuri_opts pick = base;
